@@ -1,0 +1,250 @@
+/*
+ * colloc.h -- C ABI of the MI355X collocation interior-point Newton step.
+ *
+ * The library evaluates and differentiates the simultaneous-method NLP of an ODE
+ * parameter-estimation problem (problem statement eq. 1a-1d; discretized NLP eq. 2a-2e with
+ * the collocation equation in the form of eq. 3), assembles the condensed primal-dual KKT
+ * matrix W + Sx + dw I + J^T Ds J, factors it without pivoting, solves it, and runs the
+ * filter line-search interior-point iteration around it (the solver stack in the benchmark
+ * setup: a filter line-search interior-point method on a pivoting-free KKT form, relative
+ * KKT tolerance 1e-6, acceptable level 1e-4 over 15 iterations).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - A problem handle is a batch of n_inst >= 1 instances with the same shape class
+ *    (n_s species, n_r reactions, n_p parameters, K collocation points); the number of finite
+ *    elements N and the reaction network may differ per instance.
+ *  - Right-Radau collocation points (last point at tau = 1), so continuity (eq. 2c) links
+ *    node K of element i-1 to node 0 of element i.
+ *  - Vector layouts (per instance, instances stored back to back in handle order):
+ *      x (primal, length N*b + n_p, b = (K+1) n_s):  z[i][j][s] at i*b + j*n_s + s, then theta.
+ *      g, y, s, v (constraints, length N*b):  row (i, j, s) at i*b + j*n_s + s, where j = 0 is
+ *        the initial-condition row (i = 0, eq. 2d) or the continuity row (i >= 1, eq. 2c), and
+ *        j = k >= 1 is the collocation row at point k (eq. 2b / eq. 3), written as
+ *        sum_j a_jk z_ij - h_i f(z_ik, theta), the sign used by the paper's constraint listing.
+ *    colloc_layout() returns the per-instance offsets.
+ *  - Objective: Phi = 1/2 sum_m ((sum_j l_j(tau_m) z[e_m][j][s_m] - y_m) / sigma_m)^2.
+ *  - Mass-action kinetics: f_s = sum_r nu_sr rho_r, rho_r = kappa_r prod_(filled slots) u,
+ *    kappa_r = exp(theta[param_r]) or exp(logk_fixed_r) when param_r = -1.
+ *  - Pointers named *_dev are device memory (hipMalloc or torch CUDA tensors) owned by the
+ *    caller; the library never allocates device memory after colloc_create.  Host pointers
+ *    are only read during the call.
+ *  - All device work is enqueued asynchronously on the given stream; no call synchronizes
+ *    except colloc_create/colloc_upload.  A handle must not be used from two threads at once.
+ *  - Argument and shape errors are detected on the host before anything is enqueued and
+ *    return a negative COLLOC_E* code; numerical outcomes are reported per instance in
+ *    device status words.  A failed kernel launch returns COLLOC_EHIP.
+ */
+#ifndef COLLOC_H
+#define COLLOC_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Host return codes. */
+enum {
+  COLLOC_OK = 0,
+  COLLOC_EINVAL = -1,      /* bad argument, shape or pointer */
+  COLLOC_ENOMEM = -2,      /* host allocation failed */
+  COLLOC_EHIP = -3,        /* a HIP call or kernel launch failed */
+  COLLOC_EUNSUPPORTED = -4 /* shape class outside what the kernels support (see colloc_create) */
+};
+
+/* Per-instance device status of the interior-point iteration (the paper's solve statuses,
+ * Table 1 keys: solve succeeded, solved to acceptable level, timeout/iteration cap,
+ * restoration failed, error). */
+enum {
+  COLLOC_RUNNING = 0,
+  COLLOC_SOLVED = 1,
+  COLLOC_ACCEPTABLE = 2,
+  COLLOC_MAXITER = 3,
+  COLLOC_TIMEOUT = 4,
+  COLLOC_ENOTPD = 5,              /* inertia correction exceeded delta_max */
+  COLLOC_ENONFINITE = 6,          /* NaN/Inf in the optimality error */
+  COLLOC_RESTORATION_REQUIRED = 7 /* line search reached alpha_min (no restoration phase) */
+};
+
+/* Factor precision of kkt_factor / ipm_step. */
+enum {
+  COLLOC_FP64 = 0,    /* FP64 block factors */
+  COLLOC_FP32_IR = 1  /* FP32 block factors, FP64 parameter Schur complement, FP64 refinement */
+};
+
+/* One estimation instance (eq. 1 with mass-action right-hand side).  Host pointers, copied by
+ * colloc_create.  react/prod hold two species slots per reaction (-1 = empty slot; a
+ * bimolecular 2A reaction lists A twice); nu_sr = (count of s in prod) - (count in react). */
+typedef struct colloc_instance_desc {
+  int32_t n_s, n_r, n_p, N;
+  const int32_t* react;       /* [n_r][2] */
+  const int32_t* prod;        /* [n_r][2] */
+  const int32_t* param;       /* [n_r], index into theta or -1 (rate fixed) */
+  const double* logk_fixed;   /* [n_r], natural-log rate where param == -1 */
+  const double* h;            /* [N] element widths, > 0 */
+  const double* z0;           /* [n_s] initial state (eq. 2d) */
+  int32_t n_meas;
+  const int32_t* meas_elem;   /* [n_meas] element index in [0, N) */
+  const int32_t* meas_species;/* [n_meas] */
+  const double* meas_tau;     /* [n_meas] local time in [0, 1] inside the element */
+  const double* meas_y;       /* [n_meas] observed value */
+  const double* meas_sigma;   /* [n_meas] noise scale, > 0 */
+  const double* theta_lo;     /* [n_p] bounds (eq. 1a), theta_lo < theta_hi */
+  const double* theta_hi;     /* [n_p] */
+} colloc_instance_desc;
+
+/* Interior-point options (defaults from colloc_ipm_default_opts). */
+typedef struct colloc_ipm_opts {
+  double tol, acceptable_tol;  /* 1e-6, 1e-4 */
+  int32_t acceptable_iter;     /* 15 consecutive acceptable iterations */
+  int32_t max_iter;            /* 3000 */
+  double mu_init;              /* 0.1 */
+  double tau_r;                /* equality relaxation half-width, 1e-8 */
+  double kappa_eps, kappa_mu, theta_mu, tau_min, kappa_sigma, s_max;
+  double bound_push, bound_frac;
+  double delta_w0, delta_min, delta_max, kappa_w_minus, kappa_w_plus, kappa_w_plus_bar;
+  double gamma_theta, gamma_phi, s_theta, s_phi, eta_phi, delta_sw, gamma_alpha;
+  int32_t max_ls;              /* backtracking trials per iteration, <= COLLOC_MAX_LS */
+  int32_t precision;           /* COLLOC_FP64 or COLLOC_FP32_IR */
+  int32_t ir_max;              /* refinement sweeps in FP32_IR mode */
+  int32_t pad_;
+  double ir_tol;               /* backward-error target of the refinement */
+} colloc_ipm_opts;
+
+#define COLLOC_MAX_LS 48
+#define COLLOC_FILTER_CAP 128
+
+/* Per-instance iteration record, device-resident inside the state buffer. */
+typedef struct colloc_ipm_info {
+  int32_t status, iter, phase, ls_trials;
+  int32_t factor_tries, acc_count, filter_len, ir_sweeps;
+  double mu, tau, delta_w, delta_last;
+  double alpha_pr, alpha_du, obj, inf_pr;
+  double inf_du, E0, theta_cv, phi;
+  double theta_max, theta_min, dphi, alpha_min;
+  double Emu, s_d, s_c, resv_;
+} colloc_ipm_info;
+
+/* Sizes and per-instance offsets of a handle (host arrays owned by the handle). */
+typedef struct colloc_layout {
+  int32_t n_inst, n_s, n_r, n_p, K, b;
+  int64_t n_elem;            /* total elements over the batch */
+  int64_t n_total;           /* total primal length */
+  int64_t m_total;           /* total constraint length */
+  int64_t jac_len, hess_len; /* lengths (doubles) of the derivative value arrays */
+  const int64_t* x_off;      /* [n_inst] start of instance in x */
+  const int64_t* g_off;      /* [n_inst] start of instance in g/y/s */
+  const int64_t* elem_off;   /* [n_inst] first global element of the instance */
+  const int32_t* N;          /* [n_inst] */
+} colloc_layout;
+
+typedef struct colloc_problem colloc_problem; /* opaque host handle */
+
+/* Validate a batch and build its host tables (collocation weights l_j'(tau_k) of eq. 3,
+ * continuity weights, measurement interpolation weights, work lists).  K in [1, 5].
+ * Returns COLLOC_EUNSUPPORTED for shapes beyond the kernels' LDS budget.  Host only. */
+int colloc_create(const colloc_instance_desc* inst, int32_t n_inst, int32_t K,
+                  colloc_problem** out);
+int colloc_destroy(colloc_problem* p);
+int colloc_layout_get(const colloc_problem* p, colloc_layout* out);
+
+/* Device table bytes; colloc_upload copies the tables into caller memory of that size
+ * (256-byte aligned) and synchronizes the stream.  Must precede every device call. */
+size_t colloc_table_bytes(const colloc_problem* p);
+int colloc_upload(colloc_problem* p, void* table_dev, hipStream_t stream);
+
+/* Workspace for colloc_eval/kkt_assemble/kkt_factor/kkt_solve/kkt_matvec/ipm_step (KKT blocks,
+ * factors, solve vectors, reduction partials) and the interior-point state buffer.  The block
+ * storage depends on the factor precision: a workspace sized for COLLOC_FP64 serves both
+ * precisions; every call that touches factor blocks takes the precision explicitly. */
+size_t colloc_workspace_bytes(const colloc_problem* p, int32_t precision);
+size_t colloc_state_bytes(const colloc_problem* p);
+
+/* a1 -- pattern values (eq. 2a-2d): obj[n_inst] = Phi per instance, g[m_total].
+ * x_dev: primal point.  Deterministic (fixed reduction order). */
+int colloc_eval(const colloc_problem* p, const double* x_dev, double* obj_dev, double* g_dev,
+                void* ws_dev, hipStream_t stream);
+
+/* a2 -- derivatives of every expression pattern (the paper's per-pattern parallel AD):
+ *   grad[n_total]  = grad Phi
+ *   jac[jac_len]   = per (element i, collocation point k=1..K, reaction r), three values
+ *                    (d rho_r/d slot0, d rho_r/d slot1, d rho_r/d theta) at z[i][k]; the
+ *                    constraint Jacobian is sum_j a_jk I - h_i nu (these), plus the constant
+ *                    continuity/initial rows.  Index ((e*K + k-1)*n_r + r)*3 + t, e global.
+ *   hess[hess_len] = per (e, k, r), w_ikr * (d2rho/dslot0 dslot1, d2rho/dslot0 dtheta,
+ *                    d2rho/dslot1 dtheta, d2rho/dtheta2) with w_ikr = -h_i sum_s y[i][k][s] nu_sr,
+ *                    the weight of rho_r in y^T g.  Index ((e*K + k-1)*n_r + r)*4 + t.
+ *   The objective's Hessian is constant and applied inside kkt_assemble. */
+int colloc_derivs(const colloc_problem* p, const double* x_dev, const double* y_dev,
+                  double* grad_dev, double* jac_dev, double* hess_dev, hipStream_t stream);
+
+/* a3 -- condensed KKT assembly: K = W + Sx + dw I + J^T (Ss + dw I) J into the workspace
+ * block storage, and rhs = -r_x - J^T ((Ss + dw) r_y + r_s) (relaxed-equality primal-dual
+ * system; W = Hessian of Phi + y^T g from hess and the measurement weights).
+ *   sigma_x[n_inst*n_p] (theta entries), sigma_s[m_total], delta_w[n_inst] (device),
+ *   r_x[n_total], r_s[m_total], r_y[m_total], rhs[n_total] output.  precision selects the
+ *   block storage (must match the following kkt_factor). */
+int kkt_assemble(const colloc_problem* p, const double* jac_dev, const double* hess_dev,
+                 const double* sigma_x_dev, const double* sigma_s_dev, const double* delta_w_dev,
+                 const double* r_x_dev, const double* r_s_dev, const double* r_y_dev,
+                 void* ws_dev, int32_t precision, double* rhs_dev, hipStream_t stream);
+
+/* a4 -- pivoting-free factorization of the assembled matrix: per-element static condensation
+ * of the interior collocation points, cyclic reduction of the separator chain (element-end
+ * states) level by level, then the dense parameter Schur complement.  info[n_inst] (device):
+ * 0 = positive definite, 1 = a non-positive or non-finite pivot was met. */
+int kkt_factor(const colloc_problem* p, void* ws_dev, int32_t precision, int32_t* info_dev,
+               hipStream_t stream);
+
+/* a5 -- solve K dx = rhs with the factor (forward through the elimination levels, parameter
+ * block, back substitution).  In COLLOC_FP32_IR mode up to ir_max FP64 refinement sweeps with
+ * the matrix-free FP64 residual rhs - K dx; ir_sweeps[n_inst] (device) receives the count. */
+int kkt_solve(const colloc_problem* p, void* ws_dev, int32_t precision, const double* rhs_dev,
+              double* dx_dev, int32_t ir_max, double ir_tol, int32_t* ir_sweeps_dev,
+              hipStream_t stream);
+
+/* out = K v with the assembled matrix, evaluated matrix-free in FP64 from the derivative
+ * values, Ds, Sx and dw stored by the last kkt_assemble or ipm_step (the residual of the
+ * refinement).  v and out must not alias. */
+int kkt_matvec(const colloc_problem* p, void* ws_dev, const double* v_dev, double* out_dev,
+               hipStream_t stream);
+
+/* a6 -- interior-point iteration.  ipm_init pushes theta into its bounds, sets the slacks,
+ * multipliers, mu and filter (state buffer of colloc_state_bytes).  ipm_step performs one
+ * iteration for every running instance: evaluate, test convergence, update mu, assemble and
+ * factor (an indefinite matrix makes the step a retry with a larger delta_w), solve, fraction
+ * to the boundary, filter line search over the backtracking candidates, update.  Finished
+ * instances are left unchanged. */
+void colloc_ipm_default_opts(colloc_ipm_opts* o);
+int ipm_init(const colloc_problem* p, const double* x0_dev, void* state_dev, void* ws_dev,
+             const colloc_ipm_opts* opts, hipStream_t stream);
+int ipm_step(const colloc_problem* p, void* state_dev, void* ws_dev, const colloc_ipm_opts* opts,
+             hipStream_t stream);
+
+/* Byte offsets of the state buffer's fields: x[n_total], s, y, vL, vU [m_total], zL, zU
+ * [n_inst*n_p], dx[n_total], info[n_inst] (colloc_ipm_info). */
+typedef struct colloc_state_layout {
+  size_t x, s, y, vL, vU, zL, zU, dx, ds, dy, info;
+} colloc_state_layout;
+int colloc_state_layout_get(const colloc_problem* p, colloc_state_layout* out);
+
+/* Per-phase timing with HIP events recorded on the call's stream around each phase launch:
+ * enable, then read accumulated milliseconds and launch counts per phase. */
+enum {
+  COLLOC_PH_EVAL = 0, COLLOC_PH_LEVEL0 = 1, COLLOC_PH_CR = 2, COLLOC_PH_BORDER = 3,
+  COLLOC_PH_SOLVE = 4, COLLOC_PH_STEP = 5, COLLOC_PH_LINESEARCH = 6, COLLOC_N_PHASES = 7
+};
+int colloc_timing_enable(colloc_problem* p, int32_t enable);
+int colloc_timing_read(colloc_problem* p, double* ms, int64_t* launches, int32_t n);
+
+/* Collocation tables computed by the library (tau[K+1], a[(K+1)*(K+1)] with a[j*(K+1)+k] =
+ * l_j'(tau_k)), for inspection. */
+int colloc_tables(int32_t K, double* tau, double* a);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* COLLOC_H */

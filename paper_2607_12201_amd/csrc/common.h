@@ -1,0 +1,113 @@
+// Internal structures shared by the host API and the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define CL_KMAX 5
+#define CL_MAX_LS 48
+#define CL_FILTER_CAP 128
+
+// Shape class of a batch.  Local variable order inside an element: z[j][s] (b = (K+1) ns);
+// the element's interior block I = nodes 0..K-1 (mI = K ns), its separator S = node K.
+// Panel rows of the level-0 elimination: I (mI), S (ns), P = previous separator (ns),
+// theta (np); R = mI + 2 ns + np rows, mI columns.
+struct Shape {
+  int ns, nr, np, K, b, mI, R, Rt;
+  double a[CL_KMAX + 1][CL_KMAX + 1];  // a[j][k] = l_j'(tau_k)
+};
+
+// Device tables (all pointers into the caller's table buffer).
+struct Tab {
+  int n_inst;
+  int L;                      // cyclic-reduction levels (max over the batch)
+  int64_t n_elem;
+  const int* inst_N;
+  const int64_t* inst_x;      // x offset per instance
+  const int64_t* inst_g;      // g offset per instance
+  const int64_t* inst_e0;     // first global element per instance
+  const int* elem_inst;
+  const int* elem_loc;
+  const double* elem_h;
+  const int* elem_mptr;       // [n_elem + 1] measurement CSR
+  const int* meas_sp;
+  const double* meas_w;       // [n_meas][K+1]  l_j(tau_m) / sigma_m
+  const double* meas_ys;      // y_m / sigma_m
+  const int* react;           // [n_inst][nr][2]
+  const int* param;           // [n_inst][nr]
+  const double* logk;         // [n_inst][nr] fixed natural-log rates (param == -1)
+  const int* sp_ptr;          // [n_inst][ns + 1] absolute offsets into sp_r/sp_nu
+  const int* sp_r;            // reactions with nu_sr != 0, per species
+  const double* sp_nu;
+  const int* rx_sp;           // [n_inst][nr][4] species with nu_sr != 0, -1 padded
+  const double* rx_nu;        // [n_inst][nr][4]
+  const double* z0;           // [n_inst][ns]
+  const double* th_lo;        // [n_inst][np]
+  const double* th_hi;
+  const int* cr_ptr;          // [L + 1]
+  const int* cr_inst;         // per work item of a cyclic-reduction level
+  const int* cr_j;
+  int cr_items_max;           // largest level
+};
+
+// Workspace pointers (device).  Block data of type T (double or float) lives in void*.
+struct Ws {
+  int prec;                   // 0 fp64, 1 fp32
+  void* panel;                // [n_elem][R*mI]  column-major, ld = R
+  void* dss;                  // [n_elem][ns*ns] S-S block, then T-self Schur output
+  void* bs;                   // [n_elem][ns*np] S-theta block, then G-self
+  void* tprev;                // [n_elem][ns*ns]  contribution to the previous separator
+  void* e1;                   // [n_elem][ns*ns]  coupling (S_i, S_{i-1})
+  void* gprev;                // [n_elem][ns*np]
+  void* lsep;                 // [n_elem][ns*ns]  separator factors (separator j = element j)
+  void* ul;                   // [n_elem][ns*ns]
+  void* ur;                   // [n_elem][ns*ns]
+  void* ub;                   // [n_elem][ns*np]
+  double* dcont;              // [n_elem][ns]   continuity weight on the previous separator
+  double* ath;                // [n_elem][np*np] element theta-theta block, then its Schur part
+  double* thcr;               // [n_elem][np*np] theta-theta part from each separator
+  double* S;                  // [n_inst][np*np] parameter Schur complement / its factor
+  double* thred;              // [n_inst][nchunk][np*np] reduction partials
+  int nchunk;                 // chunks per instance (max over the batch)
+  double* yI;                 // [n_elem][mI]
+  double* cS;                 // [n_elem][ns]
+  double* cP;                 // [n_elem][ns]
+  double* cB;                 // [n_elem][np]
+  double* ysep;               // [n_elem][ns]
+  double* xsep;               // [n_elem][ns]
+  double* cBsep;              // [n_elem][np]
+  double* rthp;               // [n_elem][np] right-hand-side theta partials
+  double* xth;                // [n_inst][np]
+  double* jac;                // derivative values used by assembly and the matvec
+  double* hess;
+  double* Ds;                 // [m_total] slack-block diagonal Ss + dw
+  double* sxdw;               // [n_inst][np] Sx + dw on theta
+  double* dw;                 // [n_inst]
+  double* vtmp;               // [n_total] refinement residual / correction
+  double* vtmp2;              // [n_total]
+  double* epart;              // [n_elem][EP_N] element partial sums
+  double* ipart;              // [n_inst][EP_N]
+  int* flag;                  // [n_inst] factor failure flags
+};
+
+// Element partial-sum slots (colloc_eval and the interior-point reductions).
+enum {
+  EP_OBJ = 0,     // sum of r_m^2 / 2
+  EP_L1PR,        // sum |g - s|
+  EP_INFPR,       // max |g - s|
+  EP_INFDU,       // max |grad_z L| and |grad_s L|
+  EP_L1Y,         // sum |y|
+  EP_L1V,         // sum |vL| + |vU|
+  EP_CMAX, EP_CMIN,  // complementarity max/min over slack bounds
+  EP_LOGS,        // sum log(s + tau) + log(tau - s)
+  EP_NONFIN,      // nonzero when a non-finite value was seen
+  EP_FTB_P,       // min primal step ratio
+  EP_FTB_D,       // min dual step ratio
+  EP_DPHI,        // directional derivative partial
+  EP_N
+};
+
+__host__ __device__ inline int64_t cl_ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Elements per partial of the parameter Schur reduction.  Fixed, so an instance's summation
+// order depends on its own N only (same result alone and inside any batch).
+#define CL_THCHUNK 16

@@ -1,0 +1,272 @@
+// Per-element device helpers: mass-action rates, J v, J^T u and W v for one finite element,
+// executed cooperatively by the threads of one workgroup on LDS-resident vectors.
+#pragma once
+#include "common.h"
+
+namespace cl {
+
+__device__ inline int tid() { return threadIdx.x; }
+__device__ inline int nthr() { return blockDim.x; }
+
+// Per-instance skip flag read once per workgroup: other workgroups of the same launch may set
+// it concurrently, so every wave takes the decision from one LDS copy (uniform control flow
+// around the barriers that follow).
+__device__ inline bool block_flag(const int* f) {
+  __shared__ int sflag;
+  if (threadIdx.x == 0) sflag = __atomic_load_n(f, __ATOMIC_RELAXED);
+  __syncthreads();
+  return sflag != 0;
+}
+
+// kappa_r = exp(theta[param_r]) or exp(logk_r)
+__device__ inline void load_kappa(const Shape& S, const Tab& tb, int inst, const double* th,
+                                  double* kap) {
+  for (int r = tid(); r < S.nr; r += nthr()) {
+    int c = tb.param[inst * S.nr + r];
+    kap[r] = exp(c >= 0 ? th[c] : tb.logk[inst * S.nr + r]);
+  }
+}
+
+// rho[k-1][r] and slot partials at collocation points k = 1..K of an element (z in LDS).
+__device__ inline void rates(const Shape& S, const Tab& tb, int inst, const double* z,
+                             const double* kap, double* rho, double* d0, double* d1) {
+  const int nr = S.nr, ns = S.ns;
+  for (int t = tid(); t < S.K * nr; t += nthr()) {
+    int k = t / nr + 1, r = t - (k - 1) * nr;
+    int q0 = tb.react[(inst * nr + r) * 2], q1 = tb.react[(inst * nr + r) * 2 + 1];
+    double u0 = q0 >= 0 ? z[k * ns + q0] : 1.0;
+    double u1 = q1 >= 0 ? z[k * ns + q1] : 1.0;
+    double kk = kap[r];
+    rho[t] = kk * u0 * u1;
+    if (d0) {
+      d0[t] = q0 >= 0 ? kk * u1 : 0.0;
+      d1[t] = q1 >= 0 ? kk * u0 : 0.0;
+    }
+  }
+}
+
+// Collocation/continuity residual rows of element i (b rows, LDS out).
+__device__ inline void residual_rows(const Shape& S, const Tab& tb, int inst, int i, double h,
+                                     const double* z, const double* zprevK, const double* rho,
+                                     double* g) {
+  const int ns = S.ns, nr = S.nr;
+  for (int t = tid(); t < S.b; t += nthr()) {
+    int j = t / ns, s = t - j * ns;
+    double v;
+    if (j == 0) {
+      v = z[s] - (i == 0 ? tb.z0[inst * ns + s] : zprevK[s]);
+    } else {
+      double acc = 0.0;
+      for (int jj = 0; jj <= S.K; ++jj) acc += S.a[jj][j] * z[jj * ns + s];
+      double f = 0.0;
+      int p0 = tb.sp_ptr[inst * (ns + 1) + s], p1 = tb.sp_ptr[inst * (ns + 1) + s + 1];
+      for (int q = p0; q < p1; ++q) f += tb.sp_nu[q] * rho[(j - 1) * nr + tb.sp_r[q]];
+      v = acc - h * f;
+    }
+    g[t] = v;
+  }
+}
+
+// (J v) for the b rows of element i.  v: element's z (LDS, b), vprevK: node-K values of the
+// previous element (ns) or unused for i == 0, vth: theta part (np), jac: element's values.
+__device__ inline void jv_rows(const Shape& S, const Tab& tb, int inst, int i, double h,
+                               const double* jac, const double* v, const double* vprevK,
+                               const double* vth, double* out) {
+  const int ns = S.ns, nr = S.nr;
+  for (int t = tid(); t < S.b; t += nthr()) {
+    int j = t / ns, s = t - j * ns;
+    double acc;
+    if (j == 0) {
+      acc = v[s] - (i == 0 ? 0.0 : vprevK[s]);
+    } else {
+      acc = 0.0;
+      for (int jj = 0; jj <= S.K; ++jj) acc += S.a[jj][j] * v[jj * ns + s];
+      double f = 0.0;
+      int p0 = tb.sp_ptr[inst * (ns + 1) + s], p1 = tb.sp_ptr[inst * (ns + 1) + s + 1];
+      for (int q = p0; q < p1; ++q) {
+        int r = tb.sp_r[q];
+        const double* jr = jac + ((j - 1) * nr + r) * 3;
+        int q0 = tb.react[(inst * nr + r) * 2], q1 = tb.react[(inst * nr + r) * 2 + 1];
+        int c = tb.param[inst * nr + r];
+        double dr = 0.0;
+        if (q0 >= 0) dr += jr[0] * v[j * ns + q0];
+        if (q1 >= 0) dr += jr[1] * v[j * ns + q1];
+        if (c >= 0) dr += jr[2] * vth[c];
+        f += tb.sp_nu[q] * dr;
+      }
+      acc -= h * f;
+    }
+    out[t] = acc;
+  }
+}
+
+// phi[k-1][r] = sum_s nu_sr u[k][s]: reaction-space projection of row weights (LDS).
+__device__ inline void reaction_weights(const Shape& S, const Tab& tb, int inst, const double* u,
+                                        double* phi) {
+  const int nr = S.nr, ns = S.ns;
+  for (int t = tid(); t < S.K * nr; t += nthr()) {
+    int k = t / nr + 1, r = t - (k - 1) * nr;
+    double acc = 0.0;
+    for (int q = 0; q < 4; ++q) {
+      int sp = tb.rx_sp[(inst * nr + r) * 4 + q];
+      if (sp >= 0) acc += tb.rx_nu[(inst * nr + r) * 4 + q] * u[k * ns + sp];
+    }
+    phi[t] = acc;
+  }
+}
+
+// (J^T u) restricted to element i's z variables (b outputs) given the element's row weights
+// u (b), the next element's node-0 row weights unext0 (ns; nullptr for the last element), and
+// phi from reaction_weights.  Theta contributions are returned per parameter (np partials).
+__device__ inline void jtu_rows(const Shape& S, const Tab& tb, int inst, double h,
+                                const double* jac, const double* u, const double* unext0,
+                                const double* phi, double* outz, double* outth) {
+  const int ns = S.ns, nr = S.nr, K = S.K;
+  for (int t = tid(); t < S.b; t += nthr()) {
+    int j = t / ns, s = t - j * ns;
+    double acc = (j == 0) ? u[s] : 0.0;
+    for (int k = 1; k <= K; ++k) acc += S.a[j][k] * u[k * ns + s];
+    if (j >= 1) {
+      double f = 0.0;
+      for (int r = 0; r < nr; ++r) {
+        int q0 = tb.react[(inst * nr + r) * 2], q1 = tb.react[(inst * nr + r) * 2 + 1];
+        const double* jr = jac + ((j - 1) * nr + r) * 3;
+        double w = 0.0;
+        if (q0 == s) w += jr[0];
+        if (q1 == s) w += jr[1];
+        if (w != 0.0) f += w * phi[(j - 1) * nr + r];
+      }
+      acc -= h * f;
+    }
+    if (j == K && unext0) acc -= unext0[s];
+    outz[t] = acc;
+  }
+  if (outth) {
+    for (int c = tid(); c < S.np; c += nthr()) {
+      double acc = 0.0;
+      for (int k = 1; k <= K; ++k)
+        for (int r = 0; r < nr; ++r)
+          if (tb.param[inst * nr + r] == c) acc += jac[((k - 1) * nr + r) * 3 + 2] * phi[(k - 1) * nr + r];
+      outth[c] = -h * acc;
+    }
+  }
+}
+
+// (W v) for element i: z outputs (b) and theta partials (np).  W = sum of the reaction
+// second-derivative patterns (hess values) plus the measurement Hessian of the element.
+__device__ inline void wv_rows(const Shape& S, const Tab& tb, int inst, int64_t e,
+                               const double* hess, const double* v, const double* vth,
+                               double* outz, double* outth) {
+  const int ns = S.ns, nr = S.nr, K = S.K;
+  for (int t = tid(); t < S.b; t += nthr()) {
+    int j = t / ns, s = t - j * ns;
+    double acc = 0.0;
+    if (j >= 1) {
+      for (int r = 0; r < nr; ++r) {
+        int q0 = tb.react[(inst * nr + r) * 2], q1 = tb.react[(inst * nr + r) * 2 + 1];
+        int c = tb.param[inst * nr + r];
+        const double* H = hess + ((j - 1) * nr + r) * 4;
+        if (q0 == s) {
+          if (q1 >= 0) acc += H[0] * v[j * ns + q1];
+          if (c >= 0) acc += H[1] * vth[c];
+        }
+        if (q1 == s) {
+          if (q0 >= 0) acc += H[0] * v[j * ns + q0];
+          if (c >= 0) acc += H[2] * vth[c];
+        }
+      }
+    }
+    int m0 = tb.elem_mptr[e], m1 = tb.elem_mptr[e + 1];
+    for (int m = m0; m < m1; ++m) {
+      if (tb.meas_sp[m] != s) continue;
+      const double* w = tb.meas_w + (int64_t)m * (K + 1);
+      double dot = 0.0;
+      for (int jj = 0; jj <= K; ++jj) dot += w[jj] * v[jj * ns + s];
+      acc += w[j] * dot;
+    }
+    outz[t] = acc;
+  }
+  if (outth) {
+    for (int c = tid(); c < S.np; c += nthr()) {
+      double acc = 0.0;
+      for (int k = 1; k <= K; ++k)
+        for (int r = 0; r < nr; ++r) {
+          if (tb.param[inst * nr + r] != c) continue;
+          int q0 = tb.react[(inst * nr + r) * 2], q1 = tb.react[(inst * nr + r) * 2 + 1];
+          const double* H = hess + ((k - 1) * nr + r) * 4;
+          if (q0 >= 0) acc += H[1] * v[k * ns + q0];
+          if (q1 >= 0) acc += H[2] * v[k * ns + q1];
+          acc += H[3] * vth[c];
+        }
+      outth[c] = acc;
+    }
+  }
+}
+
+// Objective residuals r_m of the element's measurements and grad Phi on its z (owner per var).
+__device__ inline double obj_element(const Shape& S, const Tab& tb, int64_t e, const double* z,
+                                     double* gradz) {
+  const int ns = S.ns, K = S.K;
+  int m0 = tb.elem_mptr[e], m1 = tb.elem_mptr[e + 1];
+  if (gradz) {
+    for (int t = tid(); t < S.b; t += nthr()) {
+      int j = t / ns, s = t - j * ns;
+      double acc = 0.0;
+      for (int m = m0; m < m1; ++m) {
+        if (tb.meas_sp[m] != s) continue;
+        const double* w = tb.meas_w + (int64_t)m * (K + 1);
+        double pr = -tb.meas_ys[m];
+        for (int jj = 0; jj <= K; ++jj) pr += w[jj] * z[jj * ns + s];
+        acc += pr * w[j];
+      }
+      gradz[t] = acc;
+    }
+  }
+  // objective: sequential over the element's measurements (fixed order, few per element)
+  double phi = 0.0;
+  for (int m = m0; m < m1; ++m) {
+    const double* w = tb.meas_w + (int64_t)m * (K + 1);
+    int s = tb.meas_sp[m];
+    double pr = -tb.meas_ys[m];
+    for (int jj = 0; jj <= K; ++jj) pr += w[jj] * z[jj * ns + s];
+    phi += 0.5 * pr * pr;
+  }
+  return phi;
+}
+
+// Deterministic block reductions (fixed pairing for a given blockDim).
+__device__ inline double block_sum(double v, double* red) {
+  red[tid()] = v;
+  __syncthreads();
+  for (int w = nthr() / 2; w > 0; w >>= 1) {
+    if (tid() < w) red[tid()] += red[tid() + w];
+    __syncthreads();
+  }
+  double r = red[0];
+  __syncthreads();
+  return r;
+}
+__device__ inline double block_max(double v, double* red) {
+  red[tid()] = v;
+  __syncthreads();
+  for (int w = nthr() / 2; w > 0; w >>= 1) {
+    if (tid() < w) red[tid()] = fmax(red[tid()], red[tid() + w]);
+    __syncthreads();
+  }
+  double r = red[0];
+  __syncthreads();
+  return r;
+}
+__device__ inline double block_min(double v, double* red) {
+  red[tid()] = v;
+  __syncthreads();
+  for (int w = nthr() / 2; w > 0; w >>= 1) {
+    if (tid() < w) red[tid()] = fmin(red[tid()], red[tid() + w]);
+    __syncthreads();
+  }
+  double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+}  // namespace cl

@@ -1,0 +1,1090 @@
+// a3-a5: condensed KKT assembly, pivoting-free factorization and solve.
+//
+// Matrix K = W + Sx + dw I + J^T Ds J of one instance is block tridiagonal over the finite
+// elements (element i couples to element i-1 only through the continuity rows, eq. 2c) with a
+// dense border in theta.  Elimination order (a nested-dissection ordering of the time chain):
+//   level 0   every element eliminates its interior collocation nodes 0..K-1 (all elements in
+//             parallel, one workgroup each, dense LDS panel), leaving a chain of separators
+//             S_i = node K of element i (n_s each) with a theta border;
+//   levels 1..L  cyclic reduction of that chain: at level l the separators j = q 2^(l-1), q odd,
+//             are eliminated in parallel; each update of a survivor is gathered by the
+//             workgroup that eliminates it later, in a fixed order (no atomics);
+//   border    separator 0 last, then the dense parameter Schur complement (FP64) and its
+//             Cholesky factor.
+// The solve walks the same levels forward and backward.  Block data is FP64 or FP32 (T); the
+// parameter Schur complement, its right-hand side and all vectors are FP64.
+#include <stdio.h>
+#include <stdlib.h>
+
+#include "kernels.h"
+#include "elem.h"
+
+namespace cl {
+
+template <typename T>
+struct L0Lds {
+  double *ath, *dcont, *d, *d0, *F, *Fth, *Wzz, *Wzt, *Wtt, *misc;
+  T *Q, *dss, *bs;
+};
+
+template <typename T>
+__device__ inline L0Lds<T> l0_carve(const Shape& S, void* base) {
+  L0Lds<T> L;
+  double* p = (double*)base;
+  L.ath = p; p += S.np * S.np;
+  L.dcont = p; p += S.ns;
+  L.d = p; p += S.ns;
+  L.d0 = p; p += S.ns;
+  L.F = p; p += S.ns * S.ns;
+  L.Fth = p; p += S.ns * S.np;
+  L.Wzz = p; p += S.ns * S.ns;
+  L.Wzt = p; p += S.ns * S.np;
+  L.Wtt = p; p += S.np;
+  L.misc = p; p += 8;
+  T* q = (T*)p;
+  L.Q = q; q += S.R * S.mI;
+  L.dss = q; q += S.ns * S.ns;
+  L.bs = q;
+  return L;
+}
+
+size_t level0_lds_bytes(const Shape& S, int prec) {
+  size_t nd = (size_t)S.np * S.np + 3 * S.ns + 2 * S.ns * S.ns + 2 * S.ns * S.np + S.np + 8;
+  size_t nt = (size_t)S.R * S.mI + S.ns * S.ns + S.ns * S.np;
+  return nd * 8 + nt * (prec ? 4 : 8);
+}
+
+__device__ inline void tri_index(int t, int& r1, int& r2) {
+  int r = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((r + 1) * (r + 2) / 2 <= t) ++r;
+  while (r * (r + 1) / 2 > t) --r;
+  r1 = r;
+  r2 = t - r * (r + 1) / 2;
+}
+
+// Value of K's lower-triangle entry (r1 >= r2, element-local natural indices: z (j,s) at
+// j*ns+s, theta c at b+c) contributed by the collocation rows of point k.
+__device__ inline double node_contrib(const Shape& S, int k, double h, const double* d,
+                                      const double* F, const double* Fth, const double* Wzz,
+                                      const double* Wzt, const double* Wtt, int r1, int r2) {
+  const int ns = S.ns, np = S.np, b = S.b;
+  double v = 0.0;
+  if (r1 < b) {
+    int j1 = r1 / ns, s1 = r1 - j1 * ns, j2 = r2 / ns, s2 = r2 - j2 * ns;
+    double a1 = S.a[j1][k], a2 = S.a[j2][k];
+    if (s1 == s2) v += d[s1] * a1 * a2;
+    if (j2 == k) v -= h * d[s1] * a1 * F[s1 * ns + s2];
+    if (j1 == k) v -= h * d[s2] * a2 * F[s2 * ns + s1];
+    if (j1 == k && j2 == k) {
+      double acc = 0.0;
+      for (int s = 0; s < ns; ++s) acc += d[s] * F[s * ns + s1] * F[s * ns + s2];
+      v += h * h * acc + Wzz[s1 * ns + s2];
+    }
+  } else if (r2 < b) {
+    int c = r1 - b, j1 = r2 / ns, s1 = r2 - j1 * ns;
+    v -= h * d[s1] * S.a[j1][k] * Fth[s1 * np + c];
+    if (j1 == k) {
+      double acc = 0.0;
+      for (int s = 0; s < ns; ++s) acc += d[s] * F[s * ns + s1] * Fth[s * np + c];
+      v += h * h * acc + Wzt[s1 * np + c];
+    }
+  } else {
+    int c1 = r1 - b, c2 = r2 - b;
+    double acc = 0.0;
+    for (int s = 0; s < ns; ++s) acc += d[s] * Fth[s * np + c1] * Fth[s * np + c2];
+    v = h * h * acc + (c1 == c2 ? Wtt[c1] : 0.0);
+  }
+  return v;
+}
+
+// Node-0 rows (initial condition / continuity), the measurement Hessian and dw on z.
+__device__ inline double base_contrib(const Shape& S, const Tab& tb, int64_t e, double dw,
+                                      const double* d0, int r1, int r2) {
+  const int ns = S.ns, b = S.b, K = S.K;
+  if (r1 >= b) return 0.0;
+  int j1 = r1 / ns, s1 = r1 - j1 * ns, j2 = r2 / ns, s2 = r2 - j2 * ns;
+  double v = 0.0;
+  if (r1 == r2) v += dw;
+  if (s1 != s2) return v;
+  if (j1 == 0 && j2 == 0) v += d0[s1];
+  int m0 = tb.elem_mptr[e], m1 = tb.elem_mptr[e + 1];
+  for (int m = m0; m < m1; ++m)
+    if (tb.meas_sp[m] == s1) {
+      const double* w = tb.meas_w + (int64_t)m * (K + 1);
+      v += w[j1] * w[j2];
+    }
+  return v;
+}
+
+// Storage of a lower-triangle entry in the level-0 LDS blocks.
+template <typename T>
+__device__ inline void entry_store(const Shape& S, L0Lds<T>& L, int r1, int r2, double v,
+                                   bool add) {
+  const int ns = S.ns, np = S.np, b = S.b, mI = S.mI, R = S.R;
+  if (r2 < mI) {
+    int row = r1 < b ? r1 : r1 + ns;
+    T* p = &L.Q[r2 * R + row];
+    *p = add ? (T)((double)*p + v) : (T)v;
+  } else if (r2 < b) {
+    T* p = (r1 < b) ? &L.dss[(r1 - mI) * ns + (r2 - mI)] : &L.bs[(r2 - mI) * np + (r1 - b)];
+    *p = add ? (T)((double)*p + v) : (T)v;
+  } else {
+    double* p = &L.ath[(r1 - b) * np + (r2 - b)];
+    *p = add ? *p + v : v;
+  }
+}
+
+// Assemble element e's blocks of K into LDS.  Inputs: derivative values of the element
+// (jac_e, hess_e), Ds of its rows (Ds_e), dw.  Accumulation is in FP64 per entry; with T =
+// float each addition rounds into the FP32 panel.
+template <typename T>
+__device__ void assemble_element(const Shape& S, const Tab& tb, int64_t e, int inst, int i,
+                                 double h, const double* jac_e, const double* hess_e,
+                                 const double* Ds_e, double dw, L0Lds<T>& L) {
+  const int ns = S.ns, np = S.np, nr = S.nr, b = S.b, mI = S.mI, R = S.R;
+  const int nb = b + np, ntri = nb * (nb + 1) / 2;
+  for (int t = tid(); t < ns; t += nthr()) {
+    L.d0[t] = Ds_e[t];
+    L.dcont[t] = i > 0 ? Ds_e[t] : 0.0;
+  }
+  __syncthreads();
+  for (int t = tid(); t < ntri; t += nthr()) {
+    int r1, r2;
+    tri_index(t, r1, r2);
+    entry_store(S, L, r1, r2, base_contrib(S, tb, e, dw, L.d0, r1, r2), false);
+  }
+  // coupling of node-0 rows to the previous separator (continuity, eq. 2c)
+  for (int t = tid(); t < ns * mI; t += nthr()) {
+    int col = t / ns, s = t - col * ns;
+    L.Q[col * R + mI + ns + s] = (T)((i > 0 && col == s) ? -L.d0[s] : 0.0);
+  }
+  for (int k = 1; k <= S.K; ++k) {
+    __syncthreads();
+    for (int s = tid(); s < ns; s += nthr()) {
+      L.d[s] = Ds_e[k * ns + s];
+      for (int q = 0; q < ns; ++q) L.F[s * ns + q] = 0.0;
+      for (int c = 0; c < np; ++c) L.Fth[s * np + c] = 0.0;
+      int p0 = tb.sp_ptr[inst * (ns + 1) + s], p1 = tb.sp_ptr[inst * (ns + 1) + s + 1];
+      for (int q = p0; q < p1; ++q) {
+        int r = tb.sp_r[q];
+        double nu = tb.sp_nu[q];
+        const double* jr = jac_e + ((k - 1) * nr + r) * 3;
+        int q0 = tb.react[(inst * nr + r) * 2], q1 = tb.react[(inst * nr + r) * 2 + 1];
+        int c = tb.param[inst * nr + r];
+        if (q0 >= 0) L.F[s * ns + q0] += nu * jr[0];
+        if (q1 >= 0) L.F[s * ns + q1] += nu * jr[1];
+        if (c >= 0) L.Fth[s * np + c] += nu * jr[2];
+      }
+    }
+    for (int q = tid(); q < ns; q += nthr()) {
+      for (int s2 = 0; s2 < ns; ++s2) L.Wzz[q * ns + s2] = 0.0;
+      for (int c = 0; c < np; ++c) L.Wzt[q * np + c] = 0.0;
+      for (int r = 0; r < nr; ++r) {
+        int q0 = tb.react[(inst * nr + r) * 2], q1 = tb.react[(inst * nr + r) * 2 + 1];
+        if (q0 != q && q1 != q) continue;
+        int c = tb.param[inst * nr + r];
+        const double* H = hess_e + ((k - 1) * nr + r) * 4;
+        if (q0 == q) {
+          if (q1 >= 0) L.Wzz[q * ns + q1] += H[0];
+          if (c >= 0) L.Wzt[q * np + c] += H[1];
+        }
+        if (q1 == q) {
+          if (q0 >= 0) L.Wzz[q * ns + q0] += H[0];
+          if (c >= 0) L.Wzt[q * np + c] += H[2];
+        }
+      }
+    }
+    for (int c = tid(); c < np; c += nthr()) {
+      double acc = 0.0;
+      for (int r = 0; r < nr; ++r)
+        if (tb.param[inst * nr + r] == c) acc += hess_e[((k - 1) * nr + r) * 4 + 3];
+      L.Wtt[c] = acc;
+    }
+    __syncthreads();
+    for (int t = tid(); t < ntri; t += nthr()) {
+      int r1, r2;
+      tri_index(t, r1, r2);
+      double v = node_contrib(S, k, h, L.d, L.F, L.Fth, L.Wzz, L.Wzt, L.Wtt, r1, r2);
+      entry_store(S, L, r1, r2, v, true);
+    }
+  }
+  __syncthreads();
+}
+
+// In-place Cholesky of the first mI columns of the R x mI column-major panel.
+template <typename T>
+__device__ bool panel_cholesky(T* Q, int R, int mI, double* misc) {
+  for (int c = 0; c < mI; ++c) {
+    if (tid() == 0) {
+      double piv = (double)Q[c * R + c];
+      bool ok = piv > 0.0 && isfinite(piv);
+      double sq = ok ? sqrt(piv) : 1.0;
+      Q[c * R + c] = (T)sq;
+      misc[0] = ok ? 1.0 : 0.0;
+      misc[1] = 1.0 / sq;
+    }
+    __syncthreads();
+    if (misc[0] == 0.0) return false;
+    T inv = (T)misc[1];
+    for (int r = c + 1 + tid(); r < R; r += nthr()) Q[c * R + r] *= inv;
+    __syncthreads();
+    const int nrow = R - c - 1, ncol = mI - c - 1;
+    for (int t = tid(); t < nrow * ncol; t += nthr()) {
+      int c2 = c + 1 + t / nrow, r = c + 1 + t % nrow;
+      if (r >= c2) Q[c2 * R + r] -= Q[c * R + r] * Q[c * R + c2];
+    }
+    __syncthreads();
+  }
+  return true;
+}
+
+// Schur complement of the panel onto its tail rows (S, P, theta) written to the chain blocks.
+template <typename T>
+__device__ void level0_outputs(const Shape& S, const Ws& ws, int64_t e, int i, L0Lds<T>& L) {
+  const int ns = S.ns, np = S.np, mI = S.mI, R = S.R, Rt = S.Rt;
+  const int ntri = Rt * (Rt + 1) / 2;
+  T* dss = (T*)ws.dss + e * ns * ns;
+  T* bs = (T*)ws.bs + e * ns * np;
+  T* tprev = (T*)ws.tprev + e * ns * ns;
+  T* e1 = (T*)ws.e1 + e * ns * ns;
+  T* gprev = (T*)ws.gprev + e * ns * np;
+  double* ath = ws.ath + e * np * np;
+  for (int t = tid(); t < ntri; t += nthr()) {
+    int a, c;
+    tri_index(t, a, c);  // a >= c, tail indices
+    bool aP = a >= ns && a < 2 * ns, cP = c >= ns && c < 2 * ns;
+    if (i == 0 && (aP || cP)) continue;
+    double acc = 0.0;
+    const T* qa = L.Q + mI + a;
+    const T* qc = L.Q + mI + c;
+    for (int k = 0; k < mI; ++k) acc += (double)qa[k * R] * (double)qc[k * R];
+    if (a < ns) {                       // S-S
+      dss[a * ns + c] = (T)((double)L.dss[a * ns + c] - acc);
+    } else if (a < 2 * ns) {
+      if (c < ns) e1[c * ns + (a - ns)] = (T)(-acc);           // (S_i c, S_{i-1} a-ns)
+      else tprev[(a - ns) * ns + (c - ns)] = (T)(((a == c) ? L.dcont[a - ns] : 0.0) - acc);
+    } else {
+      int th = a - 2 * ns;
+      if (c < ns) bs[c * np + th] = (T)((double)L.bs[c * np + th] - acc);
+      else if (c < 2 * ns) gprev[(c - ns) * np + th] = (T)(-acc);
+      else ath[th * np + (c - 2 * ns)] = L.ath[th * np + (c - 2 * ns)] - acc;
+    }
+  }
+}
+
+// kkt_assemble: blocks to the workspace (unfactored), derivative copies, Ds, rhs.
+template <typename T>
+__global__ void __launch_bounds__(256) k_assemble(Shape S, Tab tb, Ws ws, const double* __restrict__ jac,
+                                                  const double* __restrict__ hess, const double* __restrict__ sigma_s,
+                                                  const double* __restrict__ delta_w, const double* __restrict__ r_x,
+                                                  const double* __restrict__ r_s, const double* __restrict__ r_y,
+                                                  double* __restrict__ rhs) {
+  extern __shared__ double lds_raw[];
+  const int64_t e = blockIdx.x;
+  const int inst = tb.elem_inst[e], i = tb.elem_loc[e];
+  const int N = tb.inst_N[inst];
+  const double h = tb.elem_h[e];
+  const int ns = S.ns, np = S.np, b = S.b, R = S.R, mI = S.mI;
+  const double dw = delta_w[inst];
+  const int64_t gi = tb.inst_g[inst] + (int64_t)i * b;
+  const int64_t xi = tb.inst_x[inst] + (int64_t)i * b;
+  const int64_t jl = (int64_t)S.K * S.nr;
+  // copies used later by the factor and the matrix-free residual
+  for (int t = tid(); t < jl * 3; t += nthr()) ws.jac[e * jl * 3 + t] = jac[e * jl * 3 + t];
+  for (int t = tid(); t < jl * 4; t += nthr()) ws.hess[e * jl * 4 + t] = hess[e * jl * 4 + t];
+  for (int t = tid(); t < b; t += nthr()) ws.Ds[gi + t] = sigma_s[gi + t] + dw;
+  if (i == 0 && tid() == 0) ws.dw[inst] = dw;
+  L0Lds<T> L = l0_carve<T>(S, lds_raw);
+  __syncthreads();
+  assemble_element<T>(S, tb, e, inst, i, h, ws.jac + e * jl * 3, ws.hess + e * jl * 4,
+                      ws.Ds + gi, dw, L);
+  // store blocks
+  T* Qg = (T*)ws.panel + e * (int64_t)R * mI;
+  for (int t = tid(); t < R * mI; t += nthr()) Qg[t] = L.Q[t];
+  T* dssg = (T*)ws.dss + e * ns * ns;
+  T* bsg = (T*)ws.bs + e * ns * np;
+  for (int t = tid(); t < ns * ns; t += nthr()) dssg[t] = L.dss[t];
+  for (int t = tid(); t < ns * np; t += nthr()) bsg[t] = L.bs[t];
+  for (int t = tid(); t < np * np; t += nthr()) ws.ath[e * np * np + t] = L.ath[t];
+  for (int t = tid(); t < ns; t += nthr()) ws.dcont[e * ns + t] = L.dcont[t];
+  __syncthreads();
+  // rhs = -r_x - J^T w, w = Ds r_y + r_s (element rows; next element's node-0 rows).
+  // The blocks are stored, so the LDS is reused from its start (size checked at launch).
+  double* w = lds_raw;
+  double* wn = w + b;
+  double* phi = wn + ns;
+  double* outz = phi + S.K * S.nr;
+  double* outth = outz + b;
+  for (int t = tid(); t < b; t += nthr()) w[t] = (sigma_s[gi + t] + dw) * r_y[gi + t] + r_s[gi + t];
+  if (i + 1 < N)
+    for (int t = tid(); t < ns; t += nthr()) wn[t] = (sigma_s[gi + b + t] + dw) * r_y[gi + b + t] + r_s[gi + b + t];
+  __syncthreads();
+  reaction_weights(S, tb, inst, w, phi);
+  __syncthreads();
+  jtu_rows(S, tb, inst, h, ws.jac + e * jl * 3, w, (i + 1 < N) ? wn : nullptr, phi, outz, outth);
+  __syncthreads();
+  for (int t = tid(); t < b; t += nthr()) rhs[xi + t] = -r_x[xi + t] - outz[t];
+  for (int t = tid(); t < np; t += nthr()) ws.rthp[e * np + t] = -outth[t];
+}
+
+// rhs theta part: -r_x(theta) + sum_e partials (fixed order); sigma_x + dw kept for the border.
+__global__ void k_rhs_theta(Shape S, Tab tb, Ws ws, const double* __restrict__ r_x,
+                            const double* __restrict__ sigma_x, const double* __restrict__ delta_w,
+                            double* __restrict__ rhs) {
+  const int inst = blockIdx.x;
+  const int N = tb.inst_N[inst];
+  const int64_t e0 = tb.inst_e0[inst];
+  const int64_t xt = tb.inst_x[inst] + (int64_t)N * S.b;
+  for (int c = tid(); c < S.np; c += nthr()) {
+    double acc = 0.0;
+    for (int i = 0; i < N; ++i) acc += ws.rthp[(e0 + i) * S.np + c];
+    rhs[xt + c] = -r_x[xt + c] + acc;
+    ws.sxdw[inst * S.np + c] = sigma_x[inst * S.np + c] + delta_w[inst];
+  }
+}
+
+// Level 0 of the factorization.  fused = 1: assemble in LDS from ws.jac/hess/Ds/dw first.
+template <typename T>
+__global__ void __launch_bounds__(256) k_level0(Shape S, Tab tb, Ws ws, int fused) {
+  extern __shared__ double lds_raw[];
+  const int64_t e = blockIdx.x;
+  const int inst = tb.elem_inst[e], i = tb.elem_loc[e];
+  const int ns = S.ns, np = S.np, R = S.R, mI = S.mI;
+  if (block_flag(&ws.flag[inst])) return;
+  L0Lds<T> L = l0_carve<T>(S, lds_raw);
+  T* Qg = (T*)ws.panel + e * (int64_t)R * mI;
+  if (fused) {
+    const int64_t jl = (int64_t)S.K * S.nr;
+    const int64_t gi = tb.inst_g[inst] + (int64_t)i * S.b;
+    assemble_element<T>(S, tb, e, inst, i, tb.elem_h[e], ws.jac + e * jl * 3,
+                        ws.hess + e * jl * 4, ws.Ds + gi, ws.dw[inst], L);
+  } else {
+    const T* dssg = (const T*)ws.dss + e * ns * ns;
+    const T* bsg = (const T*)ws.bs + e * ns * np;
+    for (int t = tid(); t < R * mI; t += nthr()) L.Q[t] = Qg[t];
+    for (int t = tid(); t < ns * ns; t += nthr()) L.dss[t] = dssg[t];
+    for (int t = tid(); t < ns * np; t += nthr()) L.bs[t] = bsg[t];
+    for (int t = tid(); t < np * np; t += nthr()) L.ath[t] = ws.ath[e * np * np + t];
+    for (int t = tid(); t < ns; t += nthr()) L.dcont[t] = ws.dcont[e * ns + t];
+    __syncthreads();
+  }
+  bool ok = panel_cholesky<T>(L.Q, R, mI, L.misc);
+  if (!ok) {
+    if (tid() == 0) atomicOr(&ws.flag[inst], 1);
+    return;
+  }
+  level0_outputs<T>(S, ws, e, i, L);
+  for (int t = tid(); t < R * mI; t += nthr()) Qg[t] = L.Q[t];
+}
+
+// ---------------------------------------------------------------- small dense LDS helpers
+// Row-major n x n lower Cholesky in place (FP64 work array), all threads.
+__device__ bool chol_small(double* A, int n, double* misc) {
+  for (int c = 0; c < n; ++c) {
+    if (tid() == 0) {
+      double piv = A[c * n + c];
+      bool ok = piv > 0.0 && isfinite(piv);
+      double sq = ok ? sqrt(piv) : 1.0;
+      A[c * n + c] = sq;
+      misc[0] = ok ? 1.0 : 0.0;
+      misc[1] = 1.0 / sq;
+    }
+    __syncthreads();
+    if (misc[0] == 0.0) return false;
+    double inv = misc[1];
+    for (int r = c + 1 + tid(); r < n; r += nthr()) A[r * n + c] *= inv;
+    __syncthreads();
+    const int m = n - c - 1;
+    for (int t = tid(); t < m * m; t += nthr()) {
+      int r = c + 1 + t / m, q = c + 1 + t % m;
+      if (q <= r) A[r * n + q] -= A[r * n + c] * A[q * n + c];
+    }
+    __syncthreads();
+  }
+  // zero the strict upper triangle
+  for (int t = tid(); t < n * n; t += nthr()) {
+    int r = t / n, q = t % n;
+    if (q > r) A[t] = 0.0;
+  }
+  __syncthreads();
+  return true;
+}
+
+// B (n x m, row-major, ld m) <- L^{-1} B; one thread per column.
+__device__ void trsm_l(const double* Lm, int n, double* B, int m) {
+  for (int col = tid(); col < m; col += nthr()) {
+    for (int r = 0; r < n; ++r) {
+      double v = B[r * m + col];
+      for (int q = 0; q < r; ++q) v -= Lm[r * n + q] * B[q * m + col];
+      B[r * m + col] = v / Lm[r * n + r];
+    }
+  }
+}
+// x <- L^{-1} x (single thread; n small)
+__device__ void trsv_l_seq(const double* Lm, int n, double* x) {
+  for (int r = 0; r < n; ++r) {
+    double v = x[r];
+    for (int q = 0; q < r; ++q) v -= Lm[r * n + q] * x[q];
+    x[r] = v / Lm[r * n + r];
+  }
+}
+// x <- L^{-T} x (single thread)
+__device__ void trsv_lt_seq(const double* Lm, int n, double* x) {
+  for (int r = n - 1; r >= 0; --r) {
+    double v = x[r];
+    for (int q = r + 1; q < n; ++q) v -= Lm[q * n + r] * x[q];
+    x[r] = v / Lm[r * n + r];
+  }
+}
+
+template <typename T>
+__device__ inline void load_blk(double* dst, const T* src, int n) {
+  for (int t = tid(); t < n; t += nthr()) dst[t] = (double)src[t];
+}
+template <typename T>
+__device__ inline void store_blk(T* dst, const double* src, int n) {
+  for (int t = tid(); t < n; t += nthr()) dst[t] = (T)src[t];
+}
+
+// C (n x m) -= A^T B, A: k x n, B: k x m (row-major, from global T); lower only if sym.
+template <typename T>
+__device__ void sub_atb(double* C, int n, int m, const T* A, const T* B, int k, bool sym) {
+  for (int t = tid(); t < n * m; t += nthr()) {
+    int r = t / m, q = t % m;
+    if (sym && q > r) continue;
+    double acc = 0.0;
+    for (int p = 0; p < k; ++p) acc += (double)A[p * n + r] * (double)B[p * m + q];
+    C[t] -= acc;
+  }
+}
+
+// ---------------------------------------------------------------- cyclic reduction levels
+// Gather the current separator block T_j (lower, full rows), its border G_j and, when rhs is
+// given, its right-hand side, applying the updates of every level below `level`.
+template <typename T>
+__device__ void gather_sep(const Shape& S, const Tab& tb, const Ws& ws, int64_t e0, int N, int j,
+                           int level, double* Tm, double* G) {
+  const int ns = S.ns, np = S.np;
+  const int64_t ej = e0 + j;
+  load_blk(Tm, (const T*)ws.dss + ej * ns * ns, ns * ns);
+  load_blk(G, (const T*)ws.bs + ej * ns * np, ns * np);
+  __syncthreads();
+  if (j + 1 < N) {
+    const T* tp = (const T*)ws.tprev + (ej + 1) * ns * ns;
+    const T* gp = (const T*)ws.gprev + (ej + 1) * ns * np;
+    for (int t = tid(); t < ns * ns; t += nthr()) Tm[t] += (double)tp[t];
+    for (int t = tid(); t < ns * np; t += nthr()) G[t] += (double)gp[t];
+  }
+  __syncthreads();
+  for (int lp = 1; lp < level; ++lp) {
+    int hh = 1 << (lp - 1);
+    int jl = j - hh;
+    if (jl >= 0) {
+      const T* U = (const T*)ws.ur + (e0 + jl) * ns * ns;
+      sub_atb(Tm, ns, ns, U, U, ns, true);
+      sub_atb(G, ns, np, U, (const T*)ws.ub + (e0 + jl) * ns * np, ns, false);
+    }
+    int jr = j + hh;
+    if (jr < N) {
+      const T* U = (const T*)ws.ul + (e0 + jr) * ns * ns;
+      sub_atb(Tm, ns, ns, U, U, ns, true);
+      sub_atb(G, ns, np, U, (const T*)ws.ub + (e0 + jr) * ns * np, ns, false);
+    }
+    __syncthreads();
+  }
+}
+
+// Coupling block (row hi, col lo) between separators lo < hi adjacent at `level`.
+template <typename T>
+__device__ void coupling(const Shape& S, const Ws& ws, int64_t e0, int lo, int hi, int level,
+                         double* E) {
+  const int ns = S.ns;
+  if (level == 1) {
+    load_blk(E, (const T*)ws.e1 + (e0 + hi) * ns * ns, ns * ns);
+  } else {
+    int jm = lo + (1 << (level - 2));
+    const T* UR = (const T*)ws.ur + (e0 + jm) * ns * ns;
+    const T* UL = (const T*)ws.ul + (e0 + jm) * ns * ns;
+    for (int t = tid(); t < ns * ns; t += nthr()) {
+      int r = t / ns, q = t % ns;
+      double acc = 0.0;
+      for (int p = 0; p < ns; ++p) acc += (double)UR[p * ns + r] * (double)UL[p * ns + q];
+      E[t] = -acc;
+    }
+  }
+}
+
+// Theta-theta contribution -U_B^T U_B of an eliminated separator, stored as a full lower block.
+template <typename T>
+__device__ void theta_part(const Shape& S, const T* UB, double* out) {
+  const int ns = S.ns, np = S.np;
+  for (int t = tid(); t < np * np; t += nthr()) {
+    int r = t / np, q = t % np;
+    if (q > r) continue;
+    double acc = 0.0;
+    for (int p = 0; p < ns; ++p) acc += (double)UB[p * np + r] * (double)UB[p * np + q];
+    out[t] = -acc;
+  }
+}
+
+// LDS: Tm (ns^2) G (ns np) EL (ns^2) ER (ns^2) misc
+template <typename T>
+__global__ void k_cr(Shape S, Tab tb, Ws ws, int level) {
+  extern __shared__ double lds[];
+  const int it = tb.cr_ptr[level - 1] + blockIdx.x;
+  if (it >= tb.cr_ptr[level]) return;
+  const int inst = tb.cr_inst[it], j = tb.cr_j[it];
+  if (block_flag(&ws.flag[inst])) return;
+  const int ns = S.ns, np = S.np;
+  const int N = tb.inst_N[inst];
+  const int64_t e0 = tb.inst_e0[inst], ej = e0 + j;
+  double* Tm = lds;
+  double* G = Tm + ns * ns;
+  double* EL = G + ns * np;
+  double* ER = EL + ns * ns;
+  double* misc = ER + ns * ns;
+  const int half = 1 << (level - 1);
+  gather_sep<T>(S, tb, ws, e0, N, j, level, Tm, G);
+  coupling<T>(S, ws, e0, j - half, j, level, EL);
+  const bool has_r = j + half < N;
+  if (has_r) coupling<T>(S, ws, e0, j, j + half, level, ER);
+  __syncthreads();
+  if (!chol_small(Tm, ns, misc)) {
+    if (tid() == 0) atomicOr(&ws.flag[inst], 1);
+    return;
+  }
+  // UL = L^{-1} EL ; UR = L^{-1} ER^T ; UB = L^{-1} G
+  if (has_r) {
+    // transpose ER in place into EL's neighbour buffer: use misc-free swap through G? keep ER^T
+    for (int t = tid(); t < ns * ns; t += nthr()) {
+      int r = t / ns, q = t % ns;
+      if (q > r) {
+        double a = ER[r * ns + q], bb = ER[q * ns + r];
+        ER[r * ns + q] = bb;
+        ER[q * ns + r] = a;
+      }
+    }
+  } else {
+    for (int t = tid(); t < ns * ns; t += nthr()) ER[t] = 0.0;
+  }
+  __syncthreads();
+  trsm_l(Tm, ns, EL, ns);
+  trsm_l(Tm, ns, ER, ns);
+  trsm_l(Tm, ns, G, np);
+  __syncthreads();
+  store_blk((T*)ws.lsep + ej * ns * ns, Tm, ns * ns);
+  store_blk((T*)ws.ul + ej * ns * ns, EL, ns * ns);
+  store_blk((T*)ws.ur + ej * ns * ns, ER, ns * ns);
+  store_blk((T*)ws.ub + ej * ns * np, G, ns * np);
+  __syncthreads();
+  theta_part<T>(S, (const T*)ws.ub + ej * ns * np, ws.thcr + ej * np * np);
+}
+
+// Theta-theta reduction, stage 1: instance blockIdx.y, chunk blockIdx.x of its elements;
+// partial = sum over the chunk of (element Schur part + separator part), lower triangle.
+__global__ void k_thred(Shape S, Tab tb, Ws ws) {
+  const int inst = blockIdx.y, chunk = blockIdx.x;
+  if (block_flag(&ws.flag[inst])) return;
+  const int np = S.np, N = tb.inst_N[inst];
+  const int64_t e0 = tb.inst_e0[inst];
+  const int i0 = chunk * CL_THCHUNK, i1 = min(N, i0 + CL_THCHUNK);
+  if (i0 >= N) return;
+  double* out = ws.thred + ((int64_t)inst * ws.nchunk + chunk) * np * np;
+  for (int t = tid(); t < np * np; t += nthr()) {
+    int r = t / np, q = t % np;
+    if (q > r) continue;
+    double acc = 0.0;
+    for (int i = i0; i < i1; ++i) {
+      acc += ws.ath[(e0 + i) * np * np + t];
+      if (i > 0) acc += ws.thcr[(e0 + i) * np * np + t];
+    }
+    out[t] = acc;
+  }
+}
+
+// Border: eliminate separator 0, form the parameter Schur complement, factor it.
+// LDS: Tm (ns^2) G (ns np) Sm (np^2) misc
+template <typename T>
+__global__ void k_border(Shape S, Tab tb, Ws ws) {
+  extern __shared__ double lds[];
+  const int inst = blockIdx.x;
+  if (block_flag(&ws.flag[inst])) return;
+  const int ns = S.ns, np = S.np, N = tb.inst_N[inst];
+  const int64_t e0 = tb.inst_e0[inst];
+  double* Tm = lds;
+  double* G = Tm + ns * ns;
+  double* Sm = G + ns * np;
+  double* misc = Sm + np * np;
+  gather_sep<T>(S, tb, ws, e0, N, 0, tb.L + 1, Tm, G);
+  for (int t = tid(); t < np * np; t += nthr()) {
+    int r = t / np, q = t % np;
+    double acc = 0.0;
+    const int nch = (int)cl_ceil_div(N, CL_THCHUNK);
+    if (q <= r)
+      for (int c = 0; c < nch; ++c) acc += ws.thred[((int64_t)inst * ws.nchunk + c) * np * np + t];
+    Sm[t] = acc + (r == q ? ws.sxdw[inst * np + r] : 0.0);
+  }
+  __syncthreads();
+  if (!chol_small(Tm, ns, misc)) {
+    if (tid() == 0) atomicOr(&ws.flag[inst], 1);
+    return;
+  }
+  trsm_l(Tm, ns, G, np);
+  __syncthreads();
+  store_blk((T*)ws.lsep + e0 * ns * ns, Tm, ns * ns);
+  store_blk((T*)ws.ub + e0 * ns * np, G, ns * np);
+  for (int t = tid(); t < np * np; t += nthr()) {
+    int r = t / np, q = t % np;
+    if (q > r) continue;
+    double acc = 0.0;
+    for (int p = 0; p < ns; ++p) acc += G[p * np + r] * G[p * np + q];
+    Sm[t] -= acc;
+  }
+  __syncthreads();
+  if (!chol_small(Sm, np, misc)) {
+    if (tid() == 0) atomicOr(&ws.flag[inst], 1);
+    return;
+  }
+  for (int t = tid(); t < np * np; t += nthr()) ws.S[(int64_t)inst * np * np + t] = Sm[t];
+}
+
+__global__ void k_clear_flags(Ws ws, int n) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) ws.flag[t] = 0;
+}
+__global__ void k_copy_flags(Ws ws, int* info, int n) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) info[t] = ws.flag[t];
+}
+
+// ---------------------------------------------------------------- solve
+// Level-0 forward: y_I = L_I^{-1} r_I and the tail contributions X^T y_I.
+// LDS: y (mI) + Lpanel not cached (read from global, column-major)
+template <typename T>
+__global__ void k_l0_fwd(Shape S, Tab tb, Ws ws, const double* __restrict__ rhs) {
+  extern __shared__ double lds[];
+  const int64_t e = blockIdx.x;
+  const int inst = tb.elem_inst[e], i = tb.elem_loc[e];
+  if (block_flag(&ws.flag[inst])) return;
+  const int ns = S.ns, np = S.np, R = S.R, mI = S.mI;
+  const T* Q = (const T*)ws.panel + e * (int64_t)R * mI;
+  double* y = lds;
+  const double* r = rhs + tb.inst_x[inst] + (int64_t)i * S.b;
+  for (int t = tid(); t < mI; t += nthr()) y[t] = r[t];
+  __syncthreads();
+  for (int c = 0; c < mI; ++c) {
+    if (tid() == 0) y[c] /= (double)Q[c * R + c];
+    __syncthreads();
+    double yc = y[c];
+    for (int t = c + 1 + tid(); t < mI; t += nthr()) y[t] -= (double)Q[c * R + t] * yc;
+    __syncthreads();
+  }
+  for (int t = tid(); t < mI; t += nthr()) ws.yI[e * mI + t] = y[t];
+  for (int a = tid(); a < S.Rt; a += nthr()) {
+    double acc = 0.0;
+    for (int k = 0; k < mI; ++k) acc += (double)Q[k * R + mI + a] * y[k];
+    if (a < ns) ws.cS[e * ns + a] = acc;
+    else if (a < 2 * ns) ws.cP[e * ns + (a - ns)] = (i > 0) ? acc : 0.0;
+    else ws.cB[e * np + (a - 2 * ns)] = acc;
+  }
+}
+
+// Right-hand side of separator j at `level` (all updates from levels below).
+template <typename T>
+__device__ void gather_rhs(const Shape& S, const Tab& tb, const Ws& ws, int64_t e0, int64_t xoff,
+                           int N, int j, int level, const double* rhs, double* r) {
+  const int ns = S.ns;
+  const int64_t ej = e0 + j;
+  for (int a = tid(); a < ns; a += nthr()) {
+    double v = rhs[xoff + (int64_t)j * S.b + S.mI + a] - ws.cS[ej * ns + a];
+    if (j + 1 < N) v -= ws.cP[(ej + 1) * ns + a];
+    for (int lp = 1; lp < level; ++lp) {
+      int hh = 1 << (lp - 1);
+      int jl = j - hh, jr = j + hh;
+      if (jl >= 0) {
+        const T* U = (const T*)ws.ur + (e0 + jl) * ns * ns;
+        const double* yv = ws.ysep + (e0 + jl) * ns;
+        for (int p = 0; p < ns; ++p) v -= (double)U[p * ns + a] * yv[p];
+      }
+      if (jr < N) {
+        const T* U = (const T*)ws.ul + (e0 + jr) * ns * ns;
+        const double* yv = ws.ysep + (e0 + jr) * ns;
+        for (int p = 0; p < ns; ++p) v -= (double)U[p * ns + a] * yv[p];
+      }
+    }
+    r[a] = v;
+  }
+}
+
+// LDS: Lm (ns^2) r (ns)
+template <typename T>
+__global__ void k_cr_fwd(Shape S, Tab tb, Ws ws, const double* __restrict__ rhs, int level) {
+  extern __shared__ double lds[];
+  const int it = tb.cr_ptr[level - 1] + blockIdx.x;
+  if (it >= tb.cr_ptr[level]) return;
+  const int inst = tb.cr_inst[it], j = tb.cr_j[it];
+  if (block_flag(&ws.flag[inst])) return;
+  const int ns = S.ns, np = S.np, N = tb.inst_N[inst];
+  const int64_t e0 = tb.inst_e0[inst], ej = e0 + j;
+  double* Lm = lds;
+  double* r = Lm + ns * ns;
+  load_blk(Lm, (const T*)ws.lsep + ej * ns * ns, ns * ns);
+  gather_rhs<T>(S, tb, ws, e0, tb.inst_x[inst], N, j, level, rhs, r);
+  __syncthreads();
+  if (tid() == 0) trsv_l_seq(Lm, ns, r);
+  __syncthreads();
+  for (int t = tid(); t < ns; t += nthr()) ws.ysep[ej * ns + t] = r[t];
+  const T* UB = (const T*)ws.ub + ej * ns * np;
+  for (int c = tid(); c < np; c += nthr()) {
+    double acc = 0.0;
+    for (int p = 0; p < ns; ++p) acc += (double)UB[p * np + c] * r[p];
+    ws.cBsep[ej * np + c] = acc;
+  }
+}
+
+// Border solve: separator 0, theta, back to separator 0.  LDS: Lm (ns^2) r (ns) rt (np) Sm.
+template <typename T>
+__global__ void k_border_solve(Shape S, Tab tb, Ws ws, const double* __restrict__ rhs,
+                               const double* __restrict__ rthp, double* __restrict__ dx) {
+  extern __shared__ double lds[];
+  __shared__ double red[256];
+  const int inst = blockIdx.x;
+  if (block_flag(&ws.flag[inst])) return;
+  const int ns = S.ns, np = S.np, N = tb.inst_N[inst];
+  const int64_t e0 = tb.inst_e0[inst];
+  const int64_t xoff = tb.inst_x[inst];
+  double* Lm = lds;
+  double* r = Lm + ns * ns;
+  double* rt = r + ns;
+  double* Sm = rt + np;
+  load_blk(Lm, (const T*)ws.lsep + e0 * ns * ns, ns * ns);
+  for (int t = tid(); t < np * np; t += nthr()) Sm[t] = ws.S[(int64_t)inst * np * np + t];
+  gather_rhs<T>(S, tb, ws, e0, xoff, N, 0, tb.L + 1, rhs, r);
+  __syncthreads();
+  if (tid() == 0) trsv_l_seq(Lm, ns, r);
+  // theta right-hand side: rhs - sum cB - sum cBsep - UB0^T y0  (fixed order per parameter)
+  const T* UB0 = (const T*)ws.ub + e0 * ns * np;
+  __syncthreads();
+  for (int c = 0; c < np; ++c) {
+    double acc = 0.0;
+    for (int i = tid(); i < N; i += nthr()) {
+      acc += ws.cB[(e0 + i) * np + c];
+      if (i > 0) acc += ws.cBsep[(e0 + i) * np + c];
+      if (rthp) acc -= rthp[(e0 + i) * np + c];
+    }
+    acc = block_sum(acc, red);
+    if (tid() == 0) {
+      double u = 0.0;
+      for (int p = 0; p < ns; ++p) u += (double)UB0[p * np + c] * r[p];
+      rt[c] = rhs[xoff + (int64_t)N * S.b + c] - acc - u;
+    }
+  }
+  __syncthreads();
+  if (tid() == 0) {
+    trsv_l_seq(Sm, np, rt);
+    trsv_lt_seq(Sm, np, rt);
+    // x_0 = L0^{-T} (y0 - UB0 x_theta)
+    for (int a = 0; a < ns; ++a) {
+      double v = r[a];
+      for (int c = 0; c < np; ++c) v -= (double)UB0[a * np + c] * rt[c];
+      r[a] = v;
+    }
+    trsv_lt_seq(Lm, ns, r);
+  }
+  __syncthreads();
+  for (int c = tid(); c < np; c += nthr()) {
+    ws.xth[inst * np + c] = rt[c];
+    dx[xoff + (int64_t)N * S.b + c] = rt[c];
+  }
+  for (int a = tid(); a < ns; a += nthr()) ws.xsep[e0 * ns + a] = r[a];
+}
+
+template <typename T>
+__global__ void k_cr_bwd(Shape S, Tab tb, Ws ws, int level) {
+  extern __shared__ double lds[];
+  const int it = tb.cr_ptr[level - 1] + blockIdx.x;
+  if (it >= tb.cr_ptr[level]) return;
+  const int inst = tb.cr_inst[it], j = tb.cr_j[it];
+  if (block_flag(&ws.flag[inst])) return;
+  const int ns = S.ns, np = S.np, N = tb.inst_N[inst];
+  const int64_t e0 = tb.inst_e0[inst], ej = e0 + j;
+  const int half = 1 << (level - 1);
+  double* Lm = lds;
+  double* r = Lm + ns * ns;
+  load_blk(Lm, (const T*)ws.lsep + ej * ns * ns, ns * ns);
+  for (int a = tid(); a < ns; a += nthr()) {
+    double v = ws.ysep[ej * ns + a];
+    const T* UL = (const T*)ws.ul + ej * ns * ns;
+    const T* UR = (const T*)ws.ur + ej * ns * ns;
+    const T* UB = (const T*)ws.ub + ej * ns * np;
+    const double* xl = ws.xsep + (e0 + j - half) * ns;
+    for (int q = 0; q < ns; ++q) v -= (double)UL[a * ns + q] * xl[q];
+    if (j + half < N) {
+      const double* xr = ws.xsep + (e0 + j + half) * ns;
+      for (int q = 0; q < ns; ++q) v -= (double)UR[a * ns + q] * xr[q];
+    }
+    const double* xt = ws.xth + inst * np;
+    for (int c = 0; c < np; ++c) v -= (double)UB[a * np + c] * xt[c];
+    r[a] = v;
+  }
+  __syncthreads();
+  if (tid() == 0) trsv_lt_seq(Lm, ns, r);
+  __syncthreads();
+  for (int a = tid(); a < ns; a += nthr()) ws.xsep[ej * ns + a] = r[a];
+}
+
+// Level-0 backward: x_I = L_I^{-T} (y_I - X_S x_S(i) - X_P x_S(i-1) - X_B x_theta); writes dx.
+// LDS: t (mI) + xs (ns) + xp (ns) + xt (np)
+template <typename T>
+__global__ void k_l0_bwd(Shape S, Tab tb, Ws ws, double* __restrict__ dx) {
+  extern __shared__ double lds[];
+  const int64_t e = blockIdx.x;
+  const int inst = tb.elem_inst[e], i = tb.elem_loc[e];
+  if (block_flag(&ws.flag[inst])) return;
+  const int ns = S.ns, np = S.np, R = S.R, mI = S.mI;
+  const T* Q = (const T*)ws.panel + e * (int64_t)R * mI;
+  double* tv = lds;
+  double* xs = tv + mI;
+  double* xp = xs + ns;
+  double* xt = xp + ns;
+  for (int a = tid(); a < ns; a += nthr()) {
+    xs[a] = ws.xsep[e * ns + a];
+    xp[a] = i > 0 ? ws.xsep[(e - 1) * ns + a] : 0.0;
+  }
+  for (int c = tid(); c < np; c += nthr()) xt[c] = ws.xth[inst * np + c];
+  __syncthreads();
+  for (int k = tid(); k < mI; k += nthr()) {
+    double v = ws.yI[e * mI + k];
+    const T* col = Q + k * R + mI;
+    for (int a = 0; a < ns; ++a) v -= (double)col[a] * xs[a];
+    if (i > 0)
+      for (int a = 0; a < ns; ++a) v -= (double)col[ns + a] * xp[a];
+    for (int c = 0; c < np; ++c) v -= (double)col[2 * ns + c] * xt[c];
+    tv[k] = v;
+  }
+  __syncthreads();
+  // backward substitution with L^T, column oriented: x_c = t_c / L_cc; t_r -= L_cr x_c (r < c)
+  for (int c = mI - 1; c >= 0; --c) {
+    if (tid() == 0) tv[c] /= (double)Q[c * R + c];
+    __syncthreads();
+    double xc = tv[c];
+    for (int r = tid(); r < c; r += nthr()) tv[r] -= (double)Q[r * R + c] * xc;
+    __syncthreads();
+  }
+  double* out = dx + tb.inst_x[inst] + (int64_t)i * S.b;
+  for (int k = tid(); k < mI; k += nthr()) out[k] = tv[k];
+  for (int a = tid(); a < ns; a += nthr()) out[mI + a] = xs[a];
+}
+
+// ---------------------------------------------------------------- matrix-free K v (FP64)
+// u = Ds (J v) for the element's rows.  LDS: v (b) vp (ns) vt (np) out (b)
+__global__ void k_mv1(Shape S, Tab tb, Ws ws, const double* __restrict__ v, double* __restrict__ u) {
+  extern __shared__ double lds[];
+  const int64_t e = blockIdx.x;
+  const int inst = tb.elem_inst[e], i = tb.elem_loc[e];
+  const int N = tb.inst_N[inst];
+  const int b = S.b, ns = S.ns, np = S.np;
+  const double* vb = v + tb.inst_x[inst];
+  double* vl = lds;
+  double* vp = vl + b;
+  double* vt = vp + ns;
+  double* o = vt + np;
+  for (int t = tid(); t < b; t += nthr()) vl[t] = vb[(int64_t)i * b + t];
+  if (i > 0)
+    for (int t = tid(); t < ns; t += nthr()) vp[t] = vb[(int64_t)(i - 1) * b + S.K * ns + t];
+  for (int t = tid(); t < np; t += nthr()) vt[t] = vb[(int64_t)N * b + t];
+  __syncthreads();
+  const int64_t jl = (int64_t)S.K * S.nr;
+  jv_rows(S, tb, inst, i, tb.elem_h[e], ws.jac + e * jl * 3, vl, vp, vt, o);
+  const int64_t gi = tb.inst_g[inst] + (int64_t)i * b;
+  __syncthreads();
+  for (int t = tid(); t < b; t += nthr()) u[gi + t] = ws.Ds[gi + t] * o[t];
+}
+
+// out_z = J^T u + W v + dw v ; theta partials to ws.rthp.  LDS: u (b) un (ns) phi (K nr)
+// v (b) vt (np) oz (b) ot (np) wz (b) wt (np)
+__global__ void k_mv2(Shape S, Tab tb, Ws ws, const double* __restrict__ v,
+                      const double* __restrict__ u, double* __restrict__ out) {
+  extern __shared__ double lds[];
+  const int64_t e = blockIdx.x;
+  const int inst = tb.elem_inst[e], i = tb.elem_loc[e];
+  const int N = tb.inst_N[inst];
+  const int b = S.b, ns = S.ns, np = S.np;
+  double* ul = lds;
+  double* un = ul + b;
+  double* phi = un + ns;
+  double* vl = phi + S.K * S.nr;
+  double* vt = vl + b;
+  double* oz = vt + np;
+  double* ot = oz + b;
+  double* wz = ot + np;
+  double* wt = wz + b;
+  const int64_t gi = tb.inst_g[inst] + (int64_t)i * b;
+  const double* vb = v + tb.inst_x[inst];
+  for (int t = tid(); t < b; t += nthr()) {
+    ul[t] = u[gi + t];
+    vl[t] = vb[(int64_t)i * b + t];
+  }
+  if (i + 1 < N)
+    for (int t = tid(); t < ns; t += nthr()) un[t] = u[gi + b + t];
+  for (int t = tid(); t < np; t += nthr()) vt[t] = vb[(int64_t)N * b + t];
+  __syncthreads();
+  reaction_weights(S, tb, inst, ul, phi);
+  __syncthreads();
+  const int64_t jl = (int64_t)S.K * S.nr;
+  const double h = tb.elem_h[e];
+  jtu_rows(S, tb, inst, h, ws.jac + e * jl * 3, ul, (i + 1 < N) ? un : nullptr, phi, oz, ot);
+  wv_rows(S, tb, inst, e, ws.hess + e * jl * 4, vl, vt, wz, wt);
+  __syncthreads();
+  const double dw = ws.dw[inst];
+  double* ob = out + tb.inst_x[inst] + (int64_t)i * b;
+  for (int t = tid(); t < b; t += nthr()) ob[t] = oz[t] + wz[t] + dw * vl[t];
+  for (int t = tid(); t < np; t += nthr()) ws.rthp[e * np + t] = ot[t] + wt[t];
+}
+
+__global__ void k_mv3(Shape S, Tab tb, Ws ws, const double* __restrict__ v, double* __restrict__ out) {
+  const int inst = blockIdx.x;
+  const int N = tb.inst_N[inst];
+  const int64_t e0 = tb.inst_e0[inst];
+  const int64_t xt = tb.inst_x[inst] + (int64_t)N * S.b;
+  for (int c = tid(); c < S.np; c += nthr()) {
+    double acc = 0.0;
+    for (int i = 0; i < N; ++i) acc += ws.rthp[(e0 + i) * S.np + c];
+    out[xt + c] = acc + ws.sxdw[inst * S.np + c] * v[xt + c];
+  }
+}
+
+// ---------------------------------------------------------------- launches
+static inline int ok_or() { return hipGetLastError() == hipSuccess ? 0 : -3; }
+
+int launch_assemble(const Shape& S, const Tab& tb, const Ws& ws, const double* jac,
+                    const double* hess, const double* sigma_x, const double* sigma_s,
+                    const double* delta_w, const double* r_x, const double* r_s,
+                    const double* r_y, double* rhs, hipStream_t st) {
+  int nt = elem_threads(S);
+  size_t lds = level0_lds_bytes(S, ws.prec);
+  size_t lds_rhs = sizeof(double) * (2 * S.b + S.ns + S.K * S.nr + S.np);
+  if (lds_rhs > lds) lds = lds_rhs;
+  if (ws.prec)
+    hipLaunchKernelGGL(k_assemble<float>, dim3((unsigned)tb.n_elem), dim3(nt), lds, st, S, tb, ws,
+                       jac, hess, sigma_s, delta_w, r_x, r_s, r_y, rhs);
+  else
+    hipLaunchKernelGGL(k_assemble<double>, dim3((unsigned)tb.n_elem), dim3(nt), lds, st, S, tb, ws,
+                       jac, hess, sigma_s, delta_w, r_x, r_s, r_y, rhs);
+  hipLaunchKernelGGL(k_rhs_theta, dim3(tb.n_inst), dim3(64), 0, st, S, tb, ws, r_x, sigma_x,
+                     delta_w, rhs);
+  return ok_or();
+}
+
+template <typename T>
+static int factor_t(const Shape& S, const Tab& tb, const HostPlan& hp, const Ws& ws, bool fused,
+                    phase_cb cb, void* ctx, hipStream_t st) {
+  int nt = elem_threads(S);
+  size_t lds = level0_lds_bytes(S, sizeof(T) == 4);
+  if (cb) cb(ctx, 1, 1, st);
+  hipLaunchKernelGGL(k_level0<T>, dim3((unsigned)tb.n_elem), dim3(nt), lds, st, S, tb, ws, fused ? 1 : 0);
+  if (cb) cb(ctx, 1, 0, st);
+  int snt = sep_threads(S);
+  size_t clds = sizeof(double) * (3 * S.ns * S.ns + S.ns * S.np + 8);
+  if (cb) cb(ctx, 2, 1, st);
+  for (int l = 1; l <= tb.L; ++l) {
+    int n = hp.lvl[l];
+    if (n > 0) hipLaunchKernelGGL(k_cr<T>, dim3(n), dim3(snt), clds, st, S, tb, ws, l);
+  }
+  if (cb) cb(ctx, 2, 0, st);
+  if (cb) cb(ctx, 3, 1, st);
+  hipLaunchKernelGGL(k_thred, dim3(ws.nchunk, tb.n_inst), dim3(snt), 0, st, S, tb, ws);
+  size_t blds = sizeof(double) * (S.ns * S.ns + S.ns * S.np + S.np * S.np + 8);
+  hipLaunchKernelGGL(k_border<T>, dim3(tb.n_inst), dim3(snt), blds, st, S, tb, ws);
+  if (cb) cb(ctx, 3, 0, st);
+  return ok_or();
+}
+
+int launch_factor_nc(const Shape& S, const Tab& tb, const HostPlan& hp, const Ws& ws, int prec,
+                     bool fused, phase_cb cb, void* ctx, hipStream_t st) {
+  return prec ? factor_t<float>(S, tb, hp, ws, fused, cb, ctx, st)
+              : factor_t<double>(S, tb, hp, ws, fused, cb, ctx, st);
+}
+
+int launch_factor(const Shape& S, const Tab& tb, const HostPlan& hp, const Ws& ws, int prec,
+                  bool fused, phase_cb cb, void* ctx, hipStream_t st) {
+  hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(256), 0, st, ws, tb.n_inst);
+  return launch_factor_nc(S, tb, hp, ws, prec, fused, cb, ctx, st);
+}
+
+template <typename T>
+static int solve_t(const Shape& S, const Tab& tb, const HostPlan& hp, const Ws& ws,
+                   const double* rhs, const double* rthp, double* dx, phase_cb cb, void* ctx,
+                   hipStream_t st) {
+  int nt = elem_threads(S);
+  int snt = sep_threads(S);
+  if (cb) cb(ctx, 4, 1, st);
+  hipLaunchKernelGGL(k_l0_fwd<T>, dim3((unsigned)tb.n_elem), dim3(nt), sizeof(double) * S.mI, st,
+                     S, tb, ws, rhs);
+  size_t clds = sizeof(double) * (S.ns * S.ns + S.ns);
+  for (int l = 1; l <= tb.L; ++l) {
+    int n = hp.lvl[l];
+    if (n > 0) hipLaunchKernelGGL(k_cr_fwd<T>, dim3(n), dim3(snt), clds, st, S, tb, ws, rhs, l);
+  }
+  size_t blds = sizeof(double) * (S.ns * S.ns + S.ns + S.np + S.np * S.np);
+  hipLaunchKernelGGL(k_border_solve<T>, dim3(tb.n_inst), dim3(256), blds, st, S, tb, ws, rhs,
+                     rthp, dx);
+  for (int l = tb.L; l >= 1; --l) {
+    int n = hp.lvl[l];
+    if (n > 0) hipLaunchKernelGGL(k_cr_bwd<T>, dim3(n), dim3(snt), clds, st, S, tb, ws, l);
+  }
+  hipLaunchKernelGGL(k_l0_bwd<T>, dim3((unsigned)tb.n_elem), dim3(nt),
+                     sizeof(double) * (S.mI + 2 * S.ns + S.np), st, S, tb, ws, dx);
+  if (cb) cb(ctx, 4, 0, st);
+  return ok_or();
+}
+
+int launch_solve_p(const Shape& S, const Tab& tb, const HostPlan& hp, const Ws& ws,
+                   const double* rhs, const double* rthp, double* dx, phase_cb cb, void* ctx,
+                   hipStream_t st) {
+  return ws.prec ? solve_t<float>(S, tb, hp, ws, rhs, rthp, dx, cb, ctx, st)
+                 : solve_t<double>(S, tb, hp, ws, rhs, rthp, dx, cb, ctx, st);
+}
+
+int launch_matvec(const Shape& S, const Tab& tb, const Ws& ws, const double* v, double* out,
+                  hipStream_t st) {
+  int nt = elem_threads(S);
+  hipLaunchKernelGGL(k_mv1, dim3((unsigned)tb.n_elem), dim3(nt),
+                     sizeof(double) * (2 * S.b + S.ns + S.np), st, S, tb, ws, v, ws.vtmp2);
+  hipLaunchKernelGGL(k_mv2, dim3((unsigned)tb.n_elem), dim3(nt),
+                     sizeof(double) * (4 * S.b + S.ns + S.K * S.nr + 3 * S.np), st, S, tb, ws, v,
+                     ws.vtmp2, out);
+  hipLaunchKernelGGL(k_mv3, dim3(tb.n_inst), dim3(64), 0, st, S, tb, ws, v, out);
+  return ok_or();
+}
+
+int launch_copy_flags(const Tab& tb, const Ws& ws, int* info, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy_flags, dim3(1), dim3(256), 0, st, ws, info, tb.n_inst);
+  return ok_or();
+}
+
+}  // namespace cl
+
+namespace cl {
+// Dynamic LDS above the default limit must be declared per kernel: request exactly what this
+// shape class needs (static LDS of the kernel comes on top), bounded by the device's limit.
+static int set_lds(const void* fn, size_t bytes, const char* name) {
+  if (bytes <= 64 * 1024) return 0;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) {
+    if (getenv("COLLOC_DEBUG"))
+      fprintf(stderr, "colloc: hipFuncSetAttribute(%s, %zu) -> %s\n", name, bytes, hipGetErrorString(e));
+    return -1;
+  }
+  return 0;
+}
+
+int kkt_prepare_attrs(const Shape& S) {
+  size_t l64 = level0_lds_bytes(S, 0), l32 = level0_lds_bytes(S, 1);
+  size_t r = sizeof(double) * (2 * S.b + S.ns + S.K * S.nr + S.np);
+  int rc = 0;
+  rc |= set_lds((const void*)k_level0<double>, l64, "k_level0<double>");
+  rc |= set_lds((const void*)k_level0<float>, l32, "k_level0<float>");
+  rc |= set_lds((const void*)k_assemble<double>, l64 > r ? l64 : r, "k_assemble<double>");
+  rc |= set_lds((const void*)k_assemble<float>, l32 > r ? l32 : r, "k_assemble<float>");
+  return rc;
+}
+}  // namespace cl

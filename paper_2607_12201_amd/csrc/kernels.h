@@ -1,0 +1,52 @@
+// Host-side launch wrappers of the gfx950 kernels (defined in the k_*.hip files).
+#pragma once
+#include "common.h"
+
+namespace cl {
+
+// Host copy of the static work-list sizes (grid sizes of the cyclic-reduction levels).
+struct HostPlan {
+  int L;
+  int lvl[64];   // lvl[l] = work items at level l (1..L)
+};
+
+// Workgroup size of the per-element kernels: one wave for tiny elements, four otherwise.
+inline int elem_threads(const Shape& S) {
+  int w = S.b + S.np;
+  return w <= 32 ? 64 : (w <= 96 ? 128 : 256);
+}
+inline int sep_threads(const Shape& S) {
+  int w = S.ns > S.np ? S.ns : S.np;
+  return w <= 64 ? 64 : 128;
+}
+
+int launch_eval(const Shape& S, const Tab& tb, const Ws& ws, const double* x, double* obj,
+                double* g, hipStream_t st);
+int launch_derivs(const Shape& S, const Tab& tb, const double* x, const double* y, double* grad,
+                  double* jac, double* hess, hipStream_t st);
+
+// KKT assembly / factor / solve.  Phases that the timing hooks bracket are reported through
+// the callback (phase id, begin=1/end=0).
+typedef void (*phase_cb)(void* ctx, int phase, int begin, hipStream_t st);
+
+size_t level0_lds_bytes(const Shape& S, int prec);
+int launch_assemble(const Shape& S, const Tab& tb, const Ws& ws, const double* jac,
+                    const double* hess, const double* sigma_x, const double* sigma_s,
+                    const double* delta_w, const double* r_x, const double* r_s,
+                    const double* r_y, double* rhs, hipStream_t st);
+// launch_factor clears the per-instance flags first; launch_factor_nc keeps them (instances
+// whose flag is set are skipped).
+int launch_factor(const Shape& S, const Tab& tb, const HostPlan& hp, const Ws& ws, int prec,
+                  bool fused, phase_cb cb, void* ctx, hipStream_t st);
+int launch_factor_nc(const Shape& S, const Tab& tb, const HostPlan& hp, const Ws& ws, int prec,
+                     bool fused, phase_cb cb, void* ctx, hipStream_t st);
+// rthp: optional per-element theta partials added to the theta right-hand side.
+int launch_solve_p(const Shape& S, const Tab& tb, const HostPlan& hp, const Ws& ws,
+                   const double* rhs, const double* rthp, double* dx, phase_cb cb, void* ctx,
+                   hipStream_t st);
+int launch_matvec(const Shape& S, const Tab& tb, const Ws& ws, const double* v, double* out,
+                  hipStream_t st);
+int launch_copy_flags(const Tab& tb, const Ws& ws, int* info, hipStream_t st);
+
+
+}  // namespace cl
