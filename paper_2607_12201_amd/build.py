@@ -9,7 +9,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libcolloc.so")
-SOURCES = ["host.hip", "k_eval.hip", "k_kkt.hip", "k_ipm.hip"]
+SOURCES = ["host.hip", "k_eval.hip", "k_kkt.hip", "k_level0.hip", "k_ipm.hip"]
 ARCH = os.environ.get("COLLOC_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -43,9 +43,12 @@ struct Tab {
   const double* z0;           // [n_inst][ns]
   const double* th_lo;        // [n_inst][np]
   const double* th_hi;
-  const int* cr_ptr;          // [L + 1]
+  const int* cr_ptr;          // [L + 1]  separators eliminated at level l (q 2^(l-1), q odd)
   const int* cr_inst;         // per work item of a cyclic-reduction level
   const int* cr_j;
+  const int* st_ptr;          // [L]  step l (1..L-1): separators that are multiples of 2^l
+  const int* st_inst;
+  const int* st_s;
   int cr_items_max;           // largest level
 };
 
@@ -74,6 +77,7 @@ struct Ws {
   double* cB;                 // [n_elem][np]
   double* ysep;               // [n_elem][ns]
   double* xsep;               // [n_elem][ns]
+  double* rcur;               // [n_elem][ns] current right-hand side of surviving separators
   double* cBsep;              // [n_elem][np]
   double* rthp;               // [n_elem][np] right-hand-side theta partials
   double* xth;                // [n_inst][np]

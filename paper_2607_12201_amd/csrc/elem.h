@@ -234,6 +234,35 @@ __device__ inline double obj_element(const Shape& S, const Tab& tb, int64_t e, c
   return phi;
 }
 
+// out[c] = sum over the instance's elements i < N of part[(e0 + i) * np + c].  Thread t covers
+// parameter t % np over the elements t / np, t / np + G, ... (G = threads / np groups); the
+// groups are then added in order, so the result depends only on N, np and the block size.
+// red: nthr() doubles of LDS; out: np doubles of LDS.
+__device__ inline void theta_sum(const double* part, int64_t e0, int N, int np, double* out,
+                                 double* red) {
+  const int G = nthr() / np;
+  if (G >= 1) {
+    const int c = tid() % np, g = tid() / np;
+    double acc = 0.0;
+    if (g < G)
+      for (int i = g; i < N; i += G) acc += part[(e0 + i) * np + c];
+    red[tid()] = acc;
+    __syncthreads();
+    for (int c2 = tid(); c2 < np; c2 += nthr()) {
+      double sum = 0.0;
+      for (int gg = 0; gg < G; ++gg) sum += red[gg * np + c2];
+      out[c2] = sum;
+    }
+  } else {
+    for (int c2 = tid(); c2 < np; c2 += nthr()) {
+      double sum = 0.0;
+      for (int i = 0; i < N; ++i) sum += part[(e0 + i) * np + c2];
+      out[c2] = sum;
+    }
+  }
+  __syncthreads();
+}
+
 // Deterministic block reductions (fixed pairing for a given blockDim).
 __device__ inline double block_sum(double v, double* red) {
   red[tid()] = v;

@@ -124,7 +124,8 @@ struct colloc_problem {
   TableImage img;
   // offsets of each table in the image
   size_t o_N, o_x, o_g, o_e0, o_ei, o_el, o_eh, o_mptr, o_msp, o_mw, o_mys, o_react, o_param,
-      o_logk, o_spp, o_spr, o_spnu, o_rxs, o_rxnu, o_z0, o_lo, o_hi, o_crp, o_cri, o_crj;
+      o_logk, o_spp, o_spr, o_spnu, o_rxs, o_rxnu, o_z0, o_lo, o_hi, o_crp, o_cri, o_crj, o_stp,
+      o_sti, o_sts;
   int cr_items_max;
   Tab tab;
   bool uploaded;
@@ -220,7 +221,15 @@ extern "C" int colloc_create(const colloc_instance_desc* inst, int32_t n_inst, i
   // LDS budgets of the kernels (bytes)
   int nt = elem_threads(S);
   size_t need = std::max<size_t>(level0_lds_bytes(S, 0), ipm_eval_lds(S, nt));
-  size_t need_b = sizeof(double) * ((size_t)ns * ns + (size_t)ns * np + (size_t)np * np + 8 + ns + np);
+  need = std::max<size_t>(need, level0r_lds_bytes(S));
+  if (!level0r_supported(S)) {
+    delete p;
+    return COLLOC_EUNSUPPORTED;
+  }
+  size_t need_b = sizeof(double) * std::max<size_t>(
+      (size_t)2 * ns * ns + 2 * (size_t)ns * np + (size_t)np * np + 8,
+      (size_t)7 * ns * ns + 3 * (size_t)ns * np + 8);
+  need_b = std::max<size_t>(need_b, sizeof(double) * ((size_t)ns * ns + ns + np + (size_t)np * np + 256));
   if (need > lds_limit() || need_b > lds_limit() || nr * K > 65536) {
     delete p;
     return COLLOC_EUNSUPPORTED;
@@ -318,6 +327,7 @@ extern "C" int colloc_create(const colloc_instance_desc* inst, int32_t n_inst, i
     if (p->N[q] > 1) L = std::max(L, 1 + (int)floor(log2((double)(p->N[q] - 1)) + 1e-12));
   if (L > 62) { delete p; return COLLOC_EUNSUPPORTED; }
   std::vector<int> crp(L + 1, 0), cri, crj;
+  std::vector<int> stp(std::max(L, 1), 0), sti, sts;
   memset(&p->hp, 0, sizeof(p->hp));
   p->hp.L = L;
   for (int l = 1; l <= L; ++l) {
@@ -329,6 +339,17 @@ extern "C" int colloc_create(const colloc_instance_desc* inst, int32_t n_inst, i
       }
     crp[l] = (int)cri.size();
     p->hp.lvl[l] = crp[l] - crp[l - 1];
+  }
+  // step l = 1..L-1 touches every separator that is a multiple of 2^l (separator 0 included)
+  for (int l = 1; l < L; ++l) {
+    int step = 1 << l;
+    for (int q = 0; q < n_inst; ++q)
+      for (int s = 0; s < p->N[q]; s += step) {
+        sti.push_back(q);
+        sts.push_back(s);
+      }
+    stp[l] = (int)sti.size();
+    p->hp.st[l] = stp[l] - stp[l - 1];
   }
   p->cr_items_max = 0;
   for (int l = 1; l <= L; ++l) p->cr_items_max = std::max(p->cr_items_max, p->hp.lvl[l]);
@@ -360,6 +381,9 @@ extern "C" int colloc_create(const colloc_instance_desc* inst, int32_t n_inst, i
   p->o_crp = im.add(crp.data(), sizeof(int) * crp.size());
   p->o_cri = im.add(cri.data(), sizeof(int) * cri.size());
   p->o_crj = im.add(crj.data(), sizeof(int) * crj.size());
+  p->o_stp = im.add(stp.data(), sizeof(int) * stp.size());
+  p->o_sti = im.add(sti.data(), sizeof(int) * sti.size());
+  p->o_sts = im.add(sts.data(), sizeof(int) * sts.size());
   im.bytes.resize((im.bytes.size() + 255) & ~(size_t)255);
   p->uploaded = false;
   p->timing = false;
@@ -439,6 +463,9 @@ extern "C" int colloc_upload(colloc_problem* p, void* table_dev, hipStream_t str
   t.cr_ptr = (const int*)(b + p->o_crp);
   t.cr_inst = (const int*)(b + p->o_cri);
   t.cr_j = (const int*)(b + p->o_crj);
+  t.st_ptr = (const int*)(b + p->o_stp);
+  t.st_inst = (const int*)(b + p->o_sti);
+  t.st_s = (const int*)(b + p->o_sts);
   t.cr_items_max = p->cr_items_max;
   if (kkt_prepare_attrs(p->S) != 0) return COLLOC_EHIP;
   p->uploaded = true;
@@ -490,6 +517,7 @@ static Ws ws_layout(const colloc_problem* p, int prec, void* base, size_t* bytes
   w.cB = c.take<double>(E * S.np);
   w.ysep = c.take<double>(E * S.ns);
   w.xsep = c.take<double>(E * S.ns);
+  w.rcur = c.take<double>(E * S.ns);
   w.cBsep = c.take<double>(E * S.np);
   w.xth = c.take<double>(I * S.np);
   // block data in the factor precision

@@ -187,6 +187,7 @@ __global__ void __launch_bounds__(256) k_ipm_eval(Shape S, Tab tb, IpmState st, 
 __global__ void k_ipm_decide(Shape S, Tab tb, IpmState st, Ws ws, colloc_ipm_opts o) {
   __shared__ double red[256];
   __shared__ double sh[16];
+  extern __shared__ double jty[];   // np
   const int inst = blockIdx.x;
   colloc_ipm_info I = st.info[inst];
   if (I.status != COLLOC_RUNNING) {
@@ -218,11 +219,10 @@ __global__ void k_ipm_decide(Shape S, Tab tb, IpmState st, Ws ws, colloc_ipm_opt
       m_nf = fmax(m_nf, p[EP_NONFIN]);
     }
     // theta part: dual residual, complementarity, bound-multiplier norms, barrier logs
+    theta_sum(ws.rthp, e0, N, np, jty, red);
     double du_t = 0.0, l1z = 0.0, cmx = -INFINITY, cmn = INFINITY, lgt = 0.0;
     for (int c = tid(); c < np; c += nthr()) {
-      double jty = 0.0;
-      for (int i = 0; i < N; ++i) jty += ws.rthp[(e0 + i) * np + c];
-      double rx = jty - zL[c] + zU[c];
+      double rx = jty[c] - zL[c] + zU[c];
       du_t = fmax(du_t, fabs(rx));
       l1z += fabs(zL[c]) + fabs(zU[c]);
       double tl = th[c] - lo[c], tu = hi[c] - th[c];
@@ -551,10 +551,12 @@ __global__ void k_ipm_trial(Shape S, Tab tb, IpmState st, Ws ws, colloc_ipm_opts
   out[2] = lg;
 }
 
-// Acceptance: thread t sums candidate t over the instance's elements (fixed order); thread 0
-// scans the candidates in order with the filter rules and updates the filter.
+// Acceptance: the candidates' partial sums are reduced over the instance's elements with a
+// (candidate, element group) thread mapping and a fixed-order group sum; thread 0 then scans
+// the candidates in order with the filter rules and updates the filter.
 __global__ void k_ipm_select(Shape S, Tab tb, IpmState st, Ws ws, colloc_ipm_opts o) {
   __shared__ double cth[CL_MAX_LS], cph[CL_MAX_LS];
+  __shared__ double r0[256], r1[256], r2[256];
   const int inst = blockIdx.x;
   colloc_ipm_info I = st.info[inst];
   if (I.status != COLLOC_RUNNING) return;
@@ -569,16 +571,31 @@ __global__ void k_ipm_select(Shape S, Tab tb, IpmState st, Ws ws, colloc_ipm_opt
   const int64_t e0 = tb.inst_e0[inst];
   const int64_t xo = tb.inst_x[inst] + (int64_t)N * b;
   const int nls = o.max_ls;
+  const int G = nthr() / nls;
+  {
+    const int c = tid() % nls, g = tid() / nls;
+    double l1 = 0.0, ob = 0.0, lg = 0.0;
+    if (g < G)
+      for (int i = g; i < N; i += G) {
+        const double* p = st.tpart + ((e0 + i) * CL_MAX_LS + c) * 3;
+        l1 += p[0];
+        ob += p[1];
+        lg += p[2];
+      }
+    r0[tid()] = l1;
+    r1[tid()] = ob;
+    r2[tid()] = lg;
+  }
+  __syncthreads();
   const int t = tid();
   if (t < nls) {
     double alpha = I.alpha_pr;
     for (int q = 0; q < t; ++q) alpha *= 0.5;
     double l1 = 0.0, ob = 0.0, lg = 0.0;
-    for (int i = 0; i < N; ++i) {
-      const double* p = st.tpart + ((e0 + i) * CL_MAX_LS + t) * 3;
-      l1 += p[0];
-      ob += p[1];
-      lg += p[2];
+    for (int g = 0; g < G; ++g) {
+      l1 += r0[g * nls + t];
+      ob += r1[g * nls + t];
+      lg += r2[g * nls + t];
     }
     for (int c = 0; c < np; ++c) {
       double th = st.x[xo + c] + alpha * st.dx[xo + c];
@@ -710,7 +727,7 @@ int launch_ipm_step(const Shape& S, const Tab& tb, const HostPlan& hp, const Ipm
   const unsigned ne = (unsigned)tb.n_elem;
   if (cb) cb(ctx, COLLOC_PH_EVAL, 1, s);
   hipLaunchKernelGGL(k_ipm_eval, dim3(ne), dim3(nt), ipm_eval_lds(S, nt), s, S, tb, st, ws, o);
-  hipLaunchKernelGGL(k_ipm_decide, dim3(tb.n_inst), dim3(256), 0, s, S, tb, st, ws, o);
+  hipLaunchKernelGGL(k_ipm_decide, dim3(tb.n_inst), dim3(256), sizeof(double) * S.np, s, S, tb, st, ws, o);
   hipLaunchKernelGGL(k_ipm_prep, dim3(ne), dim3(nt),
                      sizeof(double) * (2 * S.b + S.ns + S.K * S.nr + S.np), s, S, tb, st, ws, o);
   if (cb) cb(ctx, COLLOC_PH_EVAL, 0, s);
@@ -726,7 +743,7 @@ int launch_ipm_step(const Shape& S, const Tab& tb, const HostPlan& hp, const Ipm
   if (cb) cb(ctx, COLLOC_PH_LINESEARCH, 1, s);
   hipLaunchKernelGGL(k_ipm_trial, dim3(ne), dim3(64), sizeof(double) * (4 * S.b + 2 * S.ns + 2 * S.np), s,
                      S, tb, st, ws, o);
-  hipLaunchKernelGGL(k_ipm_select, dim3(tb.n_inst), dim3(64), 0, s, S, tb, st, ws, o);
+  hipLaunchKernelGGL(k_ipm_select, dim3(tb.n_inst), dim3(256), 0, s, S, tb, st, ws, o);
   hipLaunchKernelGGL(k_ipm_update, dim3(ne), dim3(nt), 0, s, S, tb, st, ws, o);
   if (cb) cb(ctx, COLLOC_PH_LINESEARCH, 0, s);
   return ok_or();

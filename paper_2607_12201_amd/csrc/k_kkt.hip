@@ -122,8 +122,7 @@ __device__ inline void entry_store(const Shape& S, L0Lds<T>& L, int r1, int r2, 
                                    bool add) {
   const int ns = S.ns, np = S.np, b = S.b, mI = S.mI, R = S.R;
   if (r2 < mI) {
-    int row = r1 < b ? r1 : r1 + ns;
-    T* p = &L.Q[r2 * R + row];
+    T* p = &L.Q[r2 * R + r1];   // panel rows [I | S | theta | P]: natural order up to b + np
     *p = add ? (T)((double)*p + v) : (T)v;
   } else if (r2 < b) {
     T* p = (r1 < b) ? &L.dss[(r1 - mI) * ns + (r2 - mI)] : &L.bs[(r2 - mI) * np + (r1 - b)];
@@ -153,10 +152,10 @@ __device__ void assemble_element(const Shape& S, const Tab& tb, int64_t e, int i
     tri_index(t, r1, r2);
     entry_store(S, L, r1, r2, base_contrib(S, tb, e, dw, L.d0, r1, r2), false);
   }
-  // coupling of node-0 rows to the previous separator (continuity, eq. 2c)
+  // coupling of node-0 rows to the previous separator (continuity, eq. 2c): P rows last
   for (int t = tid(); t < ns * mI; t += nthr()) {
     int col = t / ns, s = t - col * ns;
-    L.Q[col * R + mI + ns + s] = (T)((i > 0 && col == s) ? -L.d0[s] : 0.0);
+    L.Q[col * R + b + np + s] = (T)((i > 0 && col == s) ? -L.d0[s] : 0.0);
   }
   for (int k = 1; k <= S.K; ++k) {
     __syncthreads();
@@ -209,67 +208,6 @@ __device__ void assemble_element(const Shape& S, const Tab& tb, int64_t e, int i
     }
   }
   __syncthreads();
-}
-
-// In-place Cholesky of the first mI columns of the R x mI column-major panel.
-template <typename T>
-__device__ bool panel_cholesky(T* Q, int R, int mI, double* misc) {
-  for (int c = 0; c < mI; ++c) {
-    if (tid() == 0) {
-      double piv = (double)Q[c * R + c];
-      bool ok = piv > 0.0 && isfinite(piv);
-      double sq = ok ? sqrt(piv) : 1.0;
-      Q[c * R + c] = (T)sq;
-      misc[0] = ok ? 1.0 : 0.0;
-      misc[1] = 1.0 / sq;
-    }
-    __syncthreads();
-    if (misc[0] == 0.0) return false;
-    T inv = (T)misc[1];
-    for (int r = c + 1 + tid(); r < R; r += nthr()) Q[c * R + r] *= inv;
-    __syncthreads();
-    const int nrow = R - c - 1, ncol = mI - c - 1;
-    for (int t = tid(); t < nrow * ncol; t += nthr()) {
-      int c2 = c + 1 + t / nrow, r = c + 1 + t % nrow;
-      if (r >= c2) Q[c2 * R + r] -= Q[c * R + r] * Q[c * R + c2];
-    }
-    __syncthreads();
-  }
-  return true;
-}
-
-// Schur complement of the panel onto its tail rows (S, P, theta) written to the chain blocks.
-template <typename T>
-__device__ void level0_outputs(const Shape& S, const Ws& ws, int64_t e, int i, L0Lds<T>& L) {
-  const int ns = S.ns, np = S.np, mI = S.mI, R = S.R, Rt = S.Rt;
-  const int ntri = Rt * (Rt + 1) / 2;
-  T* dss = (T*)ws.dss + e * ns * ns;
-  T* bs = (T*)ws.bs + e * ns * np;
-  T* tprev = (T*)ws.tprev + e * ns * ns;
-  T* e1 = (T*)ws.e1 + e * ns * ns;
-  T* gprev = (T*)ws.gprev + e * ns * np;
-  double* ath = ws.ath + e * np * np;
-  for (int t = tid(); t < ntri; t += nthr()) {
-    int a, c;
-    tri_index(t, a, c);  // a >= c, tail indices
-    bool aP = a >= ns && a < 2 * ns, cP = c >= ns && c < 2 * ns;
-    if (i == 0 && (aP || cP)) continue;
-    double acc = 0.0;
-    const T* qa = L.Q + mI + a;
-    const T* qc = L.Q + mI + c;
-    for (int k = 0; k < mI; ++k) acc += (double)qa[k * R] * (double)qc[k * R];
-    if (a < ns) {                       // S-S
-      dss[a * ns + c] = (T)((double)L.dss[a * ns + c] - acc);
-    } else if (a < 2 * ns) {
-      if (c < ns) e1[c * ns + (a - ns)] = (T)(-acc);           // (S_i c, S_{i-1} a-ns)
-      else tprev[(a - ns) * ns + (c - ns)] = (T)(((a == c) ? L.dcont[a - ns] : 0.0) - acc);
-    } else {
-      int th = a - 2 * ns;
-      if (c < ns) bs[c * np + th] = (T)((double)L.bs[c * np + th] - acc);
-      else if (c < 2 * ns) gprev[(c - ns) * np + th] = (T)(-acc);
-      else ath[th * np + (c - 2 * ns)] = L.ath[th * np + (c - 2 * ns)] - acc;
-    }
-  }
 }
 
 // kkt_assemble: blocks to the workspace (unfactored), derivative copies, Ds, rhs.
@@ -341,40 +279,6 @@ __global__ void k_rhs_theta(Shape S, Tab tb, Ws ws, const double* __restrict__ r
     rhs[xt + c] = -r_x[xt + c] + acc;
     ws.sxdw[inst * S.np + c] = sigma_x[inst * S.np + c] + delta_w[inst];
   }
-}
-
-// Level 0 of the factorization.  fused = 1: assemble in LDS from ws.jac/hess/Ds/dw first.
-template <typename T>
-__global__ void __launch_bounds__(256) k_level0(Shape S, Tab tb, Ws ws, int fused) {
-  extern __shared__ double lds_raw[];
-  const int64_t e = blockIdx.x;
-  const int inst = tb.elem_inst[e], i = tb.elem_loc[e];
-  const int ns = S.ns, np = S.np, R = S.R, mI = S.mI;
-  if (block_flag(&ws.flag[inst])) return;
-  L0Lds<T> L = l0_carve<T>(S, lds_raw);
-  T* Qg = (T*)ws.panel + e * (int64_t)R * mI;
-  if (fused) {
-    const int64_t jl = (int64_t)S.K * S.nr;
-    const int64_t gi = tb.inst_g[inst] + (int64_t)i * S.b;
-    assemble_element<T>(S, tb, e, inst, i, tb.elem_h[e], ws.jac + e * jl * 3,
-                        ws.hess + e * jl * 4, ws.Ds + gi, ws.dw[inst], L);
-  } else {
-    const T* dssg = (const T*)ws.dss + e * ns * ns;
-    const T* bsg = (const T*)ws.bs + e * ns * np;
-    for (int t = tid(); t < R * mI; t += nthr()) L.Q[t] = Qg[t];
-    for (int t = tid(); t < ns * ns; t += nthr()) L.dss[t] = dssg[t];
-    for (int t = tid(); t < ns * np; t += nthr()) L.bs[t] = bsg[t];
-    for (int t = tid(); t < np * np; t += nthr()) L.ath[t] = ws.ath[e * np * np + t];
-    for (int t = tid(); t < ns; t += nthr()) L.dcont[t] = ws.dcont[e * ns + t];
-    __syncthreads();
-  }
-  bool ok = panel_cholesky<T>(L.Q, R, mI, L.misc);
-  if (!ok) {
-    if (tid() == 0) atomicOr(&ws.flag[inst], 1);
-    return;
-  }
-  level0_outputs<T>(S, ws, e, i, L);
-  for (int t = tid(); t < R * mI; t += nthr()) Qg[t] = L.Q[t];
 }
 
 // ---------------------------------------------------------------- small dense LDS helpers
@@ -459,103 +363,44 @@ __device__ void sub_atb(double* C, int n, int m, const T* A, const T* B, int k, 
 }
 
 // ---------------------------------------------------------------- cyclic reduction levels
-// Gather the current separator block T_j (lower, full rows), its border G_j and, when rhs is
-// given, its right-hand side, applying the updates of every level below `level`.
-template <typename T>
-__device__ void gather_sep(const Shape& S, const Tab& tb, const Ws& ws, int64_t e0, int N, int j,
-                           int level, double* Tm, double* G) {
-  const int ns = S.ns, np = S.np;
-  const int64_t ej = e0 + j;
-  load_blk(Tm, (const T*)ws.dss + ej * ns * ns, ns * ns);
-  load_blk(G, (const T*)ws.bs + ej * ns * np, ns * np);
-  __syncthreads();
-  if (j + 1 < N) {
-    const T* tp = (const T*)ws.tprev + (ej + 1) * ns * ns;
-    const T* gp = (const T*)ws.gprev + (ej + 1) * ns * np;
-    for (int t = tid(); t < ns * ns; t += nthr()) Tm[t] += (double)tp[t];
-    for (int t = tid(); t < ns * np; t += nthr()) G[t] += (double)gp[t];
-  }
-  __syncthreads();
-  for (int lp = 1; lp < level; ++lp) {
-    int hh = 1 << (lp - 1);
-    int jl = j - hh;
-    if (jl >= 0) {
-      const T* U = (const T*)ws.ur + (e0 + jl) * ns * ns;
-      sub_atb(Tm, ns, ns, U, U, ns, true);
-      sub_atb(G, ns, np, U, (const T*)ws.ub + (e0 + jl) * ns * np, ns, false);
-    }
-    int jr = j + hh;
-    if (jr < N) {
-      const T* U = (const T*)ws.ul + (e0 + jr) * ns * ns;
-      sub_atb(Tm, ns, ns, U, U, ns, true);
-      sub_atb(G, ns, np, U, (const T*)ws.ub + (e0 + jr) * ns * np, ns, false);
-    }
-    __syncthreads();
-  }
-}
+// Eager cyclic reduction of the separator chain.  dss/bs hold the current separator block T_s
+// and border G_s (after level 0: the element's own Schur part; the next element's part sits
+// in tprev/gprev until the first level that touches s adds it).
+//   k_cr_first      level 1: eliminate the odd separators.
+//   k_cr_step(l)    for every s that is a multiple of 2^l: apply the updates of its two
+//                   neighbours eliminated at level l and, when s / 2^l is odd, eliminate s
+//                   (level l + 1) with couplings formed from those neighbours' factors.
+//   k_border        separator 0 and the parameter Schur complement.
+// Each separator is touched by exactly one workgroup per launch; operands are staged in LDS.
 
-// Coupling block (row hi, col lo) between separators lo < hi adjacent at `level`.
-template <typename T>
-__device__ void coupling(const Shape& S, const Ws& ws, int64_t e0, int lo, int hi, int level,
-                         double* E) {
-  const int ns = S.ns;
-  if (level == 1) {
-    load_blk(E, (const T*)ws.e1 + (e0 + hi) * ns * ns, ns * ns);
-  } else {
-    int jm = lo + (1 << (level - 2));
-    const T* UR = (const T*)ws.ur + (e0 + jm) * ns * ns;
-    const T* UL = (const T*)ws.ul + (e0 + jm) * ns * ns;
-    for (int t = tid(); t < ns * ns; t += nthr()) {
-      int r = t / ns, q = t % ns;
-      double acc = 0.0;
-      for (int p = 0; p < ns; ++p) acc += (double)UR[p * ns + r] * (double)UL[p * ns + q];
-      E[t] = -acc;
-    }
-  }
-}
-
-// Theta-theta contribution -U_B^T U_B of an eliminated separator, stored as a full lower block.
-template <typename T>
-__device__ void theta_part(const Shape& S, const T* UB, double* out) {
-  const int ns = S.ns, np = S.np;
-  for (int t = tid(); t < np * np; t += nthr()) {
-    int r = t / np, q = t % np;
-    if (q > r) continue;
+// C (n x m, row-major) -= A^T B with A (k x n), B (k x m) row-major in LDS.
+__device__ void lds_sub_atb(double* C, const double* A, const double* B, int k, int n, int m,
+                            bool lower_only) {
+  for (int t = tid(); t < n * m; t += nthr()) {
+    int r = t / m, q = t - r * m;
+    if (lower_only && q > r) continue;
     double acc = 0.0;
-    for (int p = 0; p < ns; ++p) acc += (double)UB[p * np + r] * (double)UB[p * np + q];
-    out[t] = -acc;
+    for (int p = 0; p < k; ++p) acc += A[p * n + r] * B[p * m + q];
+    C[t] -= acc;
+  }
+}
+__device__ void lds_neg_atb(double* C, const double* A, const double* B, int k, int n, int m) {
+  for (int t = tid(); t < n * m; t += nthr()) {
+    int r = t / m, q = t - r * m;
+    double acc = 0.0;
+    for (int p = 0; p < k; ++p) acc += A[p * n + r] * B[p * m + q];
+    C[t] = -acc;
   }
 }
 
-// LDS: Tm (ns^2) G (ns np) EL (ns^2) ER (ns^2) misc
+// Factor the separator block in Tm (lower) and form UL = L^-1 EL, UR = L^-1 ER^T,
+// UB = L^-1 G; store them and the theta-theta part -UB^T UB.  Returns false if not PD.
 template <typename T>
-__global__ void k_cr(Shape S, Tab tb, Ws ws, int level) {
-  extern __shared__ double lds[];
-  const int it = tb.cr_ptr[level - 1] + blockIdx.x;
-  if (it >= tb.cr_ptr[level]) return;
-  const int inst = tb.cr_inst[it], j = tb.cr_j[it];
-  if (block_flag(&ws.flag[inst])) return;
+__device__ bool eliminate_sep(const Shape& S, const Ws& ws, int64_t ej, double* Tm, double* G,
+                              double* EL, double* ER, bool has_r, double* misc) {
   const int ns = S.ns, np = S.np;
-  const int N = tb.inst_N[inst];
-  const int64_t e0 = tb.inst_e0[inst], ej = e0 + j;
-  double* Tm = lds;
-  double* G = Tm + ns * ns;
-  double* EL = G + ns * np;
-  double* ER = EL + ns * ns;
-  double* misc = ER + ns * ns;
-  const int half = 1 << (level - 1);
-  gather_sep<T>(S, tb, ws, e0, N, j, level, Tm, G);
-  coupling<T>(S, ws, e0, j - half, j, level, EL);
-  const bool has_r = j + half < N;
-  if (has_r) coupling<T>(S, ws, e0, j, j + half, level, ER);
-  __syncthreads();
-  if (!chol_small(Tm, ns, misc)) {
-    if (tid() == 0) atomicOr(&ws.flag[inst], 1);
-    return;
-  }
-  // UL = L^{-1} EL ; UR = L^{-1} ER^T ; UB = L^{-1} G
+  if (!chol_small(Tm, ns, misc)) return false;
   if (has_r) {
-    // transpose ER in place into EL's neighbour buffer: use misc-free swap through G? keep ER^T
     for (int t = tid(); t < ns * ns; t += nthr()) {
       int r = t / ns, q = t % ns;
       if (q > r) {
@@ -576,34 +421,141 @@ __global__ void k_cr(Shape S, Tab tb, Ws ws, int level) {
   store_blk((T*)ws.ul + ej * ns * ns, EL, ns * ns);
   store_blk((T*)ws.ur + ej * ns * ns, ER, ns * ns);
   store_blk((T*)ws.ub + ej * ns * np, G, ns * np);
-  __syncthreads();
-  theta_part<T>(S, (const T*)ws.ub + ej * ns * np, ws.thcr + ej * np * np);
-}
-
-// Theta-theta reduction, stage 1: instance blockIdx.y, chunk blockIdx.x of its elements;
-// partial = sum over the chunk of (element Schur part + separator part), lower triangle.
-__global__ void k_thred(Shape S, Tab tb, Ws ws) {
-  const int inst = blockIdx.y, chunk = blockIdx.x;
-  if (block_flag(&ws.flag[inst])) return;
-  const int np = S.np, N = tb.inst_N[inst];
-  const int64_t e0 = tb.inst_e0[inst];
-  const int i0 = chunk * CL_THCHUNK, i1 = min(N, i0 + CL_THCHUNK);
-  if (i0 >= N) return;
-  double* out = ws.thred + ((int64_t)inst * ws.nchunk + chunk) * np * np;
+  // theta-theta part from the stored (rounded) border rows, accumulated in FP64
+  double* th = ws.thcr + ej * np * np;
   for (int t = tid(); t < np * np; t += nthr()) {
     int r = t / np, q = t % np;
     if (q > r) continue;
     double acc = 0.0;
-    for (int i = i0; i < i1; ++i) {
-      acc += ws.ath[(e0 + i) * np * np + t];
-      if (i > 0) acc += ws.thcr[(e0 + i) * np * np + t];
-    }
-    out[t] = acc;
+    for (int p = 0; p < ns; ++p) acc += (double)(T)G[p * np + r] * (double)(T)G[p * np + q];
+    th[t] = -acc;
   }
+  return true;
 }
 
-// Border: eliminate separator 0, form the parameter Schur complement, factor it.
-// LDS: Tm (ns^2) G (ns np) Sm (np^2) misc
+// Separator s's block and border with the next element's level-0 part added.
+template <typename T>
+__device__ void sep_initial(const Shape& S, const Ws& ws, int64_t es, bool has_next, double* Tm,
+                            double* G) {
+  const int ns = S.ns, np = S.np;
+  const T* d = (const T*)ws.dss + es * ns * ns;
+  const T* bsv = (const T*)ws.bs + es * ns * np;
+  const T* tp = (const T*)ws.tprev + (es + 1) * ns * ns;
+  const T* gp = (const T*)ws.gprev + (es + 1) * ns * np;
+  for (int t = tid(); t < ns * ns; t += nthr()) Tm[t] = (double)d[t] + (has_next ? (double)tp[t] : 0.0);
+  for (int t = tid(); t < ns * np; t += nthr()) G[t] = (double)bsv[t] + (has_next ? (double)gp[t] : 0.0);
+}
+
+// LDS: Tm (ns^2) G (ns np) EL (ns^2) ER (ns^2) misc (8)
+template <typename T>
+__global__ void k_cr_first(Shape S, Tab tb, Ws ws) {
+  extern __shared__ double lds[];
+  const int it = tb.cr_ptr[0] + blockIdx.x;
+  if (it >= tb.cr_ptr[1]) return;
+  const int inst = tb.cr_inst[it], j = tb.cr_j[it];
+  if (block_flag(&ws.flag[inst])) return;
+  const int ns = S.ns, np = S.np, N = tb.inst_N[inst];
+  const int64_t e0 = tb.inst_e0[inst], ej = e0 + j;
+  double* Tm = lds;
+  double* G = Tm + ns * ns;
+  double* EL = G + ns * np;
+  double* ER = EL + ns * ns;
+  double* misc = ER + ns * ns;
+  const bool has_r = j + 1 < N;
+  sep_initial<T>(S, ws, ej, has_r, Tm, G);
+  load_blk(EL, (const T*)ws.e1 + ej * ns * ns, ns * ns);
+  if (has_r) load_blk(ER, (const T*)ws.e1 + (ej + 1) * ns * ns, ns * ns);
+  __syncthreads();
+  if (!eliminate_sep<T>(S, ws, ej, Tm, G, EL, ER, has_r, misc))
+    if (tid() == 0) atomicOr(&ws.flag[inst], 1);
+}
+
+// LDS: Tm G EL ER (as above) + U1r U1l (ns^2) U1b (ns np) + U2r U2l (ns^2) U2b (ns np) + misc
+template <typename T>
+__global__ void k_cr_step(Shape S, Tab tb, Ws ws, int level) {
+  extern __shared__ double lds[];
+  const int it = tb.st_ptr[level - 1] + blockIdx.x;
+  if (it >= tb.st_ptr[level]) return;
+  const int inst = tb.st_inst[it], s = tb.st_s[it];
+  if (block_flag(&ws.flag[inst])) return;
+  const int ns = S.ns, np = S.np, N = tb.inst_N[inst];
+  const int64_t e0 = tb.inst_e0[inst], es = e0 + s;
+  const int half = 1 << (level - 1);
+  const int j1 = s - half, j2 = s + half;
+  const bool h1 = s > 0, h2 = j2 < N;
+  const bool elim = ((s >> level) & 1) != 0;
+  const bool has_r = elim && (s + 2 * half < N);
+  double* Tm = lds;
+  double* G = Tm + ns * ns;
+  double* EL = G + ns * np;
+  double* ER = EL + ns * ns;
+  double* U1r = ER + ns * ns;
+  double* U1l = U1r + ns * ns;
+  double* U1b = U1l + ns * ns;
+  double* U2r = U1b + ns * np;
+  double* U2l = U2r + ns * ns;
+  double* U2b = U2l + ns * ns;
+  double* misc = U2b + ns * np;
+  if (level == 1) {
+    sep_initial<T>(S, ws, es, s + 1 < N, Tm, G);
+  } else {
+    load_blk(Tm, (const T*)ws.dss + es * ns * ns, ns * ns);
+    load_blk(G, (const T*)ws.bs + es * ns * np, ns * np);
+  }
+  if (h1) {
+    load_blk(U1r, (const T*)ws.ur + (e0 + j1) * ns * ns, ns * ns);
+    load_blk(U1l, (const T*)ws.ul + (e0 + j1) * ns * ns, ns * ns);
+    load_blk(U1b, (const T*)ws.ub + (e0 + j1) * ns * np, ns * np);
+  }
+  if (h2) {
+    load_blk(U2r, (const T*)ws.ur + (e0 + j2) * ns * ns, ns * ns);
+    load_blk(U2l, (const T*)ws.ul + (e0 + j2) * ns * ns, ns * ns);
+    load_blk(U2b, (const T*)ws.ub + (e0 + j2) * ns * np, ns * np);
+  }
+  __syncthreads();
+  if (h1) {
+    lds_sub_atb(Tm, U1r, U1r, ns, ns, ns, true);
+    lds_sub_atb(G, U1r, U1b, ns, ns, np, false);
+    if (elim) lds_neg_atb(EL, U1r, U1l, ns, ns, ns);
+  }
+  __syncthreads();
+  if (h2) {
+    lds_sub_atb(Tm, U2l, U2l, ns, ns, ns, true);
+    lds_sub_atb(G, U2l, U2b, ns, ns, np, false);
+    if (has_r) lds_neg_atb(ER, U2r, U2l, ns, ns, ns);
+  }
+  __syncthreads();
+  if (!elim) {
+    store_blk((T*)ws.dss + es * ns * ns, Tm, ns * ns);
+    store_blk((T*)ws.bs + es * ns * np, G, ns * np);
+    return;
+  }
+  if (!eliminate_sep<T>(S, ws, es, Tm, G, EL, ER, has_r, misc))
+    if (tid() == 0) atomicOr(&ws.flag[inst], 1);
+}
+
+// Theta-theta reduction, stage 1: partial sums over chunks of CL_THCHUNK elements of the
+// element Schur parts and separator parts; grid (chunk, entry tile, instance).
+__global__ void k_thred(Shape S, Tab tb, Ws ws) {
+  const int inst = blockIdx.z, chunk = blockIdx.x;
+  const int t = blockIdx.y * blockDim.x + threadIdx.x;
+  const int np = S.np, N = tb.inst_N[inst];
+  if (t >= np * np || ws.flag[inst]) return;
+  const int i0 = chunk * CL_THCHUNK, i1 = min(N, i0 + CL_THCHUNK);
+  if (i0 >= N) return;
+  const int r = t / np, q = t % np;
+  if (q > r) return;
+  const int64_t e0 = tb.inst_e0[inst];
+  double acc = 0.0;
+  for (int i = i0; i < i1; ++i) {
+    acc += ws.ath[(e0 + i) * np * np + t];
+    if (i > 0) acc += ws.thcr[(e0 + i) * np * np + t];
+  }
+  ws.thred[((int64_t)inst * ws.nchunk + chunk) * np * np + t] = acc;
+}
+
+// Border: the last cyclic-reduction update and elimination of separator 0, the parameter
+// Schur complement and its factor.  LDS: Tm (ns^2) G (ns np) Sm (np^2) U (ns^2) Ub (ns np) misc
 template <typename T>
 __global__ void k_border(Shape S, Tab tb, Ws ws) {
   extern __shared__ double lds[];
@@ -614,15 +566,33 @@ __global__ void k_border(Shape S, Tab tb, Ws ws) {
   double* Tm = lds;
   double* G = Tm + ns * ns;
   double* Sm = G + ns * np;
-  double* misc = Sm + np * np;
-  gather_sep<T>(S, tb, ws, e0, N, 0, tb.L + 1, Tm, G);
+  double* U = Sm + np * np;
+  double* Ub = U + ns * ns;
+  double* misc = Ub + ns * np;
+  const int L = tb.L;
+  if (L <= 1) {
+    sep_initial<T>(S, ws, e0, N > 1, Tm, G);
+  } else {
+    load_blk(Tm, (const T*)ws.dss + e0 * ns * ns, ns * ns);
+    load_blk(G, (const T*)ws.bs + e0 * ns * np, ns * np);
+  }
+  const int jl = L >= 1 ? (1 << (L - 1)) : N;
+  if (jl < N) {
+    load_blk(U, (const T*)ws.ul + (e0 + jl) * ns * ns, ns * ns);
+    load_blk(Ub, (const T*)ws.ub + (e0 + jl) * ns * np, ns * np);
+  }
+  const int nch = (int)cl_ceil_div(N, CL_THCHUNK);
   for (int t = tid(); t < np * np; t += nthr()) {
     int r = t / np, q = t % np;
     double acc = 0.0;
-    const int nch = (int)cl_ceil_div(N, CL_THCHUNK);
     if (q <= r)
       for (int c = 0; c < nch; ++c) acc += ws.thred[((int64_t)inst * ws.nchunk + c) * np * np + t];
     Sm[t] = acc + (r == q ? ws.sxdw[inst * np + r] : 0.0);
+  }
+  __syncthreads();
+  if (jl < N) {
+    lds_sub_atb(Tm, U, U, ns, ns, ns, true);
+    lds_sub_atb(G, U, Ub, ns, ns, np, false);
   }
   __syncthreads();
   if (!chol_small(Tm, ns, misc)) {
@@ -637,7 +607,7 @@ __global__ void k_border(Shape S, Tab tb, Ws ws) {
     int r = t / np, q = t % np;
     if (q > r) continue;
     double acc = 0.0;
-    for (int p = 0; p < ns; ++p) acc += G[p * np + r] * G[p * np + q];
+    for (int p = 0; p < ns; ++p) acc += (double)(T)G[p * np + r] * (double)(T)G[p * np + q];
     Sm[t] -= acc;
   }
   __syncthreads();
@@ -678,48 +648,30 @@ __global__ void k_l0_fwd(Shape S, Tab tb, Ws ws, const double* __restrict__ rhs)
     __syncthreads();
   }
   for (int t = tid(); t < mI; t += nthr()) ws.yI[e * mI + t] = y[t];
-  for (int a = tid(); a < S.Rt; a += nthr()) {
+  for (int a = tid(); a < S.Rt; a += nthr()) {   // tail rows [S | theta | P]
     double acc = 0.0;
     for (int k = 0; k < mI; ++k) acc += (double)Q[k * R + mI + a] * y[k];
     if (a < ns) ws.cS[e * ns + a] = acc;
-    else if (a < 2 * ns) ws.cP[e * ns + (a - ns)] = (i > 0) ? acc : 0.0;
-    else ws.cB[e * np + (a - 2 * ns)] = acc;
+    else if (a < ns + np) ws.cB[e * np + (a - ns)] = acc;
+    else ws.cP[e * ns + (a - ns - np)] = (i > 0) ? acc : 0.0;
   }
 }
 
-// Right-hand side of separator j at `level` (all updates from levels below).
-template <typename T>
-__device__ void gather_rhs(const Shape& S, const Tab& tb, const Ws& ws, int64_t e0, int64_t xoff,
-                           int N, int j, int level, const double* rhs, double* r) {
-  const int ns = S.ns;
-  const int64_t ej = e0 + j;
-  for (int a = tid(); a < ns; a += nthr()) {
-    double v = rhs[xoff + (int64_t)j * S.b + S.mI + a] - ws.cS[ej * ns + a];
-    if (j + 1 < N) v -= ws.cP[(ej + 1) * ns + a];
-    for (int lp = 1; lp < level; ++lp) {
-      int hh = 1 << (lp - 1);
-      int jl = j - hh, jr = j + hh;
-      if (jl >= 0) {
-        const T* U = (const T*)ws.ur + (e0 + jl) * ns * ns;
-        const double* yv = ws.ysep + (e0 + jl) * ns;
-        for (int p = 0; p < ns; ++p) v -= (double)U[p * ns + a] * yv[p];
-      }
-      if (jr < N) {
-        const T* U = (const T*)ws.ul + (e0 + jr) * ns * ns;
-        const double* yv = ws.ysep + (e0 + jr) * ns;
-        for (int p = 0; p < ns; ++p) v -= (double)U[p * ns + a] * yv[p];
-      }
-    }
-    r[a] = v;
-  }
+// Forward solve of the separator chain, mirroring the factor: rcur holds the current
+// right-hand side of surviving separators.
+__device__ inline double sep_rhs_initial(const Shape& S, const Ws& ws, const double* rhs,
+                                         int64_t xoff, int64_t es, int s, bool has_next, int a) {
+  double v = rhs[xoff + (int64_t)s * S.b + S.mI + a] - ws.cS[es * S.ns + a];
+  if (has_next) v -= ws.cP[(es + 1) * S.ns + a];
+  return v;
 }
 
 // LDS: Lm (ns^2) r (ns)
 template <typename T>
-__global__ void k_cr_fwd(Shape S, Tab tb, Ws ws, const double* __restrict__ rhs, int level) {
+__global__ void k_crf_first(Shape S, Tab tb, Ws ws, const double* __restrict__ rhs) {
   extern __shared__ double lds[];
-  const int it = tb.cr_ptr[level - 1] + blockIdx.x;
-  if (it >= tb.cr_ptr[level]) return;
+  const int it = tb.cr_ptr[0] + blockIdx.x;
+  if (it >= tb.cr_ptr[1]) return;
   const int inst = tb.cr_inst[it], j = tb.cr_j[it];
   if (block_flag(&ws.flag[inst])) return;
   const int ns = S.ns, np = S.np, N = tb.inst_N[inst];
@@ -727,7 +679,8 @@ __global__ void k_cr_fwd(Shape S, Tab tb, Ws ws, const double* __restrict__ rhs,
   double* Lm = lds;
   double* r = Lm + ns * ns;
   load_blk(Lm, (const T*)ws.lsep + ej * ns * ns, ns * ns);
-  gather_rhs<T>(S, tb, ws, e0, tb.inst_x[inst], N, j, level, rhs, r);
+  for (int a = tid(); a < ns; a += nthr())
+    r[a] = sep_rhs_initial(S, ws, rhs, tb.inst_x[inst], ej, j, j + 1 < N, a);
   __syncthreads();
   if (tid() == 0) trsv_l_seq(Lm, ns, r);
   __syncthreads();
@@ -740,12 +693,59 @@ __global__ void k_cr_fwd(Shape S, Tab tb, Ws ws, const double* __restrict__ rhs,
   }
 }
 
-// Border solve: separator 0, theta, back to separator 0.  LDS: Lm (ns^2) r (ns) rt (np) Sm.
+template <typename T>
+__global__ void k_crf_step(Shape S, Tab tb, Ws ws, const double* __restrict__ rhs, int level) {
+  extern __shared__ double lds[];
+  const int it = tb.st_ptr[level - 1] + blockIdx.x;
+  if (it >= tb.st_ptr[level]) return;
+  const int inst = tb.st_inst[it], s = tb.st_s[it];
+  if (block_flag(&ws.flag[inst])) return;
+  const int ns = S.ns, np = S.np, N = tb.inst_N[inst];
+  const int64_t e0 = tb.inst_e0[inst], es = e0 + s;
+  const int half = 1 << (level - 1);
+  const int j1 = s - half, j2 = s + half;
+  const bool h1 = s > 0, h2 = j2 < N;
+  const bool elim = ((s >> level) & 1) != 0;
+  double* Lm = lds;
+  double* r = Lm + ns * ns;
+  if (elim) load_blk(Lm, (const T*)ws.lsep + es * ns * ns, ns * ns);
+  for (int a = tid(); a < ns; a += nthr()) {
+    double v = level == 1 ? sep_rhs_initial(S, ws, rhs, tb.inst_x[inst], es, s, s + 1 < N, a)
+                          : ws.rcur[es * ns + a];
+    if (h1) {
+      const T* U = (const T*)ws.ur + (e0 + j1) * ns * ns;
+      const double* yv = ws.ysep + (e0 + j1) * ns;
+      for (int p = 0; p < ns; ++p) v -= (double)U[p * ns + a] * yv[p];
+    }
+    if (h2) {
+      const T* U = (const T*)ws.ul + (e0 + j2) * ns * ns;
+      const double* yv = ws.ysep + (e0 + j2) * ns;
+      for (int p = 0; p < ns; ++p) v -= (double)U[p * ns + a] * yv[p];
+    }
+    r[a] = v;
+  }
+  __syncthreads();
+  if (!elim) {
+    for (int a = tid(); a < ns; a += nthr()) ws.rcur[es * ns + a] = r[a];
+    return;
+  }
+  if (tid() == 0) trsv_l_seq(Lm, ns, r);
+  __syncthreads();
+  for (int t = tid(); t < ns; t += nthr()) ws.ysep[es * ns + t] = r[t];
+  const T* UB = (const T*)ws.ub + es * ns * np;
+  for (int c = tid(); c < np; c += nthr()) {
+    double acc = 0.0;
+    for (int p = 0; p < ns; ++p) acc += (double)UB[p * np + c] * r[p];
+    ws.cBsep[es * np + c] = acc;
+  }
+}
+
+// Border solve: separator 0, theta, back to separator 0.
+// LDS: Lm (ns^2) r (ns) rt (np) Sm (np^2) red (nthr * np)
 template <typename T>
 __global__ void k_border_solve(Shape S, Tab tb, Ws ws, const double* __restrict__ rhs,
                                const double* __restrict__ rthp, double* __restrict__ dx) {
   extern __shared__ double lds[];
-  __shared__ double red[256];
   const int inst = blockIdx.x;
   if (block_flag(&ws.flag[inst])) return;
   const int ns = S.ns, np = S.np, N = tb.inst_N[inst];
@@ -755,33 +755,58 @@ __global__ void k_border_solve(Shape S, Tab tb, Ws ws, const double* __restrict_
   double* r = Lm + ns * ns;
   double* rt = r + ns;
   double* Sm = rt + np;
+  double* red = Sm + np * np;
   load_blk(Lm, (const T*)ws.lsep + e0 * ns * ns, ns * ns);
   for (int t = tid(); t < np * np; t += nthr()) Sm[t] = ws.S[(int64_t)inst * np * np + t];
-  gather_rhs<T>(S, tb, ws, e0, xoff, N, 0, tb.L + 1, rhs, r);
+  const int L = tb.L;
+  const int jl = L >= 1 ? (1 << (L - 1)) : N;
+  for (int a = tid(); a < ns; a += nthr()) {
+    double v = L <= 1 ? sep_rhs_initial(S, ws, rhs, xoff, e0, 0, N > 1, a) : ws.rcur[e0 * ns + a];
+    if (jl < N) {
+      const T* U = (const T*)ws.ul + (e0 + jl) * ns * ns;
+      const double* yv = ws.ysep + (e0 + jl) * ns;
+      for (int p = 0; p < ns; ++p) v -= (double)U[p * ns + a] * yv[p];
+    }
+    r[a] = v;
+  }
+  // theta right-hand side partial sums: thread t covers parameter t % np over the elements
+  // i = t / np, t / np + G, ... (G = threads / np groups), then a fixed-order group sum
+  const int G = max(1, nthr() / np);
+  const int c0 = tid() % np, g0 = tid() / np;
+  double acc = 0.0;
+  if (g0 < G)
+    for (int i = g0; i < N; i += G) {
+      acc += ws.cB[(e0 + i) * np + c0];
+      if (i > 0) acc += ws.cBsep[(e0 + i) * np + c0];
+      if (rthp) acc -= rthp[(e0 + i) * np + c0];
+    }
+  if (np > nthr()) {  // fall back: loop parameters per thread
+    acc = 0.0;
+  }
+  red[tid()] = (g0 < G) ? acc : 0.0;
   __syncthreads();
   if (tid() == 0) trsv_l_seq(Lm, ns, r);
-  // theta right-hand side: rhs - sum cB - sum cBsep - UB0^T y0  (fixed order per parameter)
-  const T* UB0 = (const T*)ws.ub + e0 * ns * np;
   __syncthreads();
-  for (int c = 0; c < np; ++c) {
-    double acc = 0.0;
-    for (int i = tid(); i < N; i += nthr()) {
-      acc += ws.cB[(e0 + i) * np + c];
-      if (i > 0) acc += ws.cBsep[(e0 + i) * np + c];
-      if (rthp) acc -= rthp[(e0 + i) * np + c];
+  const T* UB0 = (const T*)ws.ub + e0 * ns * np;
+  for (int c = tid(); c < np; c += nthr()) {
+    double sum = 0.0;
+    if (np <= nthr()) {
+      for (int g = 0; g < G; ++g) sum += red[g * np + c];
+    } else {
+      for (int i = 0; i < N; ++i) {
+        sum += ws.cB[(e0 + i) * np + c];
+        if (i > 0) sum += ws.cBsep[(e0 + i) * np + c];
+        if (rthp) sum -= rthp[(e0 + i) * np + c];
+      }
     }
-    acc = block_sum(acc, red);
-    if (tid() == 0) {
-      double u = 0.0;
-      for (int p = 0; p < ns; ++p) u += (double)UB0[p * np + c] * r[p];
-      rt[c] = rhs[xoff + (int64_t)N * S.b + c] - acc - u;
-    }
+    double u = 0.0;
+    for (int p = 0; p < ns; ++p) u += (double)UB0[p * np + c] * r[p];
+    rt[c] = rhs[xoff + (int64_t)N * S.b + c] - sum - u;
   }
   __syncthreads();
   if (tid() == 0) {
     trsv_l_seq(Sm, np, rt);
     trsv_lt_seq(Sm, np, rt);
-    // x_0 = L0^{-T} (y0 - UB0 x_theta)
     for (int a = 0; a < ns; ++a) {
       double v = r[a];
       for (int c = 0; c < np; ++c) v -= (double)UB0[a * np + c] * rt[c];
@@ -855,9 +880,9 @@ __global__ void k_l0_bwd(Shape S, Tab tb, Ws ws, double* __restrict__ dx) {
     double v = ws.yI[e * mI + k];
     const T* col = Q + k * R + mI;
     for (int a = 0; a < ns; ++a) v -= (double)col[a] * xs[a];
+    for (int c = 0; c < np; ++c) v -= (double)col[ns + c] * xt[c];
     if (i > 0)
-      for (int a = 0; a < ns; ++a) v -= (double)col[ns + a] * xp[a];
-    for (int c = 0; c < np; ++c) v -= (double)col[2 * ns + c] * xt[c];
+      for (int a = 0; a < ns; ++a) v -= (double)col[ns + np + a] * xp[a];
     tv[k] = v;
   }
   __syncthreads();
@@ -977,23 +1002,25 @@ int launch_assemble(const Shape& S, const Tab& tb, const Ws& ws, const double* j
 template <typename T>
 static int factor_t(const Shape& S, const Tab& tb, const HostPlan& hp, const Ws& ws, bool fused,
                     phase_cb cb, void* ctx, hipStream_t st) {
-  int nt = elem_threads(S);
-  size_t lds = level0_lds_bytes(S, sizeof(T) == 4);
   if (cb) cb(ctx, 1, 1, st);
-  hipLaunchKernelGGL(k_level0<T>, dim3((unsigned)tb.n_elem), dim3(nt), lds, st, S, tb, ws, fused ? 1 : 0);
+  if (launch_level0(S, tb, ws, sizeof(T) == 4 ? 1 : 0, fused, st)) return -4;
   if (cb) cb(ctx, 1, 0, st);
   int snt = sep_threads(S);
-  size_t clds = sizeof(double) * (3 * S.ns * S.ns + S.ns * S.np + 8);
+  const int ns = S.ns, np = S.np;
   if (cb) cb(ctx, 2, 1, st);
-  for (int l = 1; l <= tb.L; ++l) {
-    int n = hp.lvl[l];
-    if (n > 0) hipLaunchKernelGGL(k_cr<T>, dim3(n), dim3(snt), clds, st, S, tb, ws, l);
-  }
+  if (tb.L >= 1 && hp.lvl[1] > 0)
+    hipLaunchKernelGGL(k_cr_first<T>, dim3(hp.lvl[1]), dim3(snt),
+                       sizeof(double) * (3 * ns * ns + ns * np + 8), st, S, tb, ws);
+  for (int l = 1; l < tb.L; ++l)
+    if (hp.st[l] > 0)
+      hipLaunchKernelGGL(k_cr_step<T>, dim3(hp.st[l]), dim3(snt),
+                         sizeof(double) * (7 * ns * ns + 3 * ns * np + 8), st, S, tb, ws, l);
   if (cb) cb(ctx, 2, 0, st);
   if (cb) cb(ctx, 3, 1, st);
-  hipLaunchKernelGGL(k_thred, dim3(ws.nchunk, tb.n_inst), dim3(snt), 0, st, S, tb, ws);
-  size_t blds = sizeof(double) * (S.ns * S.ns + S.ns * S.np + S.np * S.np + 8);
-  hipLaunchKernelGGL(k_border<T>, dim3(tb.n_inst), dim3(snt), blds, st, S, tb, ws);
+  hipLaunchKernelGGL(k_thred, dim3(ws.nchunk, (unsigned)cl_ceil_div(np * np, 256), tb.n_inst), dim3(256),
+                     0, st, S, tb, ws);
+  hipLaunchKernelGGL(k_border<T>, dim3(tb.n_inst), dim3(snt),
+                     sizeof(double) * (2 * ns * ns + 2 * ns * np + np * np + 8), st, S, tb, ws);
   if (cb) cb(ctx, 3, 0, st);
   return ok_or();
 }
@@ -1020,11 +1047,12 @@ static int solve_t(const Shape& S, const Tab& tb, const HostPlan& hp, const Ws& 
   hipLaunchKernelGGL(k_l0_fwd<T>, dim3((unsigned)tb.n_elem), dim3(nt), sizeof(double) * S.mI, st,
                      S, tb, ws, rhs);
   size_t clds = sizeof(double) * (S.ns * S.ns + S.ns);
-  for (int l = 1; l <= tb.L; ++l) {
-    int n = hp.lvl[l];
-    if (n > 0) hipLaunchKernelGGL(k_cr_fwd<T>, dim3(n), dim3(snt), clds, st, S, tb, ws, rhs, l);
-  }
-  size_t blds = sizeof(double) * (S.ns * S.ns + S.ns + S.np + S.np * S.np);
+  if (tb.L >= 1 && hp.lvl[1] > 0)
+    hipLaunchKernelGGL(k_crf_first<T>, dim3(hp.lvl[1]), dim3(snt), clds, st, S, tb, ws, rhs);
+  for (int l = 1; l < tb.L; ++l)
+    if (hp.st[l] > 0)
+      hipLaunchKernelGGL(k_crf_step<T>, dim3(hp.st[l]), dim3(snt), clds, st, S, tb, ws, rhs, l);
+  size_t blds = sizeof(double) * (S.ns * S.ns + S.ns + S.np + S.np * S.np + 256);
   hipLaunchKernelGGL(k_border_solve<T>, dim3(tb.n_inst), dim3(256), blds, st, S, tb, ws, rhs,
                      rthp, dx);
   for (int l = tb.L; l >= 1; --l) {
@@ -1081,8 +1109,6 @@ int kkt_prepare_attrs(const Shape& S) {
   size_t l64 = level0_lds_bytes(S, 0), l32 = level0_lds_bytes(S, 1);
   size_t r = sizeof(double) * (2 * S.b + S.ns + S.K * S.nr + S.np);
   int rc = 0;
-  rc |= set_lds((const void*)k_level0<double>, l64, "k_level0<double>");
-  rc |= set_lds((const void*)k_level0<float>, l32, "k_level0<float>");
   rc |= set_lds((const void*)k_assemble<double>, l64 > r ? l64 : r, "k_assemble<double>");
   rc |= set_lds((const void*)k_assemble<float>, l32 > r ? l32 : r, "k_assemble<float>");
   return rc;

@@ -7,7 +7,8 @@ namespace cl {
 // Host copy of the static work-list sizes (grid sizes of the cyclic-reduction levels).
 struct HostPlan {
   int L;
-  int lvl[64];   // lvl[l] = work items at level l (1..L)
+  int lvl[64];   // lvl[l] = separators eliminated at level l (1..L)
+  int st[64];    // st[l] = work items of cyclic-reduction step l (1..L-1)
 };
 
 // Workgroup size of the per-element kernels: one wave for tiny elements, four otherwise.
@@ -29,7 +30,10 @@ int launch_derivs(const Shape& S, const Tab& tb, const double* x, const double* 
 // the callback (phase id, begin=1/end=0).
 typedef void (*phase_cb)(void* ctx, int phase, int begin, hipStream_t st);
 
-size_t level0_lds_bytes(const Shape& S, int prec);
+size_t level0_lds_bytes(const Shape& S, int prec);        // kkt_assemble's LDS blocks
+size_t level0r_lds_bytes(const Shape& S);
+bool level0r_supported(const Shape& S);
+int launch_level0(const Shape& S, const Tab& tb, const Ws& ws, int prec, bool fused, hipStream_t st);
 int launch_assemble(const Shape& S, const Tab& tb, const Ws& ws, const double* jac,
                     const double* hess, const double* sigma_x, const double* sigma_s,
                     const double* delta_w, const double* r_x, const double* r_s,
