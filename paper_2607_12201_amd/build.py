@@ -9,7 +9,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libcolloc.so")
-SOURCES = ["host.hip", "k_eval.hip", "k_kkt.hip", "k_level0.hip", "k_ipm.hip"]
+SOURCES = ["host.hip", "k_eval.hip", "k_kkt.hip", "k_level0.hip", "k_level0_s.hip", "k_level0_m.hip",
+           "k_level0_l.hip", "k_level0_x.hip", "k_ipm.hip"]
 ARCH = os.environ.get("COLLOC_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
@@ -41,7 +42,7 @@ def build(verbose: bool = False) -> str:
             print(r.stderr, file=sys.stderr)
         return obj
 
-    with ThreadPoolExecutor(max_workers=4) as ex:
+    with ThreadPoolExecutor(max_workers=max(1, min(8, os.cpu_count() or 1))) as ex:
         objs = list(ex.map(compile_one, SOURCES))
     tmp = OUT + ".tmp"
     cmd = [hipcc, "-shared", f"--offload-arch={ARCH}", "-fPIC", *objs, "-o", tmp]

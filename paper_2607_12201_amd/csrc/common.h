@@ -13,6 +13,8 @@
 // theta (np); R = mI + 2 ns + np rows, mI columns.
 struct Shape {
   int ns, nr, np, K, b, mI, R, Rt;
+  int lsp, lrq, lpc, mmax;      // longest per-instance lists (species->reactions, reactant
+                                // slots, parameter->reactions) and most measurements per element
   double a[CL_KMAX + 1][CL_KMAX + 1];  // a[j][k] = l_j'(tau_k)
 };
 
@@ -38,6 +40,11 @@ struct Tab {
   const int* sp_ptr;          // [n_inst][ns + 1] absolute offsets into sp_r/sp_nu
   const int* sp_r;            // reactions with nu_sr != 0, per species
   const double* sp_nu;
+  const int* rq_ptr;          // [n_inst][ns + 1] absolute offsets: reactant slots of species q
+  const int* rq_r;            //   reaction of the slot
+  const int* rq_t;            //   slot index (0/1)
+  const int* pc_ptr;          // [n_inst][np + 1] absolute offsets: reactions using parameter c
+  const int* pc_r;
   const int* rx_sp;           // [n_inst][nr][4] species with nu_sr != 0, -1 padded
   const double* rx_nu;        // [n_inst][nr][4]
   const double* z0;           // [n_inst][ns]
@@ -65,6 +72,11 @@ struct Ws {
   void* ul;                   // [n_elem][ns*ns]
   void* ur;                   // [n_elem][ns*ns]
   void* ub;                   // [n_elem][ns*np]
+  void* cTl;                  // [n_elem][ns*ns] Schur contributions of an eliminated separator:
+  void* cTr;                  //   to its left / right neighbour's block,
+  void* cE;                   //   the new coupling (right row, left column),
+  void* cGl;                  //   [n_elem][ns*np] to the neighbours' borders
+  void* cGr;
   double* dcont;              // [n_elem][ns]   continuity weight on the previous separator
   double* ath;                // [n_elem][np*np] element theta-theta block, then its Schur part
   double* thcr;               // [n_elem][np*np] theta-theta part from each separator

@@ -125,7 +125,7 @@ struct colloc_problem {
   // offsets of each table in the image
   size_t o_N, o_x, o_g, o_e0, o_ei, o_el, o_eh, o_mptr, o_msp, o_mw, o_mys, o_react, o_param,
       o_logk, o_spp, o_spr, o_spnu, o_rxs, o_rxnu, o_z0, o_lo, o_hi, o_crp, o_cri, o_crj, o_stp,
-      o_sti, o_sts;
+      o_sti, o_sts, o_rqp, o_rqr, o_rqt, o_pcp, o_pcr;
   int cr_items_max;
   Tab tab;
   bool uploaded;
@@ -284,6 +284,7 @@ extern "C" int colloc_create(const colloc_instance_desc* inst, int32_t n_inst, i
   // reaction tables
   std::vector<int> react((size_t)n_inst * nr * 2), param((size_t)n_inst * nr), spp((size_t)n_inst * (ns + 1)),
       spr, rxs((size_t)n_inst * nr * 4, -1);
+  std::vector<int> rqp((size_t)n_inst * (ns + 1)), rqr, rqt, pcp((size_t)n_inst * (np + 1)), pcr;
   std::vector<double> logk((size_t)n_inst * nr), spnu, rxnu((size_t)n_inst * nr * 4, 0.0), z0((size_t)n_inst * ns),
       lo((size_t)n_inst * np), hi((size_t)n_inst * np);
   for (int q = 0; q < n_inst; ++q) {
@@ -315,11 +316,37 @@ extern "C" int colloc_create(const colloc_instance_desc* inst, int32_t n_inst, i
         }
     }
     spp[(size_t)q * (ns + 1) + ns] = (int)spr.size();
+    for (int sp = 0; sp < ns; ++sp) {
+      rqp[(size_t)q * (ns + 1) + sp] = (int)rqr.size();
+      for (int r = 0; r < nr; ++r)
+        for (int t = 0; t < 2; ++t)
+          if (d.react[2 * r + t] == sp) {
+            rqr.push_back(r);
+            rqt.push_back(t);
+          }
+    }
+    rqp[(size_t)q * (ns + 1) + ns] = (int)rqr.size();
+    for (int c = 0; c < np; ++c) {
+      pcp[(size_t)q * (np + 1) + c] = (int)pcr.size();
+      for (int r = 0; r < nr; ++r)
+        if (d.param[r] == c) pcr.push_back(r);
+    }
+    pcp[(size_t)q * (np + 1) + np] = (int)pcr.size();
     for (int s = 0; s < ns; ++s) z0[(size_t)q * ns + s] = d.z0[s];
     for (int c = 0; c < np; ++c) {
       lo[(size_t)q * np + c] = d.theta_lo[c];
       hi[(size_t)q * np + c] = d.theta_hi[c];
     }
+  }
+  for (int q = 0; q < n_inst; ++q) {
+    S.lsp = std::max(S.lsp, spp[(size_t)q * (ns + 1) + ns] - spp[(size_t)q * (ns + 1)]);
+    S.lrq = std::max(S.lrq, rqp[(size_t)q * (ns + 1) + ns] - rqp[(size_t)q * (ns + 1)]);
+    S.lpc = std::max(S.lpc, pcp[(size_t)q * (np + 1) + np] - pcp[(size_t)q * (np + 1)]);
+  }
+  for (int64_t e = 0; e < eo; ++e) S.mmax = std::max(S.mmax, mptr[e + 1] - mptr[e]);
+  if (level0r_lds_bytes(S) > lds_limit()) {
+    delete p;
+    return COLLOC_EUNSUPPORTED;
   }
   // cyclic-reduction work lists: separator j >= 1 is eliminated at level 1 + ctz(j)
   int L = 0;
@@ -374,6 +401,11 @@ extern "C" int colloc_create(const colloc_instance_desc* inst, int32_t n_inst, i
   p->o_spr = im.add(spr.data(), sizeof(int) * spr.size());
   p->o_spnu = im.add(spnu.data(), sizeof(double) * spnu.size());
   p->o_rxs = im.add(rxs.data(), sizeof(int) * rxs.size());
+  p->o_rqp = im.add(rqp.data(), sizeof(int) * rqp.size());
+  p->o_rqr = im.add(rqr.data(), sizeof(int) * rqr.size());
+  p->o_rqt = im.add(rqt.data(), sizeof(int) * rqt.size());
+  p->o_pcp = im.add(pcp.data(), sizeof(int) * pcp.size());
+  p->o_pcr = im.add(pcr.data(), sizeof(int) * pcr.size());
   p->o_rxnu = im.add(rxnu.data(), sizeof(double) * rxnu.size());
   p->o_z0 = im.add(z0.data(), sizeof(double) * z0.size());
   p->o_lo = im.add(lo.data(), sizeof(double) * lo.size());
@@ -456,6 +488,11 @@ extern "C" int colloc_upload(colloc_problem* p, void* table_dev, hipStream_t str
   t.sp_r = (const int*)(b + p->o_spr);
   t.sp_nu = (const double*)(b + p->o_spnu);
   t.rx_sp = (const int*)(b + p->o_rxs);
+  t.rq_ptr = (const int*)(b + p->o_rqp);
+  t.rq_r = (const int*)(b + p->o_rqr);
+  t.rq_t = (const int*)(b + p->o_rqt);
+  t.pc_ptr = (const int*)(b + p->o_pcp);
+  t.pc_r = (const int*)(b + p->o_pcr);
   t.rx_nu = (const double*)(b + p->o_rxnu);
   t.z0 = (const double*)(b + p->o_z0);
   t.th_lo = (const double*)(b + p->o_lo);
@@ -467,7 +504,7 @@ extern "C" int colloc_upload(colloc_problem* p, void* table_dev, hipStream_t str
   t.st_inst = (const int*)(b + p->o_sti);
   t.st_s = (const int*)(b + p->o_sts);
   t.cr_items_max = p->cr_items_max;
-  if (kkt_prepare_attrs(p->S) != 0) return COLLOC_EHIP;
+  if (kkt_prepare_attrs(p->S) != 0 || level0_prepare_attrs(p->S) != 0) return COLLOC_EHIP;
   p->uploaded = true;
   return COLLOC_OK;
 }
@@ -531,6 +568,11 @@ static Ws ws_layout(const colloc_problem* p, int prec, void* base, size_t* bytes
   w.ul = c.take<char>(E * S.ns * S.ns, sz);
   w.ur = c.take<char>(E * S.ns * S.ns, sz);
   w.ub = c.take<char>(E * S.ns * S.np, sz);
+  w.cTl = c.take<char>(E * S.ns * S.ns, sz);
+  w.cTr = c.take<char>(E * S.ns * S.ns, sz);
+  w.cE = c.take<char>(E * S.ns * S.ns, sz);
+  w.cGl = c.take<char>(E * S.ns * S.np, sz);
+  w.cGr = c.take<char>(E * S.ns * S.np, sz);
   if (bytes) *bytes = (c.off + 255) & ~(size_t)255;
   return w;
 }

@@ -363,176 +363,8 @@ __device__ void sub_atb(double* C, int n, int m, const T* A, const T* B, int k, 
 }
 
 // ---------------------------------------------------------------- cyclic reduction levels
-// Eager cyclic reduction of the separator chain.  dss/bs hold the current separator block T_s
-// and border G_s (after level 0: the element's own Schur part; the next element's part sits
-// in tprev/gprev until the first level that touches s adds it).
-//   k_cr_first      level 1: eliminate the odd separators.
-//   k_cr_step(l)    for every s that is a multiple of 2^l: apply the updates of its two
-//                   neighbours eliminated at level l and, when s / 2^l is odd, eliminate s
-//                   (level l + 1) with couplings formed from those neighbours' factors.
-//   k_border        separator 0 and the parameter Schur complement.
-// Each separator is touched by exactly one workgroup per launch; operands are staged in LDS.
-
-// C (n x m, row-major) -= A^T B with A (k x n), B (k x m) row-major in LDS.
-__device__ void lds_sub_atb(double* C, const double* A, const double* B, int k, int n, int m,
-                            bool lower_only) {
-  for (int t = tid(); t < n * m; t += nthr()) {
-    int r = t / m, q = t - r * m;
-    if (lower_only && q > r) continue;
-    double acc = 0.0;
-    for (int p = 0; p < k; ++p) acc += A[p * n + r] * B[p * m + q];
-    C[t] -= acc;
-  }
-}
-__device__ void lds_neg_atb(double* C, const double* A, const double* B, int k, int n, int m) {
-  for (int t = tid(); t < n * m; t += nthr()) {
-    int r = t / m, q = t - r * m;
-    double acc = 0.0;
-    for (int p = 0; p < k; ++p) acc += A[p * n + r] * B[p * m + q];
-    C[t] = -acc;
-  }
-}
-
-// Factor the separator block in Tm (lower) and form UL = L^-1 EL, UR = L^-1 ER^T,
-// UB = L^-1 G; store them and the theta-theta part -UB^T UB.  Returns false if not PD.
-template <typename T>
-__device__ bool eliminate_sep(const Shape& S, const Ws& ws, int64_t ej, double* Tm, double* G,
-                              double* EL, double* ER, bool has_r, double* misc) {
-  const int ns = S.ns, np = S.np;
-  if (!chol_small(Tm, ns, misc)) return false;
-  if (has_r) {
-    for (int t = tid(); t < ns * ns; t += nthr()) {
-      int r = t / ns, q = t % ns;
-      if (q > r) {
-        double a = ER[r * ns + q], bb = ER[q * ns + r];
-        ER[r * ns + q] = bb;
-        ER[q * ns + r] = a;
-      }
-    }
-  } else {
-    for (int t = tid(); t < ns * ns; t += nthr()) ER[t] = 0.0;
-  }
-  __syncthreads();
-  trsm_l(Tm, ns, EL, ns);
-  trsm_l(Tm, ns, ER, ns);
-  trsm_l(Tm, ns, G, np);
-  __syncthreads();
-  store_blk((T*)ws.lsep + ej * ns * ns, Tm, ns * ns);
-  store_blk((T*)ws.ul + ej * ns * ns, EL, ns * ns);
-  store_blk((T*)ws.ur + ej * ns * ns, ER, ns * ns);
-  store_blk((T*)ws.ub + ej * ns * np, G, ns * np);
-  // theta-theta part from the stored (rounded) border rows, accumulated in FP64
-  double* th = ws.thcr + ej * np * np;
-  for (int t = tid(); t < np * np; t += nthr()) {
-    int r = t / np, q = t % np;
-    if (q > r) continue;
-    double acc = 0.0;
-    for (int p = 0; p < ns; ++p) acc += (double)(T)G[p * np + r] * (double)(T)G[p * np + q];
-    th[t] = -acc;
-  }
-  return true;
-}
-
-// Separator s's block and border with the next element's level-0 part added.
-template <typename T>
-__device__ void sep_initial(const Shape& S, const Ws& ws, int64_t es, bool has_next, double* Tm,
-                            double* G) {
-  const int ns = S.ns, np = S.np;
-  const T* d = (const T*)ws.dss + es * ns * ns;
-  const T* bsv = (const T*)ws.bs + es * ns * np;
-  const T* tp = (const T*)ws.tprev + (es + 1) * ns * ns;
-  const T* gp = (const T*)ws.gprev + (es + 1) * ns * np;
-  for (int t = tid(); t < ns * ns; t += nthr()) Tm[t] = (double)d[t] + (has_next ? (double)tp[t] : 0.0);
-  for (int t = tid(); t < ns * np; t += nthr()) G[t] = (double)bsv[t] + (has_next ? (double)gp[t] : 0.0);
-}
-
-// LDS: Tm (ns^2) G (ns np) EL (ns^2) ER (ns^2) misc (8)
-template <typename T>
-__global__ void k_cr_first(Shape S, Tab tb, Ws ws) {
-  extern __shared__ double lds[];
-  const int it = tb.cr_ptr[0] + blockIdx.x;
-  if (it >= tb.cr_ptr[1]) return;
-  const int inst = tb.cr_inst[it], j = tb.cr_j[it];
-  if (block_flag(&ws.flag[inst])) return;
-  const int ns = S.ns, np = S.np, N = tb.inst_N[inst];
-  const int64_t e0 = tb.inst_e0[inst], ej = e0 + j;
-  double* Tm = lds;
-  double* G = Tm + ns * ns;
-  double* EL = G + ns * np;
-  double* ER = EL + ns * ns;
-  double* misc = ER + ns * ns;
-  const bool has_r = j + 1 < N;
-  sep_initial<T>(S, ws, ej, has_r, Tm, G);
-  load_blk(EL, (const T*)ws.e1 + ej * ns * ns, ns * ns);
-  if (has_r) load_blk(ER, (const T*)ws.e1 + (ej + 1) * ns * ns, ns * ns);
-  __syncthreads();
-  if (!eliminate_sep<T>(S, ws, ej, Tm, G, EL, ER, has_r, misc))
-    if (tid() == 0) atomicOr(&ws.flag[inst], 1);
-}
-
-// LDS: Tm G EL ER (as above) + U1r U1l (ns^2) U1b (ns np) + U2r U2l (ns^2) U2b (ns np) + misc
-template <typename T>
-__global__ void k_cr_step(Shape S, Tab tb, Ws ws, int level) {
-  extern __shared__ double lds[];
-  const int it = tb.st_ptr[level - 1] + blockIdx.x;
-  if (it >= tb.st_ptr[level]) return;
-  const int inst = tb.st_inst[it], s = tb.st_s[it];
-  if (block_flag(&ws.flag[inst])) return;
-  const int ns = S.ns, np = S.np, N = tb.inst_N[inst];
-  const int64_t e0 = tb.inst_e0[inst], es = e0 + s;
-  const int half = 1 << (level - 1);
-  const int j1 = s - half, j2 = s + half;
-  const bool h1 = s > 0, h2 = j2 < N;
-  const bool elim = ((s >> level) & 1) != 0;
-  const bool has_r = elim && (s + 2 * half < N);
-  double* Tm = lds;
-  double* G = Tm + ns * ns;
-  double* EL = G + ns * np;
-  double* ER = EL + ns * ns;
-  double* U1r = ER + ns * ns;
-  double* U1l = U1r + ns * ns;
-  double* U1b = U1l + ns * ns;
-  double* U2r = U1b + ns * np;
-  double* U2l = U2r + ns * ns;
-  double* U2b = U2l + ns * ns;
-  double* misc = U2b + ns * np;
-  if (level == 1) {
-    sep_initial<T>(S, ws, es, s + 1 < N, Tm, G);
-  } else {
-    load_blk(Tm, (const T*)ws.dss + es * ns * ns, ns * ns);
-    load_blk(G, (const T*)ws.bs + es * ns * np, ns * np);
-  }
-  if (h1) {
-    load_blk(U1r, (const T*)ws.ur + (e0 + j1) * ns * ns, ns * ns);
-    load_blk(U1l, (const T*)ws.ul + (e0 + j1) * ns * ns, ns * ns);
-    load_blk(U1b, (const T*)ws.ub + (e0 + j1) * ns * np, ns * np);
-  }
-  if (h2) {
-    load_blk(U2r, (const T*)ws.ur + (e0 + j2) * ns * ns, ns * ns);
-    load_blk(U2l, (const T*)ws.ul + (e0 + j2) * ns * ns, ns * ns);
-    load_blk(U2b, (const T*)ws.ub + (e0 + j2) * ns * np, ns * np);
-  }
-  __syncthreads();
-  if (h1) {
-    lds_sub_atb(Tm, U1r, U1r, ns, ns, ns, true);
-    lds_sub_atb(G, U1r, U1b, ns, ns, np, false);
-    if (elim) lds_neg_atb(EL, U1r, U1l, ns, ns, ns);
-  }
-  __syncthreads();
-  if (h2) {
-    lds_sub_atb(Tm, U2l, U2l, ns, ns, ns, true);
-    lds_sub_atb(G, U2l, U2b, ns, ns, np, false);
-    if (has_r) lds_neg_atb(ER, U2r, U2l, ns, ns, ns);
-  }
-  __syncthreads();
-  if (!elim) {
-    store_blk((T*)ws.dss + es * ns * ns, Tm, ns * ns);
-    store_blk((T*)ws.bs + es * ns * np, G, ns * np);
-    return;
-  }
-  if (!eliminate_sep<T>(S, ws, es, Tm, G, EL, ER, has_r, misc))
-    if (tid() == 0) atomicOr(&ws.flag[inst], 1);
-}
+// The chain eliminations themselves run in the k_chain kernels (register partial Cholesky of
+// each separator's local matrix, chain_impl.h); here only the parameter-block reductions.
 
 // Theta-theta reduction, stage 1: partial sums over chunks of CL_THCHUNK elements of the
 // element Schur parts and separator parts; grid (chunk, entry tile, instance).
@@ -547,6 +379,7 @@ __global__ void k_thred(Shape S, Tab tb, Ws ws) {
   if (q > r) return;
   const int64_t e0 = tb.inst_e0[inst];
   double acc = 0.0;
+#pragma unroll 4
   for (int i = i0; i < i1; ++i) {
     acc += ws.ath[(e0 + i) * np * np + t];
     if (i > 0) acc += ws.thcr[(e0 + i) * np * np + t];
@@ -554,68 +387,21 @@ __global__ void k_thred(Shape S, Tab tb, Ws ws) {
   ws.thred[((int64_t)inst * ws.nchunk + chunk) * np * np + t] = acc;
 }
 
-// Border: the last cyclic-reduction update and elimination of separator 0, the parameter
-// Schur complement and its factor.  LDS: Tm (ns^2) G (ns np) Sm (np^2) U (ns^2) Ub (ns np) misc
-template <typename T>
-__global__ void k_border(Shape S, Tab tb, Ws ws) {
-  extern __shared__ double lds[];
-  const int inst = blockIdx.x;
-  if (block_flag(&ws.flag[inst])) return;
-  const int ns = S.ns, np = S.np, N = tb.inst_N[inst];
-  const int64_t e0 = tb.inst_e0[inst];
-  double* Tm = lds;
-  double* G = Tm + ns * ns;
-  double* Sm = G + ns * np;
-  double* U = Sm + np * np;
-  double* Ub = U + ns * ns;
-  double* misc = Ub + ns * np;
-  const int L = tb.L;
-  if (L <= 1) {
-    sep_initial<T>(S, ws, e0, N > 1, Tm, G);
-  } else {
-    load_blk(Tm, (const T*)ws.dss + e0 * ns * ns, ns * ns);
-    load_blk(G, (const T*)ws.bs + e0 * ns * np, ns * np);
-  }
-  const int jl = L >= 1 ? (1 << (L - 1)) : N;
-  if (jl < N) {
-    load_blk(U, (const T*)ws.ul + (e0 + jl) * ns * ns, ns * ns);
-    load_blk(Ub, (const T*)ws.ub + (e0 + jl) * ns * np, ns * np);
-  }
-  const int nch = (int)cl_ceil_div(N, CL_THCHUNK);
-  for (int t = tid(); t < np * np; t += nthr()) {
-    int r = t / np, q = t % np;
-    double acc = 0.0;
-    if (q <= r)
-      for (int c = 0; c < nch; ++c) acc += ws.thred[((int64_t)inst * ws.nchunk + c) * np * np + t];
-    Sm[t] = acc + (r == q ? ws.sxdw[inst * np + r] : 0.0);
-  }
-  __syncthreads();
-  if (jl < N) {
-    lds_sub_atb(Tm, U, U, ns, ns, ns, true);
-    lds_sub_atb(G, U, Ub, ns, ns, np, false);
-  }
-  __syncthreads();
-  if (!chol_small(Tm, ns, misc)) {
-    if (tid() == 0) atomicOr(&ws.flag[inst], 1);
-    return;
-  }
-  trsm_l(Tm, ns, G, np);
-  __syncthreads();
-  store_blk((T*)ws.lsep + e0 * ns * ns, Tm, ns * ns);
-  store_blk((T*)ws.ub + e0 * ns * np, G, ns * np);
-  for (int t = tid(); t < np * np; t += nthr()) {
-    int r = t / np, q = t % np;
-    if (q > r) continue;
-    double acc = 0.0;
-    for (int p = 0; p < ns; ++p) acc += (double)(T)G[p * np + r] * (double)(T)G[p * np + q];
-    Sm[t] -= acc;
-  }
-  __syncthreads();
-  if (!chol_small(Sm, np, misc)) {
-    if (tid() == 0) atomicOr(&ws.flag[inst], 1);
-    return;
-  }
-  for (int t = tid(); t < np * np; t += nthr()) ws.S[(int64_t)inst * np * np + t] = Sm[t];
+// Theta-theta reduction, stage 2: the reduced parameter block S = sum of the chunk partials
+// + Sx + dw on the diagonal (lower triangle); grid (entry tile, instance).
+__global__ void k_thred2(Shape S, Tab tb, Ws ws) {
+  const int inst = blockIdx.y;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int np = S.np;
+  if (t >= np * np || ws.flag[inst]) return;
+  const int r = t / np, q = t % np;
+  if (q > r) return;
+  const int nch = (int)cl_ceil_div(tb.inst_N[inst], CL_THCHUNK);
+  const double* src = ws.thred + (int64_t)inst * ws.nchunk * np * np + t;
+  double acc = 0.0;
+#pragma unroll 8
+  for (int c = 0; c < nch; ++c) acc += src[(int64_t)c * np * np];
+  ws.S[(int64_t)inst * np * np + t] = acc + (r == q ? ws.sxdw[inst * np + r] : 0.0);
 }
 
 __global__ void k_clear_flags(Ws ws, int n) {
@@ -1005,22 +791,19 @@ static int factor_t(const Shape& S, const Tab& tb, const HostPlan& hp, const Ws&
   if (cb) cb(ctx, 1, 1, st);
   if (launch_level0(S, tb, ws, sizeof(T) == 4 ? 1 : 0, fused, st)) return -4;
   if (cb) cb(ctx, 1, 0, st);
-  int snt = sep_threads(S);
-  const int ns = S.ns, np = S.np;
+  const int np = S.np;
+  const int prec = sizeof(T) == 4 ? 1 : 0;
   if (cb) cb(ctx, 2, 1, st);
-  if (tb.L >= 1 && hp.lvl[1] > 0)
-    hipLaunchKernelGGL(k_cr_first<T>, dim3(hp.lvl[1]), dim3(snt),
-                       sizeof(double) * (3 * ns * ns + ns * np + 8), st, S, tb, ws);
-  for (int l = 1; l < tb.L; ++l)
-    if (hp.st[l] > 0)
-      hipLaunchKernelGGL(k_cr_step<T>, dim3(hp.st[l]), dim3(snt),
-                         sizeof(double) * (7 * ns * ns + 3 * ns * np + 8), st, S, tb, ws, l);
+  int rc = 0;
+  if (tb.L >= 1) rc |= launch_chain(S, tb, ws, prec, 0, 1, hp.lvl[1], st);
+  for (int l = 1; l < tb.L; ++l) rc |= launch_chain(S, tb, ws, prec, 1, l, hp.st[l], st);
   if (cb) cb(ctx, 2, 0, st);
   if (cb) cb(ctx, 3, 1, st);
-  hipLaunchKernelGGL(k_thred, dim3(ws.nchunk, (unsigned)cl_ceil_div(np * np, 256), tb.n_inst), dim3(256),
-                     0, st, S, tb, ws);
-  hipLaunchKernelGGL(k_border<T>, dim3(tb.n_inst), dim3(snt),
-                     sizeof(double) * (2 * ns * ns + 2 * ns * np + np * np + 8), st, S, tb, ws);
+  const unsigned tiles = (unsigned)cl_ceil_div(np * np, 256);
+  hipLaunchKernelGGL(k_thred, dim3(ws.nchunk, tiles, tb.n_inst), dim3(256), 0, st, S, tb, ws);
+  hipLaunchKernelGGL(k_thred2, dim3(tiles, tb.n_inst), dim3(256), 0, st, S, tb, ws);
+  rc |= launch_chain(S, tb, ws, prec, 2, 0, tb.n_inst, st);
+  if (rc) return -4;
   if (cb) cb(ctx, 3, 0, st);
   return ok_or();
 }

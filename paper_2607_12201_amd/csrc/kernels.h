@@ -34,6 +34,9 @@ size_t level0_lds_bytes(const Shape& S, int prec);        // kkt_assemble's LDS 
 size_t level0r_lds_bytes(const Shape& S);
 bool level0r_supported(const Shape& S);
 int launch_level0(const Shape& S, const Tab& tb, const Ws& ws, int prec, bool fused, hipStream_t st);
+int level0_prepare_attrs(const Shape& S);
+int launch_chain(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level,
+                 unsigned grid, hipStream_t st);
 int launch_assemble(const Shape& S, const Tab& tb, const Ws& ws, const double* jac,
                     const double* hess, const double* sigma_x, const double* sigma_s,
                     const double* delta_w, const double* r_x, const double* r_s,

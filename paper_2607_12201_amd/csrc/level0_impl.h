@@ -1,0 +1,354 @@
+// Level-0 element kernel template (included by the k_level0*.hip translation units).
+#pragma once
+// Level 0 of the factorization: every finite element, in parallel, assembles its block of the
+// condensed KKT matrix and eliminates its interior collocation nodes 0..K-1.
+//
+// The element's symmetric matrix over [I (nodes 0..K-1) | S (node K) | theta | P (previous
+// element's node K)] lives in registers: a TS x TS thread grid owns the lower-triangle
+// entries block-cyclically (thread (ty, tx) owns rows ty + TS*I and columns tx + TS*J), so the
+// assembly accumulates every entry in a register and the right-looking elimination of the mI
+// interior columns only exchanges one column per step through LDS.  After the mI steps the
+// remaining entries are the Schur complement on (S, theta, P): the separator-chain blocks and
+// the element's parameter-border contribution.  Panel (L_I and the eliminated rows) is stored
+// column-major with ld = R for the solve.
+#include "kernels.h"
+#include "elem.h"
+#include "regchol.h"
+
+namespace cl {
+
+// Per-instance tables and the element's measurements staged in LDS (relative list offsets).
+struct LTab {
+  int *react, *param, *sp_ptr, *sp_r, *rq_ptr, *rq_r, *rq_t, *pc_ptr, *pc_r, *msp, *jdiv;
+  double *sp_nu, *mw;
+  int nmeas;
+};
+
+__device__ inline void stage_tables(const Shape& S, const Tab& tb, int inst, int64_t e, LTab& L) {
+  const int ns = S.ns, np = S.np, nr = S.nr, K = S.K;
+  for (int t = tid(); t < 2 * nr; t += nthr()) L.react[t] = tb.react[inst * nr * 2 + t];
+  for (int t = tid(); t < nr; t += nthr()) L.param[t] = tb.param[inst * nr + t];
+  const int sp0 = tb.sp_ptr[inst * (ns + 1)], rq0 = tb.rq_ptr[inst * (ns + 1)];
+  const int pc0 = tb.pc_ptr[inst * (np + 1)];
+  for (int t = tid(); t <= ns; t += nthr()) {
+    L.sp_ptr[t] = tb.sp_ptr[inst * (ns + 1) + t] - sp0;
+    L.rq_ptr[t] = tb.rq_ptr[inst * (ns + 1) + t] - rq0;
+  }
+  for (int t = tid(); t <= np; t += nthr()) L.pc_ptr[t] = tb.pc_ptr[inst * (np + 1) + t] - pc0;
+  const int nsp = tb.sp_ptr[inst * (ns + 1) + ns] - sp0;
+  const int nrq = tb.rq_ptr[inst * (ns + 1) + ns] - rq0;
+  const int npc = tb.pc_ptr[inst * (np + 1) + np] - pc0;
+  for (int t = tid(); t < nsp; t += nthr()) {
+    L.sp_r[t] = tb.sp_r[sp0 + t];
+    L.sp_nu[t] = tb.sp_nu[sp0 + t];
+  }
+  for (int t = tid(); t < nrq; t += nthr()) {
+    L.rq_r[t] = tb.rq_r[rq0 + t];
+    L.rq_t[t] = tb.rq_t[rq0 + t];
+  }
+  for (int t = tid(); t < npc; t += nthr()) L.pc_r[t] = tb.pc_r[pc0 + t];
+  const int m0 = tb.elem_mptr[e], m1 = tb.elem_mptr[e + 1];
+  L.nmeas = m1 - m0;
+  for (int t = tid(); t < m1 - m0; t += nthr()) L.msp[t] = tb.meas_sp[m0 + t];
+  for (int t = tid(); t < (m1 - m0) * (K + 1); t += nthr()) L.mw[t] = tb.meas_w[(int64_t)m0 * (K + 1) + t];
+  for (int t = tid(); t < S.R; t += nthr()) L.jdiv[t] = t / ns;
+}
+
+// node-0 rows (initial condition / continuity), measurement Hessian, dw on z; P couplings.
+__device__ inline double base_entry(const Shape& S, const LTab& L, int i, double dw,
+                                    const double* d0, int r, int q) {
+  const int ns = S.ns, b = S.b, K = S.K, bp = S.b + S.np;
+  if (r >= bp) {  // P row: previous separator, coupled by the continuity rows (eq. 2c)
+    const int s = r - bp;
+    if (i == 0) return 0.0;
+    if (q < bp) return (q == s) ? -d0[s] : 0.0;
+    return (q == r) ? d0[s] : 0.0;
+  }
+  if (r >= b) return 0.0;   // theta rows: parameter bounds and dw are added once per instance
+  const int j1 = L.jdiv[r], s1 = r - j1 * ns, j2 = L.jdiv[q], s2 = q - j2 * ns;
+  double v = (r == q) ? dw : 0.0;
+  if (s1 != s2) return v;
+  if (j1 == 0 && j2 == 0) v += d0[s1];
+  for (int m = 0; m < L.nmeas; ++m)
+    if (L.msp[m] == s1) {
+      const double* w = L.mw + m * (K + 1);
+      v += w[j1] * w[j2];
+    }
+  return v;
+}
+
+// Per-point tables of the collocation rows of point k (eq. 2b / 3).  The rows are
+// a_jk e_(j,s) - h (F_k)_(s,.) on node k and -h (Fth_k)_(s,.) on theta, weighted by d_(k,s);
+// with HF = h d F, HFt = h d Fth and the products Q1 = h^2 F^T D F + Wzz,
+// Q2 = h^2 F^T D Fth + Wzt, Q3 = h^2 Fth^T D Fth + diag(Wtt), each entry of their
+// contribution needs a few lookups.
+struct NodeTab {
+  double *d, *F, *Fth, *Wzz, *Wzt, *Wtt, *HF, *HFt, *Q1, *Q2, *Q3;
+};
+
+__device__ inline double node_entry(const Shape& S, const LTab& L, int k, const NodeTab& nt, int r,
+                                   int q) {
+  const int ns = S.ns, np = S.np, b = S.b;
+  if (r < b) {
+    const int j1 = L.jdiv[r], s1 = r - j1 * ns, j2 = L.jdiv[q], s2 = q - j2 * ns;
+    double a1 = S.a[j1][k], a2 = S.a[j2][k];
+    double v = 0.0;
+    if (s1 == s2) v += nt.d[s1] * a1 * a2;
+    if (j2 == k) v -= a1 * nt.HF[s1 * ns + s2];
+    if (j1 == k) v -= a2 * nt.HF[s2 * ns + s1];
+    if (j1 == k && j2 == k) v += nt.Q1[s1 * ns + s2];
+    return v;
+  }
+  if (q < b) {
+    const int c = r - b, j1 = L.jdiv[q], s1 = q - j1 * ns;
+    double v = -S.a[j1][k] * nt.HFt[s1 * np + c];
+    if (j1 == k) v += nt.Q2[s1 * np + c];
+    return v;
+  }
+  return nt.Q3[(r - b) * np + (q - b)];
+}
+
+// Build the tables of point k from the element's staged derivative values (jv, hv) and Ds.
+__device__ inline void node_tables(const Shape& S, const LTab& L, int k, double h,
+                                   const double* jv, const double* hv, const double* Ds_e,
+                                   const NodeTab& nt) {
+  const int ns = S.ns, np = S.np, nr = S.nr;
+  for (int s = tid(); s < ns; s += nthr()) {
+    nt.d[s] = Ds_e[k * ns + s];
+    double* Fr = nt.F + s * ns;
+    double* Ftr = nt.Fth + s * np;
+    for (int q = 0; q < ns; ++q) Fr[q] = 0.0;
+    for (int c = 0; c < np; ++c) Ftr[c] = 0.0;
+    for (int q = L.sp_ptr[s]; q < L.sp_ptr[s + 1]; ++q) {
+      const int r = L.sp_r[q];
+      const double nu = L.sp_nu[q];
+      const double* jr = jv + ((k - 1) * nr + r) * 3;
+      const int q0 = L.react[2 * r], q1 = L.react[2 * r + 1], c = L.param[r];
+      if (q0 >= 0) Fr[q0] += nu * jr[0];
+      if (q1 >= 0) Fr[q1] += nu * jr[1];
+      if (c >= 0) Ftr[c] += nu * jr[2];
+    }
+  }
+  for (int q = tid(); q < ns; q += nthr()) {
+    double* Wr = nt.Wzz + q * ns;
+    double* Wtr = nt.Wzt + q * np;
+    for (int s2 = 0; s2 < ns; ++s2) Wr[s2] = 0.0;
+    for (int c = 0; c < np; ++c) Wtr[c] = 0.0;
+    for (int o = L.rq_ptr[q]; o < L.rq_ptr[q + 1]; ++o) {
+      const int r = L.rq_r[o], t = L.rq_t[o];
+      const int other = L.react[2 * r + (1 - t)], c = L.param[r];
+      const double* H = hv + ((k - 1) * nr + r) * 4;
+      if (other >= 0) Wr[other] += H[0];
+      if (c >= 0) Wtr[c] += H[1 + t];
+    }
+  }
+  for (int c = tid(); c < np; c += nthr()) {
+    double acc = 0.0;
+    for (int o = L.pc_ptr[c]; o < L.pc_ptr[c + 1]; ++o) acc += hv[((k - 1) * nr + L.pc_r[o]) * 4 + 3];
+    nt.Wtt[c] = acc;
+  }
+  __syncthreads();
+  for (int t = tid(); t < ns * ns; t += nthr()) {
+    int s = t / ns;
+    nt.HF[t] = h * nt.d[s] * nt.F[t];
+  }
+  for (int t = tid(); t < ns * np; t += nthr()) {
+    int s = t / np;
+    nt.HFt[t] = h * nt.d[s] * nt.Fth[t];
+  }
+  const double h2 = h * h;
+  const int n1 = ns * ns, n2 = ns * np, n3 = np * np;
+  for (int t = tid(); t < n1 + n2 + n3; t += nthr()) {
+    if (t < n1) {
+      int s1 = t / ns, s2 = t - s1 * ns;
+      if (s2 > s1) continue;
+      double acc = 0.0;
+      for (int s = 0; s < ns; ++s) acc += nt.d[s] * nt.F[s * ns + s1] * nt.F[s * ns + s2];
+      nt.Q1[t] = h2 * acc + nt.Wzz[t];
+    } else if (t < n1 + n2) {
+      int u = t - n1, s1 = u / np, c = u - s1 * np;
+      double acc = 0.0;
+      for (int s = 0; s < ns; ++s) acc += nt.d[s] * nt.F[s * ns + s1] * nt.Fth[s * np + c];
+      nt.Q2[u] = h2 * acc + nt.Wzt[u];
+    } else {
+      int u = t - n1 - n2, c1 = u / np, c2 = u - c1 * np;
+      if (c2 > c1) continue;
+      double acc = 0.0;
+      for (int s = 0; s < ns; ++s) acc += nt.d[s] * nt.Fth[s * np + c1] * nt.Fth[s * np + c2];
+      nt.Q3[u] = h2 * acc + (c1 == c2 ? nt.Wtt[c1] : 0.0);
+    }
+  }
+}
+
+// Stored value of entry (r, q) of the assembled matrix (kkt_assemble's block storage).
+template <typename T>
+__device__ inline double stored_entry(const Shape& S, const Ws& ws, int64_t e, int r, int q) {
+  const int ns = S.ns, np = S.np, b = S.b, mI = S.mI, R = S.R, bp = S.b + S.np;
+  if (q < mI) return (double)((const T*)ws.panel)[e * (int64_t)R * mI + (int64_t)q * R + r];
+  if (r < b) return (double)((const T*)ws.dss)[e * ns * ns + (r - mI) * ns + (q - mI)];
+  if (r < bp) {
+    if (q < b) return (double)((const T*)ws.bs)[e * ns * np + (q - mI) * np + (r - b)];
+    return ws.ath[e * np * np + (r - b) * np + (q - b)];
+  }
+  return (r == q) ? ws.dcont[e * ns + (r - bp)] : 0.0;
+}
+
+// Panel columns and the Schur complement on (S, theta, P) from the register entries.
+template <typename T, int TS, int NB>
+__device__ inline void store_regs(const Shape& S, const Ws& ws, int64_t e, int i, const T* acc,
+                                  int ty, int tx) {
+  const int ns = S.ns, np = S.np, b = S.b, mI = S.mI, R = S.R, bp = S.b + S.np;
+  T* Qg = (T*)ws.panel + e * (int64_t)R * mI;
+  T* dss = (T*)ws.dss + e * ns * ns;
+  T* bsv = (T*)ws.bs + e * ns * np;
+  T* tprev = (T*)ws.tprev + e * ns * ns;
+  T* e1 = (T*)ws.e1 + e * ns * ns;
+  T* gprev = (T*)ws.gprev + e * ns * np;
+  double* ath = ws.ath + e * np * np;
+#pragma unroll
+  for (int I = 0; I < NB; ++I)
+#pragma unroll
+    for (int J = 0; J <= I; ++J) {
+      const int r = I * TS + ty, q = J * TS + tx;
+      if (!(r < R && q <= r)) continue;
+      const T v = acc[I * (I + 1) / 2 + J];
+      if (q < mI) {
+        Qg[(int64_t)q * R + r] = v;
+      } else if (r < b) {
+        dss[(r - mI) * ns + (q - mI)] = v;
+      } else if (r < bp) {
+        if (q < b) bsv[(q - mI) * np + (r - b)] = v;
+        else if (sizeof(T) == 8) ath[(r - b) * np + (q - b)] = (double)v;
+      } else if (i > 0) {
+        const int pr = r - bp;
+        if (q < b) e1[(q - mI) * ns + pr] = v;
+        else if (q < bp) gprev[pr * np + (q - b)] = v;
+        else tprev[pr * ns + (q - bp)] = v;
+      }
+    }
+}
+
+template <typename T, int TS, int NB>
+__global__ void __launch_bounds__(TS* TS) k_level0r(Shape S, Tab tb, Ws ws, int fused) {
+  extern __shared__ double lds[];
+  constexpr int NBLK = NB * (NB + 1) / 2;
+  const int64_t e = blockIdx.x;
+  const int inst = tb.elem_inst[e], i = tb.elem_loc[e];
+  if (block_flag(&ws.flag[inst])) return;
+  const int ns = S.ns, np = S.np, b = S.b, R = S.R, bp = S.b + S.np;
+  const int ty = threadIdx.x / TS, tx = threadIdx.x % TS;
+  const int jl = S.K * S.nr;
+  double* pbuf = lds;                 // 2 R 4
+  double* misc = pbuf + 8 * R;        // 8
+  double* d0 = misc + 8;              // b (Ds of the element's rows)
+  double* jv = d0 + b;                // 3 K nr
+  double* hv = jv + 3 * jl;           // 4 K nr
+  NodeTab nt;
+  nt.d = hv + 4 * jl;
+  nt.F = nt.d + ns;
+  nt.Fth = nt.F + ns * ns;
+  nt.Wzz = nt.Fth + ns * np;
+  nt.Wzt = nt.Wzz + ns * ns;
+  nt.Wtt = nt.Wzt + ns * np;
+  nt.HF = nt.Wtt + np;
+  nt.HFt = nt.HF + ns * ns;
+  nt.Q1 = nt.HFt + ns * np;
+  nt.Q2 = nt.Q1 + ns * ns;
+  nt.Q3 = nt.Q2 + ns * np;
+  LTab L;
+  L.sp_nu = nt.Q3 + np * np;
+  L.mw = L.sp_nu + S.lsp;
+  int* ib = (int*)(L.mw + S.mmax * (S.K + 1));
+  L.react = ib;
+  L.param = L.react + 2 * S.nr;
+  L.sp_ptr = L.param + S.nr;
+  L.rq_ptr = L.sp_ptr + ns + 1;
+  L.pc_ptr = L.rq_ptr + ns + 1;
+  L.sp_r = L.pc_ptr + np + 1;
+  L.rq_r = L.sp_r + S.lsp;
+  L.rq_t = L.rq_r + S.lrq;
+  L.pc_r = L.rq_t + S.lrq;
+  L.msp = L.pc_r + S.lpc;
+  L.jdiv = L.msp + S.mmax;
+  double av[NBLK];
+
+  if (fused) {
+    const int64_t gi = tb.inst_g[inst] + (int64_t)i * b;
+    const double h = tb.elem_h[e], dw = ws.dw[inst];
+    for (int t = tid(); t < b; t += nthr()) d0[t] = ws.Ds[gi + t];
+    for (int t = tid(); t < 3 * jl; t += nthr()) jv[t] = ws.jac[e * 3 * jl + t];
+    for (int t = tid(); t < 4 * jl; t += nthr()) hv[t] = ws.hess[e * 4 * jl + t];
+    stage_tables(S, tb, inst, e, L);
+    __syncthreads();
+#pragma unroll
+    for (int I = 0; I < NB; ++I)
+#pragma unroll
+      for (int J = 0; J <= I; ++J) {
+        const int r = I * TS + ty, q = J * TS + tx;
+        av[I * (I + 1) / 2 + J] = (r < R && q <= r) ? base_entry(S, L, i, dw, d0, r, q) : 0.0;
+      }
+    for (int k = 1; k <= S.K; ++k) {
+      __syncthreads();
+      node_tables(S, L, k, h, jv, hv, d0, nt);
+      __syncthreads();
+#pragma unroll
+      for (int I = 0; I < NB; ++I)
+#pragma unroll
+        for (int J = 0; J <= I; ++J) {
+          const int r = I * TS + ty, q = J * TS + tx;
+          if (r < bp && q <= r) av[I * (I + 1) / 2 + J] += node_entry(S, L, k, nt, r, q);
+        }
+    }
+    if (sizeof(T) == 4) {  // FP32 factors: keep the assembled theta-theta block in FP64
+#pragma unroll
+      for (int I = 0; I < NB; ++I)
+#pragma unroll
+        for (int J = 0; J <= I; ++J) {
+          const int r = I * TS + ty, q = J * TS + tx;
+          if (r >= b && r < bp && q >= b && q <= r)
+            ws.ath[e * np * np + (r - b) * np + (q - b)] = av[I * (I + 1) / 2 + J];
+        }
+    }
+    __syncthreads();
+  } else {
+#pragma unroll
+    for (int I = 0; I < NB; ++I)
+#pragma unroll
+      for (int J = 0; J <= I; ++J) {
+        const int r = I * TS + ty, q = J * TS + tx;
+        av[I * (I + 1) / 2 + J] = (r < R && q <= r) ? stored_entry<T>(S, ws, e, r, q) : 0.0;
+      }
+  }
+  const int mI = S.mI;
+
+  bool ok;
+  if constexpr (sizeof(T) == 8) {
+    ok = eliminate_regs<double, TS, NB>(av, mI, R, ty, tx, pbuf, misc);
+    if (ok) store_regs<double, TS, NB>(S, ws, e, i, av, ty, tx);
+  } else {
+    float af[NBLK];
+#pragma unroll
+    for (int B = 0; B < NBLK; ++B) af[B] = (float)av[B];
+    ok = eliminate_regs<float, TS, NB>(af, mI, R, ty, tx, pbuf, misc);
+    if (ok) store_regs<float, TS, NB>(S, ws, e, i, af, ty, tx);
+  }
+  if (!ok) {
+    if (tid() == 0) atomicOr(&ws.flag[inst], 1);
+    return;
+  }
+  if (sizeof(T) == 4) {
+    // FP64 parameter Schur part from the FP32 eliminated rows: ath -= X_B^T X_B
+    const T* Qg = (const T*)ws.panel + e * (int64_t)R * mI;
+    double* ath = ws.ath + e * np * np;
+    __syncthreads();
+    for (int t = tid(); t < np * np; t += nthr()) {
+      int r = t / np, q = t % np;
+      if (q > r) continue;
+      double sum = 0.0;
+      for (int k = 0; k < mI; ++k) sum += (double)Qg[(int64_t)k * R + b + r] * (double)Qg[(int64_t)k * R + b + q];
+      ath[t] -= sum;
+    }
+  }
+}
+
+}  // namespace cl
