@@ -12,8 +12,8 @@ void launch_level0_16_5(const Shape& S, const Tab& tb, const Ws& ws, int prec, i
 void launch_level0_16_6(const Shape& S, const Tab& tb, const Ws& ws, int prec, int fused, hipStream_t st);
 void launch_level0_16_7(const Shape& S, const Tab& tb, const Ws& ws, int prec, int fused, hipStream_t st);
 void launch_level0_16_8(const Shape& S, const Tab& tb, const Ws& ws, int prec, int fused, hipStream_t st);
-void launch_level0_16_9(const Shape& S, const Tab& tb, const Ws& ws, int prec, int fused, hipStream_t st);
-void launch_level0_16_10(const Shape& S, const Tab& tb, const Ws& ws, int prec, int fused, hipStream_t st);
+void launch_level0_24_6(const Shape& S, const Tab& tb, const Ws& ws, int prec, int fused, hipStream_t st);
+void launch_level0_24_7(const Shape& S, const Tab& tb, const Ws& ws, int prec, int fused, hipStream_t st);
 
 int attrs_level0_8_1(size_t bytes);
 int attrs_level0_8_2(size_t bytes);
@@ -25,8 +25,8 @@ int attrs_level0_16_5(size_t bytes);
 int attrs_level0_16_6(size_t bytes);
 int attrs_level0_16_7(size_t bytes);
 int attrs_level0_16_8(size_t bytes);
-int attrs_level0_16_9(size_t bytes);
-int attrs_level0_16_10(size_t bytes);
+int attrs_level0_24_6(size_t bytes);
+int attrs_level0_24_7(size_t bytes);
 
 void launch_chain_8_1(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level, unsigned grid, size_t lds, hipStream_t st);
 void launch_chain_8_2(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level, unsigned grid, size_t lds, hipStream_t st);
@@ -38,8 +38,8 @@ void launch_chain_16_5(const Shape& S, const Tab& tb, const Ws& ws, int prec, in
 void launch_chain_16_6(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level, unsigned grid, size_t lds, hipStream_t st);
 void launch_chain_16_7(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level, unsigned grid, size_t lds, hipStream_t st);
 void launch_chain_16_8(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level, unsigned grid, size_t lds, hipStream_t st);
-void launch_chain_16_9(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level, unsigned grid, size_t lds, hipStream_t st);
-void launch_chain_16_10(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level, unsigned grid, size_t lds, hipStream_t st);
+void launch_chain_24_6(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level, unsigned grid, size_t lds, hipStream_t st);
+void launch_chain_24_7(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level, unsigned grid, size_t lds, hipStream_t st);
 
 size_t level0r_lds_bytes(const Shape& S) {
   const size_t ns = S.ns, np = S.np, jl = (size_t)S.K * S.nr;
@@ -62,6 +62,13 @@ int launch_level0(const Shape& S, const Tab& tb, const Ws& ws, int prec, bool fu
       case 4: launch_level0_8_4(S, tb, ws, prec, f, st); return 0;
     }
   }
+  if (S.R > 128) {
+    switch ((int)cl_ceil_div(S.R, 24)) {
+      case 6: launch_level0_24_6(S, tb, ws, prec, f, st); return 0;
+      case 7: launch_level0_24_7(S, tb, ws, prec, f, st); return 0;
+    }
+    return -1;
+  }
   switch ((int)cl_ceil_div(S.R, 16)) {
     case 3: launch_level0_16_3(S, tb, ws, prec, f, st); return 0;
     case 4: launch_level0_16_4(S, tb, ws, prec, f, st); return 0;
@@ -69,8 +76,6 @@ int launch_level0(const Shape& S, const Tab& tb, const Ws& ws, int prec, bool fu
     case 6: launch_level0_16_6(S, tb, ws, prec, f, st); return 0;
     case 7: launch_level0_16_7(S, tb, ws, prec, f, st); return 0;
     case 8: launch_level0_16_8(S, tb, ws, prec, f, st); return 0;
-    case 9: launch_level0_16_9(S, tb, ws, prec, f, st); return 0;
-    case 10: launch_level0_16_10(S, tb, ws, prec, f, st); return 0;
   }
   return -1;
 }
@@ -86,6 +91,13 @@ int level0_prepare_attrs(const Shape& S) {
       case 4: return attrs_level0_8_4(by);
     }
   }
+  if (S.R > 128) {
+    switch ((int)cl_ceil_div(S.R, 24)) {
+      case 6: return attrs_level0_24_6(by);
+      case 7: return attrs_level0_24_7(by);
+    }
+    return -1;
+  }
   switch ((int)cl_ceil_div(S.R, 16)) {
     case 3: return attrs_level0_16_3(by);
     case 4: return attrs_level0_16_4(by);
@@ -93,8 +105,6 @@ int level0_prepare_attrs(const Shape& S) {
     case 6: return attrs_level0_16_6(by);
     case 7: return attrs_level0_16_7(by);
     case 8: return attrs_level0_16_8(by);
-    case 9: return attrs_level0_16_9(by);
-    case 10: return attrs_level0_16_10(by);
   }
   return -1;
 }
@@ -111,6 +121,13 @@ int launch_chain(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode
       case 4: launch_chain_8_4(S, tb, ws, prec, mode, level, grid, lds, st); return 0;
     }
   }
+  if (Rl > 128) {
+    switch ((int)cl_ceil_div(Rl, 24)) {
+      case 6: launch_chain_24_6(S, tb, ws, prec, mode, level, grid, lds, st); return 0;
+      case 7: launch_chain_24_7(S, tb, ws, prec, mode, level, grid, lds, st); return 0;
+    }
+    return -1;
+  }
   switch ((int)cl_ceil_div(Rl, 16)) {
     case 3: launch_chain_16_3(S, tb, ws, prec, mode, level, grid, lds, st); return 0;
     case 4: launch_chain_16_4(S, tb, ws, prec, mode, level, grid, lds, st); return 0;
@@ -118,8 +135,6 @@ int launch_chain(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode
     case 6: launch_chain_16_6(S, tb, ws, prec, mode, level, grid, lds, st); return 0;
     case 7: launch_chain_16_7(S, tb, ws, prec, mode, level, grid, lds, st); return 0;
     case 8: launch_chain_16_8(S, tb, ws, prec, mode, level, grid, lds, st); return 0;
-    case 9: launch_chain_16_9(S, tb, ws, prec, mode, level, grid, lds, st); return 0;
-    case 10: launch_chain_16_10(S, tb, ws, prec, mode, level, grid, lds, st); return 0;
   }
   return -1;
 }
