@@ -72,6 +72,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="before the timed region, copy a buffer of this size once (a plain "
+                         "copy kernel of known traffic for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -92,6 +95,13 @@ def main():
     for _ in range(args.warmup):
         P.ipm_step(state, ws, opts)
     torch.cuda.synchronize()
+    if args.calib_copy_mib:
+        n = args.calib_copy_mib * 2 ** 20 // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     P.ipm_init(x0d, state, ws, opts)          # timed region starts from the same point
     torch.cuda.synchronize()
     it0 = int(P.info(state)[0]["iter"])

@@ -59,9 +59,12 @@ def test_init_matches_oracle(torch):
 @pytest.mark.parametrize("name,tau_r,same_path", [("ab20", 1e-8, True), ("ab20", 1e-4, True),
                                                   ("tiny", 1e-6, True), ("ragged37", 1e-6, False)])
 def test_solve_matches_oracle(torch, name, tau_r, same_path):
-    """same_path: the iteration count must agree too.  On ill-conditioned instances rounding
-    differences of the two elimination orders can flip a line-search decision; there only the
-    outcome (status, final parameters) is compared."""
+    """same_path: the iteration count must agree too, and the final parameters within 1e-6.
+    On ill-conditioned instances rounding differences of the two elimination orders can flip a
+    line-search decision; the two runs then stop at different points of the tolerance region,
+    and along sloppy parameter directions (nearly unidentifiable rates) those points differ by
+    far more than 1e-6 in theta.  There the outcome is compared: status, and the final
+    objective within 1e-8 relative, the gap two 1e-6-stationary points can have."""
     announce(f"ipm solve {name} tau_r={tau_r}")
     inst = CASES[name]()
     m = problem.Model(inst, 3)
@@ -76,7 +79,10 @@ def test_solve_matches_oracle(torch, name, tau_r, same_path):
     assert info["status"] == st_o.status
     if same_path:
         assert info["iter"] == st_o.it
-    assert np.max(np.abs(th - st_o.x[m.nz:]) / np.maximum(1.0, np.abs(st_o.x[m.nz:]))) < 1e-6
+        assert np.max(np.abs(th - st_o.x[m.nz:]) / np.maximum(1.0, np.abs(st_o.x[m.nz:]))) < 1e-6
+    else:
+        phi_o = m.objective(st_o.x)
+        assert abs(info["obj"] - phi_o) <= 1e-8 * max(1.0, abs(phi_o)), (info["obj"], phi_o)
 
 
 def test_first_iterate_matches_oracle(torch):
