@@ -109,9 +109,9 @@ typedef struct colloc_ipm_opts {
   double gamma_theta, gamma_phi, s_theta, s_phi, eta_phi, delta_sw, gamma_alpha;
   int32_t max_ls;              /* backtracking trials per iteration, <= COLLOC_MAX_LS */
   int32_t precision;           /* COLLOC_FP64 or COLLOC_FP32_IR */
-  int32_t ir_max;              /* refinement sweeps in FP32_IR mode */
+  int32_t ir_max;              /* refinement sweeps in FP32_IR mode (default 10) */
   int32_t pad_;
-  double ir_tol;               /* backward-error target of the refinement */
+  double ir_tol;               /* relative correction target of the refinement (1e-14) */
 } colloc_ipm_opts;
 
 #define COLLOC_MAX_LS 48
@@ -125,7 +125,8 @@ typedef struct colloc_ipm_info {
   double alpha_pr, alpha_du, obj, inf_pr;
   double inf_du, E0, theta_cv, phi;
   double theta_max, theta_min, dphi, alpha_min;
-  double Emu, s_d, s_c, resv_;
+  double Emu, s_d, s_c;
+  int32_t ir_fallbacks, pad_;  /* FP32_IR: iterations that re-factored in FP64 */
 } colloc_ipm_info;
 
 /* Sizes and per-instance offsets of a handle (host arrays owned by the handle). */
@@ -157,9 +158,10 @@ size_t colloc_table_bytes(const colloc_problem* p);
 int colloc_upload(colloc_problem* p, void* table_dev, hipStream_t stream);
 
 /* Workspace for colloc_eval/kkt_assemble/kkt_factor/kkt_solve/kkt_matvec/ipm_step (KKT blocks,
- * factors, solve vectors, reduction partials) and the interior-point state buffer.  The block
- * storage depends on the factor precision: a workspace sized for COLLOC_FP64 serves both
- * precisions; every call that touches factor blocks takes the precision explicitly. */
+ * factors, solve vectors, reduction partials) and the interior-point state buffer.  Every call
+ * that touches factor blocks takes the precision explicitly.  The FP32_IR size equals the FP64
+ * size: an interior-point iteration whose FP32 factor fails or whose refinement does not
+ * converge re-factors that instance in FP64 in the same workspace. */
 size_t colloc_workspace_bytes(const colloc_problem* p, int32_t precision);
 size_t colloc_state_bytes(const colloc_problem* p);
 
@@ -200,8 +202,13 @@ int kkt_factor(const colloc_problem* p, void* ws_dev, int32_t precision, int32_t
                hipStream_t stream);
 
 /* a5 -- solve K dx = rhs with the factor (forward through the elimination levels, parameter
- * block, back substitution).  In COLLOC_FP32_IR mode up to ir_max FP64 refinement sweeps with
- * the matrix-free FP64 residual rhs - K dx; ir_sweeps[n_inst] (device) receives the count. */
+ * block, back substitution).  With ir_max > 0, up to ir_max refinement sweeps follow: the
+ * residual r = rhs - K dx is formed matrix-free in FP64 from the derivative values, Ds, Sx and
+ * dw of the last assembly (kkt_matvec), the correction solves with the same factor, and an
+ * instance stops once its correction satisfies |d|_inf <= ir_tol |dx|_inf.
+ * ir_sweeps[n_inst] (device, may be NULL): the sweeps taken by a converged instance, minus the
+ * sweeps taken when ir_max was reached without convergence, 0 without refinement or where the
+ * factor failed.  Refinement is what makes COLLOC_FP32_IR factors reach FP64 accuracy. */
 int kkt_solve(const colloc_problem* p, void* ws_dev, int32_t precision, const double* rhs_dev,
               double* dx_dev, int32_t ir_max, double ir_tol, int32_t* ir_sweeps_dev,
               hipStream_t stream);
@@ -223,6 +230,20 @@ int ipm_init(const colloc_problem* p, const double* x0_dev, void* state_dev, voi
              const colloc_ipm_opts* opts, hipStream_t stream);
 int ipm_step(const colloc_problem* p, void* state_dev, void* ws_dev, const colloc_ipm_opts* opts,
              hipStream_t stream);
+
+/* Graph-captured interior-point iterations (batched instances run as one replayed graph per
+ * step instead of one launch per kernel).  ipm_graph_create captures `steps` consecutive
+ * ipm_step calls on (state, ws, opts) by stream capture on `stream` (not the null stream) and
+ * instantiates the graph; nothing is executed during capture.  ipm_graph_launch replays them:
+ * each replay performs exactly what `steps` ipm_step calls would.  The graph is bound to the
+ * given buffers and options; phase timing is not recorded inside it.  Host-only errors:
+ * COLLOC_EINVAL, COLLOC_EHIP when capture or instantiation fails. */
+typedef struct colloc_graph colloc_graph;
+int ipm_graph_create(const colloc_problem* p, void* state_dev, void* ws_dev,
+                     const colloc_ipm_opts* opts, int32_t steps, hipStream_t stream,
+                     colloc_graph** out);
+int ipm_graph_launch(colloc_graph* g, hipStream_t stream);
+int ipm_graph_destroy(colloc_graph* g);
 
 /* Byte offsets of the state buffer's fields: x[n_total], s, y, vL, vU [m_total], zL, zU
  * [n_inst*n_p], dx[n_total], info[n_inst] (colloc_ipm_info). */

@@ -54,7 +54,7 @@ INFO_DTYPE = np.dtype([
     ("alpha_pr", "<f8"), ("alpha_du", "<f8"), ("obj", "<f8"), ("inf_pr", "<f8"),
     ("inf_du", "<f8"), ("E0", "<f8"), ("theta_cv", "<f8"), ("phi", "<f8"),
     ("theta_max", "<f8"), ("theta_min", "<f8"), ("dphi", "<f8"), ("alpha_min", "<f8"),
-    ("Emu", "<f8"), ("s_d", "<f8"), ("s_c", "<f8"), ("resv_", "<f8"),
+    ("Emu", "<f8"), ("s_d", "<f8"), ("s_c", "<f8"), ("ir_fallbacks", "<i4"), ("pad_", "<i4"),
 ])
 
 
@@ -77,7 +77,8 @@ EXPORTS = [
     "colloc_workspace_bytes", "colloc_state_bytes", "colloc_eval", "colloc_derivs",
     "kkt_assemble", "kkt_factor", "kkt_solve", "kkt_matvec", "colloc_ipm_default_opts",
     "ipm_init", "ipm_step", "colloc_state_layout_get", "colloc_timing_enable",
-    "colloc_timing_read", "colloc_tables",
+    "colloc_timing_read", "colloc_tables", "ipm_graph_create", "ipm_graph_launch",
+    "ipm_graph_destroy",
 ]
 
 _lib = None
@@ -113,6 +114,9 @@ def load(path: str = LIB_PATH):
         "colloc_timing_enable": (i32, [vp, i32]),
         "colloc_timing_read": (i32, [vp, _f64p, C.POINTER(i64), i32]),
         "colloc_tables": (i32, [i32, _f64p, _f64p]),
+        "ipm_graph_create": (i32, [vp, vp, vp, C.POINTER(IpmOpts), i32, vp, C.POINTER(vp)]),
+        "ipm_graph_launch": (i32, [vp, vp]),
+        "ipm_graph_destroy": (i32, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -270,12 +274,14 @@ class Problem:
         _check(self.lib.kkt_factor(self.h, _ptr(ws), precision, _ptr(info), _stream()), "kkt_factor")
         return info
 
-    def solve(self, ws, rhs, precision=FP64, ir_max=0, ir_tol=0.0):
+    def solve(self, ws, rhs, precision=FP64, ir_max=0, ir_tol=0.0, sweeps=False):
+        """dx = K^{-1} rhs with the last factor; with ir_max > 0 FP64 refinement sweeps follow.
+        sweeps=True also returns the per-instance sweep counts (negative: not converged)."""
         dx = self.vec(self.n_total)
-        sweeps = self.torch.zeros(self.n_inst, dtype=self.torch.int32, device=self.device)
+        sw = self.torch.zeros(self.n_inst, dtype=self.torch.int32, device=self.device)
         _check(self.lib.kkt_solve(self.h, _ptr(ws), precision, _ptr(rhs), _ptr(dx), ir_max, ir_tol,
-                                  _ptr(sweeps), _stream()), "kkt_solve")
-        return dx
+                                  _ptr(sw), _stream()), "kkt_solve")
+        return (dx, sw) if sweeps else dx
 
     def matvec(self, ws, v):
         out = self.vec(self.n_total)
@@ -289,6 +295,19 @@ class Problem:
 
     def ipm_step(self, state, ws, opts):
         _check(self.lib.ipm_step(self.h, _ptr(state), _ptr(ws), C.byref(opts), _stream()), "ipm_step")
+
+    def graph_create(self, state, ws, opts, steps=1):
+        """Capture `steps` ipm_step calls into a HIP graph on the current (non-default) stream."""
+        g = C.c_void_p()
+        _check(self.lib.ipm_graph_create(self.h, _ptr(state), _ptr(ws), C.byref(opts), steps,
+                                         _stream(), C.byref(g)), "ipm_graph_create")
+        return g
+
+    def graph_launch(self, g):
+        _check(self.lib.ipm_graph_launch(g, _stream()), "ipm_graph_launch")
+
+    def graph_destroy(self, g):
+        _check(self.lib.ipm_graph_destroy(g), "ipm_graph_destroy")
 
     def state_vec(self, state, name, n=None):
         off = self.state_layout[name]

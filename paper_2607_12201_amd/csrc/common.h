@@ -103,6 +103,12 @@ struct Ws {
   double* epart;              // [n_elem][EP_N] element partial sums
   double* ipart;              // [n_inst][EP_N]
   int* flag;                  // [n_inst] factor failure flags
+  int* irflag;                // [n_inst] refinement: 1 = instance done (converged / failed)
+  int* ircount;               // [n_inst] refinement sweeps (negative: not converged)
+  int* runskip;               // [n_inst] 1 = instance not iterating this step
+  int* fbflag;                // [n_inst] FP64 fallback mask (0 = re-factor in FP64)
+  int* fbneed;                // [n_inst] 1 = the instance re-factors in FP64 this step
+  double* irpart;             // [n_elem][2] refinement partial maxima |d|, |dx|
 };
 
 // Element partial-sum slots (colloc_eval and the interior-point reductions).

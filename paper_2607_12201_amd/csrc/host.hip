@@ -541,6 +541,12 @@ static Ws ws_layout(const colloc_problem* p, int prec, void* base, size_t* bytes
   w.epart = c.take<double>(E * EP_N);
   w.ipart = c.take<double>(I * EP_N);
   w.flag = c.take<int>(I);
+  w.irflag = c.take<int>(I);
+  w.ircount = c.take<int>(I);
+  w.runskip = c.take<int>(I);
+  w.fbflag = c.take<int>(I);
+  w.fbneed = c.take<int>(I);
+  w.irpart = c.take<double>(E * 2);
   w.rthp = c.take<double>(E * S.np);
   w.dcont = c.take<double>(E * S.ns);
   w.ath = c.take<double>(E * S.np * S.np);
@@ -616,7 +622,7 @@ static IpmState state_layout(const colloc_problem* p, void* base, size_t* bytes,
 extern "C" size_t colloc_workspace_bytes(const colloc_problem* p, int32_t precision) {
   if (!p || (precision != COLLOC_FP64 && precision != COLLOC_FP32_IR)) return 0;
   size_t b = 0;
-  ws_layout(p, precision, nullptr, &b);
+  ws_layout(p, COLLOC_FP64, nullptr, &b);   // FP32_IR keeps room for its FP64 fallback
   return b;
 }
 
@@ -683,13 +689,14 @@ extern "C" int kkt_solve(const colloc_problem* p, void* ws_dev, int32_t precisio
                          double* dx, int32_t ir_max, double ir_tol, int32_t* ir_sweeps,
                          hipStream_t stream) {
   CHECK(p && p->uploaded && ws_dev && aligned8(rhs) && aligned8(dx) && ir_max >= 0 && prec_ok(precision));
-  CHECK(rhs != dx);
-  (void)ir_tol;
-  (void)ir_sweeps;
+  CHECK(rhs != dx && ir_tol >= 0.0 && ir_max <= 1000);
   Ws w = ws_layout(p, precision, ws_dev, nullptr);
   colloc_problem* pm = const_cast<colloc_problem*>(p);
-  return launch_solve_p(p->S, p->tab, p->hp, w, rhs, nullptr, dx, phase_hook, pm, stream) ? COLLOC_EHIP
-                                                                                         : COLLOC_OK;
+  if (launch_solve_p(p->S, p->tab, p->hp, w, rhs, nullptr, dx, phase_hook, pm, stream)) return COLLOC_EHIP;
+  if (launch_refine(p->S, p->tab, p->hp, w, rhs, dx, ir_max, ir_tol, phase_hook, pm, stream))
+    return COLLOC_EHIP;
+  if (ir_sweeps && launch_refine_report(p->tab, w, ir_sweeps, stream)) return COLLOC_EHIP;
+  return COLLOC_OK;
 }
 
 extern "C" int kkt_matvec(const colloc_problem* p, void* ws_dev, const double* v, double* out,
@@ -731,7 +738,7 @@ extern "C" void colloc_ipm_default_opts(colloc_ipm_opts* o) {
   o->gamma_alpha = 0.05;
   o->max_ls = 40;
   o->precision = COLLOC_FP64;
-  o->ir_max = 10;
+  o->ir_max = 4;
   o->ir_tol = 1e-14;
 }
 
@@ -739,6 +746,7 @@ static int check_opts(const colloc_ipm_opts* o) {
   if (!o) return 0;
   if (!(o->tol > 0 && o->tau_r > 0 && o->mu_init > 0 && o->max_ls >= 1 && o->max_ls <= CL_MAX_LS)) return 0;
   if (o->precision != COLLOC_FP64 && o->precision != COLLOC_FP32_IR) return 0;
+  if (o->ir_max < 0 || o->ir_max > 100 || !(o->ir_tol >= 0.0)) return 0;
   return 1;
 }
 
@@ -754,10 +762,64 @@ extern "C" int ipm_step(const colloc_problem* p, void* state, void* ws_dev, cons
                         hipStream_t stream) {
   CHECK(p && p->uploaded && state && ws_dev && check_opts(opts));
   Ws w = ws_layout(p, opts->precision, ws_dev, nullptr);
+  Ws w64 = ws_layout(p, COLLOC_FP64, ws_dev, nullptr);
   IpmState st = state_layout(p, state, nullptr, nullptr);
   colloc_problem* pm = const_cast<colloc_problem*>(p);
-  return launch_ipm_step(p->S, p->tab, p->hp, st, w, *opts, phase_hook, pm, stream) ? COLLOC_EHIP
-                                                                                     : COLLOC_OK;
+  return launch_ipm_step(p->S, p->tab, p->hp, st, w, w64, *opts, phase_hook, pm, stream) ? COLLOC_EHIP
+                                                                                          : COLLOC_OK;
+}
+
+struct colloc_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" int ipm_graph_create(const colloc_problem* p, void* state, void* ws_dev,
+                                const colloc_ipm_opts* opts, int32_t steps, hipStream_t stream,
+                                colloc_graph** out) {
+  CHECK(p && p->uploaded && state && ws_dev && check_opts(opts) && out && stream && steps >= 1 &&
+        steps <= 64);
+  *out = nullptr;
+  Ws w = ws_layout(p, opts->precision, ws_dev, nullptr);
+  Ws w64 = ws_layout(p, COLLOC_FP64, ws_dev, nullptr);
+  IpmState st = state_layout(p, state, nullptr, nullptr);
+  colloc_graph* g = new (std::nothrow) colloc_graph;
+  if (!g) return COLLOC_ENOMEM;
+  if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    delete g;
+    return COLLOC_EHIP;
+  }
+  int rc = 0;
+  for (int s = 0; s < steps && !rc; ++s)
+    rc = launch_ipm_step(p->S, p->tab, p->hp, st, w, w64, *opts, nullptr, nullptr, stream);
+  hipGraph_t graph = nullptr;
+  const hipError_t ec = hipStreamEndCapture(stream, &graph);
+  if (rc || ec != hipSuccess || !graph) {
+    if (graph) hipGraphDestroy(graph);
+    delete g;
+    return COLLOC_EHIP;
+  }
+  g->graph = graph;
+  if (hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+    hipGraphDestroy(graph);
+    delete g;
+    return COLLOC_EHIP;
+  }
+  *out = g;
+  return COLLOC_OK;
+}
+
+extern "C" int ipm_graph_launch(colloc_graph* g, hipStream_t stream) {
+  CHECK(g && g->exec);
+  return hipGraphLaunch(g->exec, stream) == hipSuccess ? COLLOC_OK : COLLOC_EHIP;
+}
+
+extern "C" int ipm_graph_destroy(colloc_graph* g) {
+  if (!g) return COLLOC_OK;
+  if (g->exec) hipGraphExecDestroy(g->exec);
+  if (g->graph) hipGraphDestroy(g->graph);
+  delete g;
+  return COLLOC_OK;
 }
 
 extern "C" int colloc_timing_enable(colloc_problem* p, int32_t enable) {

@@ -18,7 +18,9 @@ struct IpmState {
 
 int launch_ipm_init(const Shape& S, const Tab& tb, const IpmState& st, const Ws& ws,
                     const double* x0, const colloc_ipm_opts& o, hipStream_t s);
+// ws64: the FP64 layout of the same workspace (the FP32_IR fallback), unused in FP64 mode.
 int launch_ipm_step(const Shape& S, const Tab& tb, const HostPlan& hp, const IpmState& st,
-                    const Ws& ws, const colloc_ipm_opts& o, phase_cb cb, void* ctx, hipStream_t s);
+                    const Ws& ws, const Ws& ws64, const colloc_ipm_opts& o, phase_cb cb, void* ctx,
+                    hipStream_t s);
 
 }  // namespace cl

@@ -721,8 +721,45 @@ size_t ipm_eval_lds(const Shape& S, int nt) {
   return sizeof(double) * (5 * S.b + 2 * S.ns + S.np * 2 + S.nr + 4 * S.K * S.nr + nt);
 }
 
+// FP32_IR helpers.  Materialise the theta part of the condensed right-hand side (barrier terms
+// already in st.rhs plus the element partials, fixed order) so the refinement residual sees it.
+__global__ void k_fp32_prep(Shape S, Tab tb, IpmState st, Ws ws) {
+  const int inst = blockIdx.x;
+  const int skip = ws.flag[inst];
+  if (tid() == 0) ws.runskip[inst] = skip;
+  if (skip) return;
+  const int N = tb.inst_N[inst], np = S.np;
+  const int64_t e0 = tb.inst_e0[inst], xt = tb.inst_x[inst] + (int64_t)N * S.b;
+  for (int c = tid(); c < np; c += nthr()) {
+    double acc = st.rhs[xt + c];
+    for (int i = 0; i < N; ++i) acc += ws.rthp[(e0 + i) * np + c];
+    st.rhs[xt + c] = acc;
+  }
+}
+
+// Instances whose FP32 factor failed or whose refinement did not converge re-factor in FP64.
+__global__ void k_fp32_fallback(Tab tb, IpmState st, Ws ws) {
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < tb.n_inst; q += gridDim.x * blockDim.x) {
+    const bool run = ws.runskip[q] == 0;
+    const bool need = run && (ws.flag[q] != 0 || ws.ircount[q] <= 0);
+    ws.fbneed[q] = need ? 1 : 0;
+    ws.fbflag[q] = need ? 0 : 1;
+    if (run) {
+      const int c = ws.ircount[q];
+      st.info[q].ir_sweeps = c < 0 ? -c : c;
+      if (need) st.info[q].ir_fallbacks += 1;
+    }
+  }
+}
+
+__global__ void k_fp32_done(Tab tb, Ws ws) {
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < tb.n_inst; q += gridDim.x * blockDim.x)
+    if (ws.fbneed[q]) ws.flag[q] = ws.fbflag[q];
+}
+
 int launch_ipm_step(const Shape& S, const Tab& tb, const HostPlan& hp, const IpmState& st,
-                    const Ws& ws, const colloc_ipm_opts& o, phase_cb cb, void* ctx, hipStream_t s) {
+                    const Ws& ws, const Ws& ws64, const colloc_ipm_opts& o, phase_cb cb, void* ctx,
+                    hipStream_t s) {
   const int nt = elem_threads(S);
   const unsigned ne = (unsigned)tb.n_elem;
   if (cb) cb(ctx, COLLOC_PH_EVAL, 1, s);
@@ -731,10 +768,32 @@ int launch_ipm_step(const Shape& S, const Tab& tb, const HostPlan& hp, const Ipm
   hipLaunchKernelGGL(k_ipm_prep, dim3(ne), dim3(nt),
                      sizeof(double) * (2 * S.b + S.ns + S.K * S.nr + S.np), s, S, tb, st, ws, o);
   if (cb) cb(ctx, COLLOC_PH_EVAL, 0, s);
-  int rc = launch_factor_nc(S, tb, hp, ws, ws.prec, true, cb, ctx, s);
-  if (rc) return rc;
-  rc = launch_solve_p(S, tb, hp, ws, st.rhs, ws.rthp, st.dx, cb, ctx, s);
-  if (rc) return rc;
+  int rc;
+  if (ws.prec == 0) {
+    rc = launch_factor_nc(S, tb, hp, ws, 0, true, cb, ctx, s);
+    if (rc) return rc;
+    rc = launch_solve_p(S, tb, hp, ws, st.rhs, ws.rthp, st.dx, cb, ctx, s);
+    if (rc) return rc;
+  } else {
+    // FP32 block factors, FP64 refinement; per-instance FP64 re-factorization where the FP32
+    // factor fails or the refinement does not reach its target
+    hipLaunchKernelGGL(k_fp32_prep, dim3(tb.n_inst), dim3(64), 0, s, S, tb, st, ws);
+    rc = launch_factor_nc(S, tb, hp, ws, 1, true, cb, ctx, s);
+    if (rc) return rc;
+    rc = launch_solve_p(S, tb, hp, ws, st.rhs, nullptr, st.dx, cb, ctx, s);
+    if (rc) return rc;
+    rc = launch_refine(S, tb, hp, ws, st.rhs, st.dx, o.ir_max, o.ir_tol, cb, ctx, s);
+    if (rc) return rc;
+    const unsigned gi = (unsigned)cl_ceil_div(tb.n_inst, 256);
+    hipLaunchKernelGGL(k_fp32_fallback, dim3(gi), dim3(256), 0, s, tb, st, ws);
+    Ws wf = ws64;
+    wf.flag = ws.fbflag;
+    rc = launch_factor_nc(S, tb, hp, wf, 0, true, cb, ctx, s);
+    if (rc) return rc;
+    rc = launch_solve_p(S, tb, hp, wf, st.rhs, nullptr, st.dx, cb, ctx, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_fp32_done, dim3(gi), dim3(256), 0, s, tb, ws);
+  }
   if (cb) cb(ctx, COLLOC_PH_STEP, 1, s);
   hipLaunchKernelGGL(k_ipm_dir, dim3(ne), dim3(nt), sizeof(double) * (2 * S.b + S.ns + S.np + nt), s,
                      S, tb, st, ws, o);

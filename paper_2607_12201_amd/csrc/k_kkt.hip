@@ -324,22 +324,73 @@ __device__ void trsm_l(const double* Lm, int n, double* B, int m) {
     }
   }
 }
-// x <- L^{-1} x (single thread; n small)
-__device__ void trsv_l_seq(const double* Lm, int n, double* x) {
-  for (int r = 0; r < n; ++r) {
-    double v = x[r];
-    for (int q = 0; q < r; ++q) v -= Lm[r * n + q] * x[q];
-    x[r] = v / Lm[r * n + r];
+// ---------------------------------------------------------------- wave triangular solves
+// One full wave (the calling workgroup's threads 0..63) solves with a lower-triangular L of
+// order n <= 256 in place on the LDS vector x.  Column oriented: lane t keeps rows t, t+64,
+// t+128, t+192 in registers; the pivot value x_c is broadcast from its owner lane by a
+// shuffle, so no workgroup barrier is needed inside the solve.  Lrc(r, c) returns L(r, c)
+// for r >= c.  The caller synchronises before (x written by other threads) and after.
+template <class F>
+__device__ inline void wave_trsv_l(const F& Lrc, int n, double* x) {
+  const int lane = threadIdx.x & 63;
+  double v[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) v[k] = (lane + 64 * k < n) ? x[lane + 64 * k] : 0.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int cend = min(n, 64 * k + 64);
+    for (int c = 64 * k; c < cend; ++c) {
+      const double xc = __shfl(v[k], c - 64 * k) / Lrc(c, c);
+      if (lane == c - 64 * k) v[k] = xc;
+#pragma unroll
+      for (int k2 = k; k2 < 4; ++k2) {
+        const int r = lane + 64 * k2;
+        if (r > c && r < n) v[k2] -= Lrc(r, c) * xc;
+      }
+    }
   }
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (lane + 64 * k < n) x[lane + 64 * k] = v[k];
 }
-// x <- L^{-T} x (single thread)
-__device__ void trsv_lt_seq(const double* Lm, int n, double* x) {
-  for (int r = n - 1; r >= 0; --r) {
-    double v = x[r];
-    for (int q = r + 1; q < n; ++q) v -= Lm[q * n + r] * x[q];
-    x[r] = v / Lm[r * n + r];
+
+// Same with L^T: x <- L^{-T} x, columns taken from the last one down.
+template <class F>
+__device__ inline void wave_trsv_lt(const F& Lrc, int n, double* x) {
+  const int lane = threadIdx.x & 63;
+  double v[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) v[k] = (lane + 64 * k < n) ? x[lane + 64 * k] : 0.0;
+#pragma unroll
+  for (int k = 3; k >= 0; --k) {
+    for (int c = min(n, 64 * k + 64) - 1; c >= 64 * k; --c) {
+      const double xc = __shfl(v[k], c - 64 * k) / Lrc(c, c);
+      if (lane == c - 64 * k) v[k] = xc;
+#pragma unroll
+      for (int k2 = 0; k2 <= k; ++k2) {
+        const int r = lane + 64 * k2;
+        if (r < c) v[k2] -= Lrc(c, r) * xc;
+      }
+    }
   }
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (lane + 64 * k < n) x[lane + 64 * k] = v[k];
 }
+
+// Row-major dense block in LDS (L(r, c) at M[r * n + c]).
+struct RowMajor {
+  const double* M;
+  int n;
+  __device__ double operator()(int r, int c) const { return M[r * n + c]; }
+};
+// Packed lower triangle, column-major: column c holds rows c..n-1.
+struct PackedCol {
+  const double* M;
+  int n;
+  __device__ int off(int c) const { return c * n - (c * (c - 1)) / 2; }
+  __device__ double operator()(int r, int c) const { return M[off(c) + (r - c)]; }
+};
 
 template <typename T>
 __device__ inline void load_blk(double* dst, const T* src, int n) {
@@ -412,31 +463,65 @@ __global__ void k_copy_flags(Ws ws, int* info, int n) {
 }
 
 // ---------------------------------------------------------------- solve
-// Level-0 forward: y_I = L_I^{-1} r_I and the tail contributions X^T y_I.
-// LDS: y (mI) + Lpanel not cached (read from global, column-major)
+
+// Stage the lower triangle of the leading mI x mI block of a column-major panel (ld R) into
+// LDS as a packed lower triangle; eight independent loads in flight per thread.
 template <typename T>
-__global__ void k_l0_fwd(Shape S, Tab tb, Ws ws, const double* __restrict__ rhs) {
+__device__ inline void stage_tri(double* dst, const T* Q, int R, int mI) {
+  const int nn = mI * mI;
+  for (int t0 = 0; t0 < nn; t0 += 8 * nthr()) {
+    double tmp[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int t = t0 + u * nthr() + tid();
+      const int c = t / mI, r = t - c * mI;
+      tmp[u] = (t < nn && r >= c) ? (double)Q[c * R + r] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int t = t0 + u * nthr() + tid();
+      const int c = t / mI, r = t - c * mI;
+      if (t < nn && r >= c) dst[c * mI - (c * (c - 1)) / 2 + (r - c)] = tmp[u];
+    }
+  }
+}
+
+// sum_k a[k * sa] * b[k] over k < n with four independent partial sums.
+template <typename T>
+__device__ inline double dot4(const T* a, int sa, const double* b, int n) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int k = 0;
+  for (; k + 4 <= n; k += 4) {
+    s0 += (double)a[k * sa] * b[k];
+    s1 += (double)a[(k + 1) * sa] * b[k + 1];
+    s2 += (double)a[(k + 2) * sa] * b[k + 2];
+    s3 += (double)a[(k + 3) * sa] * b[k + 3];
+  }
+  for (; k < n; ++k) s0 += (double)a[k * sa] * b[k];
+  return (s0 + s1) + (s2 + s3);
+}
+// Level-0 forward, one wave per element: the element's interior factor L_I is staged in LDS as
+// a packed lower triangle, y_I = L_I^{-1} r_I by the wave solve, then the tail contributions
+// X^T y_I for the rows [S | theta | P].  LDS: packed L_I (mI (mI+1) / 2) + y (mI).
+template <typename T>
+__global__ void __launch_bounds__(64) k_l0_fwd(Shape S, Tab tb, Ws ws, const double* __restrict__ rhs) {
   extern __shared__ double lds[];
   const int64_t e = blockIdx.x;
   const int inst = tb.elem_inst[e], i = tb.elem_loc[e];
   if (block_flag(&ws.flag[inst])) return;
   const int ns = S.ns, np = S.np, R = S.R, mI = S.mI;
   const T* Q = (const T*)ws.panel + e * (int64_t)R * mI;
-  double* y = lds;
+  const PackedCol Lp{lds, mI};
+  double* y = lds + mI * (mI + 1) / 2;
+  stage_tri(lds, Q, R, mI);
   const double* r = rhs + tb.inst_x[inst] + (int64_t)i * S.b;
   for (int t = tid(); t < mI; t += nthr()) y[t] = r[t];
   __syncthreads();
-  for (int c = 0; c < mI; ++c) {
-    if (tid() == 0) y[c] /= (double)Q[c * R + c];
-    __syncthreads();
-    double yc = y[c];
-    for (int t = c + 1 + tid(); t < mI; t += nthr()) y[t] -= (double)Q[c * R + t] * yc;
-    __syncthreads();
-  }
+  wave_trsv_l(Lp, mI, y);
+  __syncthreads();
   for (int t = tid(); t < mI; t += nthr()) ws.yI[e * mI + t] = y[t];
   for (int a = tid(); a < S.Rt; a += nthr()) {   // tail rows [S | theta | P]
-    double acc = 0.0;
-    for (int k = 0; k < mI; ++k) acc += (double)Q[k * R + mI + a] * y[k];
+    const double acc = dot4(Q + mI + a, R, y, mI);
     if (a < ns) ws.cS[e * ns + a] = acc;
     else if (a < ns + np) ws.cB[e * np + (a - ns)] = acc;
     else ws.cP[e * ns + (a - ns - np)] = (i > 0) ? acc : 0.0;
@@ -468,7 +553,7 @@ __global__ void k_crf_first(Shape S, Tab tb, Ws ws, const double* __restrict__ r
   for (int a = tid(); a < ns; a += nthr())
     r[a] = sep_rhs_initial(S, ws, rhs, tb.inst_x[inst], ej, j, j + 1 < N, a);
   __syncthreads();
-  if (tid() == 0) trsv_l_seq(Lm, ns, r);
+  if (tid() < 64) wave_trsv_l(RowMajor{Lm, ns}, ns, r);
   __syncthreads();
   for (int t = tid(); t < ns; t += nthr()) ws.ysep[ej * ns + t] = r[t];
   const T* UB = (const T*)ws.ub + ej * ns * np;
@@ -515,7 +600,7 @@ __global__ void k_crf_step(Shape S, Tab tb, Ws ws, const double* __restrict__ rh
     for (int a = tid(); a < ns; a += nthr()) ws.rcur[es * ns + a] = r[a];
     return;
   }
-  if (tid() == 0) trsv_l_seq(Lm, ns, r);
+  if (tid() < 64) wave_trsv_l(RowMajor{Lm, ns}, ns, r);
   __syncthreads();
   for (int t = tid(); t < ns; t += nthr()) ws.ysep[es * ns + t] = r[t];
   const T* UB = (const T*)ws.ub + es * ns * np;
@@ -571,7 +656,7 @@ __global__ void k_border_solve(Shape S, Tab tb, Ws ws, const double* __restrict_
   }
   red[tid()] = (g0 < G) ? acc : 0.0;
   __syncthreads();
-  if (tid() == 0) trsv_l_seq(Lm, ns, r);
+  if (tid() < 64) wave_trsv_l(RowMajor{Lm, ns}, ns, r);
   __syncthreads();
   const T* UB0 = (const T*)ws.ub + e0 * ns * np;
   for (int c = tid(); c < np; c += nthr()) {
@@ -590,16 +675,18 @@ __global__ void k_border_solve(Shape S, Tab tb, Ws ws, const double* __restrict_
     rt[c] = rhs[xoff + (int64_t)N * S.b + c] - sum - u;
   }
   __syncthreads();
-  if (tid() == 0) {
-    trsv_l_seq(Sm, np, rt);
-    trsv_lt_seq(Sm, np, rt);
-    for (int a = 0; a < ns; ++a) {
-      double v = r[a];
-      for (int c = 0; c < np; ++c) v -= (double)UB0[a * np + c] * rt[c];
-      r[a] = v;
-    }
-    trsv_lt_seq(Lm, ns, r);
+  if (tid() < 64) {
+    wave_trsv_l(RowMajor{Sm, np}, np, rt);
+    wave_trsv_lt(RowMajor{Sm, np}, np, rt);
   }
+  __syncthreads();
+  for (int a = tid(); a < ns; a += nthr()) {
+    double v = r[a];
+    for (int c = 0; c < np; ++c) v -= (double)UB0[a * np + c] * rt[c];
+    r[a] = v;
+  }
+  __syncthreads();
+  if (tid() < 64) wave_trsv_lt(RowMajor{Lm, ns}, ns, r);
   __syncthreads();
   for (int c = tid(); c < np; c += nthr()) {
     ws.xth[inst * np + c] = rt[c];
@@ -637,25 +724,27 @@ __global__ void k_cr_bwd(Shape S, Tab tb, Ws ws, int level) {
     r[a] = v;
   }
   __syncthreads();
-  if (tid() == 0) trsv_lt_seq(Lm, ns, r);
+  if (tid() < 64) wave_trsv_lt(RowMajor{Lm, ns}, ns, r);
   __syncthreads();
   for (int a = tid(); a < ns; a += nthr()) ws.xsep[ej * ns + a] = r[a];
 }
 
-// Level-0 backward: x_I = L_I^{-T} (y_I - X_S x_S(i) - X_P x_S(i-1) - X_B x_theta); writes dx.
-// LDS: t (mI) + xs (ns) + xp (ns) + xt (np)
+// Level-0 backward, one wave per element: x_I = L_I^{-T} (y_I - X_S x_S(i) - X_P x_S(i-1) -
+// X_B x_theta); writes dx.  LDS: packed L_I + t (mI) + xs (ns) + xp (ns) + xt (np)
 template <typename T>
-__global__ void k_l0_bwd(Shape S, Tab tb, Ws ws, double* __restrict__ dx) {
+__global__ void __launch_bounds__(64) k_l0_bwd(Shape S, Tab tb, Ws ws, double* __restrict__ dx) {
   extern __shared__ double lds[];
   const int64_t e = blockIdx.x;
   const int inst = tb.elem_inst[e], i = tb.elem_loc[e];
   if (block_flag(&ws.flag[inst])) return;
   const int ns = S.ns, np = S.np, R = S.R, mI = S.mI;
   const T* Q = (const T*)ws.panel + e * (int64_t)R * mI;
-  double* tv = lds;
+  const PackedCol Lp{lds, mI};
+  double* tv = lds + mI * (mI + 1) / 2;
   double* xs = tv + mI;
   double* xp = xs + ns;
   double* xt = xp + ns;
+  stage_tri(lds, Q, R, mI);
   for (int a = tid(); a < ns; a += nthr()) {
     xs[a] = ws.xsep[e * ns + a];
     xp[a] = i > 0 ? ws.xsep[(e - 1) * ns + a] : 0.0;
@@ -663,23 +752,14 @@ __global__ void k_l0_bwd(Shape S, Tab tb, Ws ws, double* __restrict__ dx) {
   for (int c = tid(); c < np; c += nthr()) xt[c] = ws.xth[inst * np + c];
   __syncthreads();
   for (int k = tid(); k < mI; k += nthr()) {
-    double v = ws.yI[e * mI + k];
     const T* col = Q + k * R + mI;
-    for (int a = 0; a < ns; ++a) v -= (double)col[a] * xs[a];
-    for (int c = 0; c < np; ++c) v -= (double)col[ns + c] * xt[c];
-    if (i > 0)
-      for (int a = 0; a < ns; ++a) v -= (double)col[ns + np + a] * xp[a];
+    double v = ws.yI[e * mI + k] - dot4(col, 1, xs, ns) - dot4(col + ns, 1, xt, np);
+    if (i > 0) v -= dot4(col + ns + np, 1, xp, ns);
     tv[k] = v;
   }
   __syncthreads();
-  // backward substitution with L^T, column oriented: x_c = t_c / L_cc; t_r -= L_cr x_c (r < c)
-  for (int c = mI - 1; c >= 0; --c) {
-    if (tid() == 0) tv[c] /= (double)Q[c * R + c];
-    __syncthreads();
-    double xc = tv[c];
-    for (int r = tid(); r < c; r += nthr()) tv[r] -= (double)Q[r * R + c] * xc;
-    __syncthreads();
-  }
+  wave_trsv_lt(Lp, mI, tv);
+  __syncthreads();
   double* out = dx + tb.inst_x[inst] + (int64_t)i * S.b;
   for (int k = tid(); k < mI; k += nthr()) out[k] = tv[k];
   for (int a = tid(); a < ns; a += nthr()) out[mI + a] = xs[a];
@@ -687,10 +767,12 @@ __global__ void k_l0_bwd(Shape S, Tab tb, Ws ws, double* __restrict__ dx) {
 
 // ---------------------------------------------------------------- matrix-free K v (FP64)
 // u = Ds (J v) for the element's rows.  LDS: v (b) vp (ns) vt (np) out (b)
-__global__ void k_mv1(Shape S, Tab tb, Ws ws, const double* __restrict__ v, double* __restrict__ u) {
+__global__ void k_mv1(Shape S, Tab tb, Ws ws, const double* __restrict__ v, double* __restrict__ u,
+                      const int* skip) {
   extern __shared__ double lds[];
   const int64_t e = blockIdx.x;
   const int inst = tb.elem_inst[e], i = tb.elem_loc[e];
+  if (skip && block_flag(&skip[inst])) return;
   const int N = tb.inst_N[inst];
   const int b = S.b, ns = S.ns, np = S.np;
   const double* vb = v + tb.inst_x[inst];
@@ -713,10 +795,11 @@ __global__ void k_mv1(Shape S, Tab tb, Ws ws, const double* __restrict__ v, doub
 // out_z = J^T u + W v + dw v ; theta partials to ws.rthp.  LDS: u (b) un (ns) phi (K nr)
 // v (b) vt (np) oz (b) ot (np) wz (b) wt (np)
 __global__ void k_mv2(Shape S, Tab tb, Ws ws, const double* __restrict__ v,
-                      const double* __restrict__ u, double* __restrict__ out) {
+                      const double* __restrict__ u, double* __restrict__ out, const int* skip) {
   extern __shared__ double lds[];
   const int64_t e = blockIdx.x;
   const int inst = tb.elem_inst[e], i = tb.elem_loc[e];
+  if (skip && block_flag(&skip[inst])) return;
   const int N = tb.inst_N[inst];
   const int b = S.b, ns = S.ns, np = S.np;
   double* ul = lds;
@@ -751,8 +834,10 @@ __global__ void k_mv2(Shape S, Tab tb, Ws ws, const double* __restrict__ v,
   for (int t = tid(); t < np; t += nthr()) ws.rthp[e * np + t] = ot[t] + wt[t];
 }
 
-__global__ void k_mv3(Shape S, Tab tb, Ws ws, const double* __restrict__ v, double* __restrict__ out) {
+__global__ void k_mv3(Shape S, Tab tb, Ws ws, const double* __restrict__ v, double* __restrict__ out,
+                      const int* skip) {
   const int inst = blockIdx.x;
+  if (skip && block_flag(&skip[inst])) return;
   const int N = tb.inst_N[inst];
   const int64_t e0 = tb.inst_e0[inst];
   const int64_t xt = tb.inst_x[inst] + (int64_t)N * S.b;
@@ -824,11 +909,11 @@ template <typename T>
 static int solve_t(const Shape& S, const Tab& tb, const HostPlan& hp, const Ws& ws,
                    const double* rhs, const double* rthp, double* dx, phase_cb cb, void* ctx,
                    hipStream_t st) {
-  int nt = elem_threads(S);
   int snt = sep_threads(S);
   if (cb) cb(ctx, 4, 1, st);
-  hipLaunchKernelGGL(k_l0_fwd<T>, dim3((unsigned)tb.n_elem), dim3(nt), sizeof(double) * S.mI, st,
-                     S, tb, ws, rhs);
+  const size_t tri = (size_t)S.mI * (S.mI + 1) / 2;
+  hipLaunchKernelGGL(k_l0_fwd<T>, dim3((unsigned)tb.n_elem), dim3(64), sizeof(double) * (tri + S.mI),
+                     st, S, tb, ws, rhs);
   size_t clds = sizeof(double) * (S.ns * S.ns + S.ns);
   if (tb.L >= 1 && hp.lvl[1] > 0)
     hipLaunchKernelGGL(k_crf_first<T>, dim3(hp.lvl[1]), dim3(snt), clds, st, S, tb, ws, rhs);
@@ -842,8 +927,8 @@ static int solve_t(const Shape& S, const Tab& tb, const HostPlan& hp, const Ws& 
     int n = hp.lvl[l];
     if (n > 0) hipLaunchKernelGGL(k_cr_bwd<T>, dim3(n), dim3(snt), clds, st, S, tb, ws, l);
   }
-  hipLaunchKernelGGL(k_l0_bwd<T>, dim3((unsigned)tb.n_elem), dim3(nt),
-                     sizeof(double) * (S.mI + 2 * S.ns + S.np), st, S, tb, ws, dx);
+  hipLaunchKernelGGL(k_l0_bwd<T>, dim3((unsigned)tb.n_elem), dim3(64),
+                     sizeof(double) * (tri + S.mI + 2 * S.ns + S.np), st, S, tb, ws, dx);
   if (cb) cb(ctx, 4, 0, st);
   return ok_or();
 }
@@ -855,15 +940,127 @@ int launch_solve_p(const Shape& S, const Tab& tb, const HostPlan& hp, const Ws& 
                  : solve_t<double>(S, tb, hp, ws, rhs, rthp, dx, cb, ctx, st);
 }
 
-int launch_matvec(const Shape& S, const Tab& tb, const Ws& ws, const double* v, double* out,
-                  hipStream_t st) {
+static int matvec_masked(const Shape& S, const Tab& tb, const Ws& ws, const double* v, double* out,
+                         const int* skip, hipStream_t st) {
   int nt = elem_threads(S);
   hipLaunchKernelGGL(k_mv1, dim3((unsigned)tb.n_elem), dim3(nt),
-                     sizeof(double) * (2 * S.b + S.ns + S.np), st, S, tb, ws, v, ws.vtmp2);
+                     sizeof(double) * (2 * S.b + S.ns + S.np), st, S, tb, ws, v, ws.vtmp2, skip);
   hipLaunchKernelGGL(k_mv2, dim3((unsigned)tb.n_elem), dim3(nt),
                      sizeof(double) * (4 * S.b + S.ns + S.K * S.nr + 3 * S.np), st, S, tb, ws, v,
-                     ws.vtmp2, out);
-  hipLaunchKernelGGL(k_mv3, dim3(tb.n_inst), dim3(64), 0, st, S, tb, ws, v, out);
+                     ws.vtmp2, out, skip);
+  hipLaunchKernelGGL(k_mv3, dim3(tb.n_inst), dim3(64), 0, st, S, tb, ws, v, out, skip);
+  return ok_or();
+}
+
+int launch_matvec(const Shape& S, const Tab& tb, const Ws& ws, const double* v, double* out,
+                  hipStream_t st) {
+  return matvec_masked(S, tb, ws, v, out, nullptr, st);
+}
+
+// ---------------------------------------------------------------- FP64 iterative refinement
+// Per sweep: r = rhs - K dx (matrix-free FP64 product), d = K_factor^{-1} r, dx += d; an
+// instance stops when |d|_inf <= ir_tol |dx|_inf (converged) or after ir_max sweeps.
+// ws.irflag masks finished instances out of every kernel of the sweep.
+__global__ void k_ir_init(Ws ws, int n) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+    ws.irflag[t] = ws.flag[t];
+    ws.ircount[t] = 0;
+  }
+}
+
+__global__ void k_ir_resid(Shape S, Tab tb, Ws ws, const double* __restrict__ rhs) {
+  const int64_t e = blockIdx.x;
+  const int inst = tb.elem_inst[e], i = tb.elem_loc[e];
+  if (block_flag(&ws.irflag[inst])) return;
+  const int64_t o = tb.inst_x[inst] + (int64_t)i * S.b;
+  for (int t = tid(); t < S.b; t += nthr()) ws.vtmp[o + t] = rhs[o + t] - ws.vtmp[o + t];
+  if (i == 0) {
+    const int64_t xt = tb.inst_x[inst] + (int64_t)tb.inst_N[inst] * S.b;
+    for (int c = tid(); c < S.np; c += nthr()) ws.vtmp[xt + c] = rhs[xt + c] - ws.vtmp[xt + c];
+  }
+}
+
+__global__ void k_ir_update(Shape S, Tab tb, Ws ws, double* __restrict__ dx) {
+  __shared__ double red[256];
+  const int64_t e = blockIdx.x;
+  const int inst = tb.elem_inst[e], i = tb.elem_loc[e];
+  if (block_flag(&ws.irflag[inst])) return;
+  const int64_t o = tb.inst_x[inst] + (int64_t)i * S.b;
+  double dm = 0.0, xm = 0.0;
+  for (int t = tid(); t < S.b; t += nthr()) {
+    const double d = ws.vtmp2[o + t], x = dx[o + t] + d;
+    dx[o + t] = x;
+    dm = fmax(dm, fabs(d));
+    xm = fmax(xm, fabs(x));
+  }
+  dm = block_max(dm, red);
+  xm = block_max(xm, red);
+  if (tid() == 0) {
+    ws.irpart[e * 2] = dm;
+    ws.irpart[e * 2 + 1] = xm;
+  }
+}
+
+__global__ void k_ir_decide(Shape S, Tab tb, Ws ws, double* __restrict__ dx, int ir_max,
+                            double ir_tol) {
+  __shared__ double red[256];
+  const int inst = blockIdx.x;
+  if (block_flag(&ws.irflag[inst])) return;
+  const int N = tb.inst_N[inst];
+  const int64_t e0 = tb.inst_e0[inst];
+  const int64_t xt = tb.inst_x[inst] + (int64_t)N * S.b;
+  double dm = 0.0, xm = 0.0;
+  for (int c = tid(); c < S.np; c += nthr()) {
+    const double d = ws.vtmp2[xt + c], x = dx[xt + c] + d;
+    dx[xt + c] = x;
+    dm = fmax(dm, fabs(d));
+    xm = fmax(xm, fabs(x));
+  }
+  for (int i = tid(); i < N; i += nthr()) {
+    dm = fmax(dm, ws.irpart[(e0 + i) * 2]);
+    xm = fmax(xm, ws.irpart[(e0 + i) * 2 + 1]);
+  }
+  dm = block_max(dm, red);
+  xm = block_max(xm, red);
+  if (tid() == 0) {
+    const int cnt = ws.ircount[inst] + 1;
+    if (dm <= ir_tol * xm) {
+      ws.ircount[inst] = cnt;
+      ws.irflag[inst] = 1;
+    } else if (cnt >= ir_max) {
+      ws.ircount[inst] = -cnt;
+      ws.irflag[inst] = 1;
+    } else {
+      ws.ircount[inst] = cnt;
+    }
+  }
+}
+
+__global__ void k_ir_report(Ws ws, int* out, int n) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x)
+    out[t] = ws.flag[t] ? 0 : ws.ircount[t];
+}
+
+int launch_refine(const Shape& S, const Tab& tb, const HostPlan& hp, const Ws& ws, const double* rhs,
+                  double* dx, int ir_max, double ir_tol, phase_cb cb, void* ctx, hipStream_t st) {
+  const unsigned gi = (unsigned)cl_ceil_div(tb.n_inst, 256);
+  hipLaunchKernelGGL(k_ir_init, dim3(gi), dim3(256), 0, st, ws, tb.n_inst);
+  Ws wm = ws;
+  wm.flag = ws.irflag;
+  const int nt = elem_threads(S);
+  for (int s = 0; s < ir_max; ++s) {
+    if (matvec_masked(S, tb, ws, dx, ws.vtmp, ws.irflag, st)) return -3;
+    hipLaunchKernelGGL(k_ir_resid, dim3((unsigned)tb.n_elem), dim3(nt), 0, st, S, tb, ws, rhs);
+    if (launch_solve_p(S, tb, hp, wm, ws.vtmp, nullptr, ws.vtmp2, cb, ctx, st)) return -3;
+    hipLaunchKernelGGL(k_ir_update, dim3((unsigned)tb.n_elem), dim3(nt), 0, st, S, tb, ws, dx);
+    hipLaunchKernelGGL(k_ir_decide, dim3(tb.n_inst), dim3(256), 0, st, S, tb, ws, dx, ir_max, ir_tol);
+  }
+  return ok_or();
+}
+
+int launch_refine_report(const Tab& tb, const Ws& ws, int* ir_sweeps, hipStream_t st) {
+  hipLaunchKernelGGL(k_ir_report, dim3((unsigned)cl_ceil_div(tb.n_inst, 256)), dim3(256), 0, st, ws,
+                     ir_sweeps, tb.n_inst);
   return ok_or();
 }
 

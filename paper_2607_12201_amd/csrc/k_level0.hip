@@ -43,7 +43,7 @@ void launch_chain_24_7(const Shape& S, const Tab& tb, const Ws& ws, int prec, in
 
 size_t level0r_lds_bytes(const Shape& S) {
   const size_t ns = S.ns, np = S.np, jl = (size_t)S.K * S.nr;
-  size_t nd = 8 * (size_t)S.R + 8 + S.b + 7 * jl + ns + 4 * ns * ns + 4 * ns * np + np + np * np +
+  size_t nd = 8 * (size_t)S.R + 8 + S.b + 7 * jl + ns + 3 * ns * ns + 3 * ns * np + np + np * np +
               S.lsp + (size_t)S.mmax * (S.K + 1);
   size_t ni = 3 * (size_t)S.nr + 2 * (ns + 1) + (np + 1) + S.lsp + 2 * (size_t)S.lrq + S.lpc +
               S.mmax + S.R;

@@ -51,6 +51,11 @@ int launch_factor_nc(const Shape& S, const Tab& tb, const HostPlan& hp, const Ws
 int launch_solve_p(const Shape& S, const Tab& tb, const HostPlan& hp, const Ws& ws,
                    const double* rhs, const double* rthp, double* dx, phase_cb cb, void* ctx,
                    hipStream_t st);
+// FP64 iterative refinement of dx against rhs with the current factor (ws.prec), masked per
+// instance by the factor flags; ws.ircount receives the sweep counts.
+int launch_refine(const Shape& S, const Tab& tb, const HostPlan& hp, const Ws& ws, const double* rhs,
+                  double* dx, int ir_max, double ir_tol, phase_cb cb, void* ctx, hipStream_t st);
+int launch_refine_report(const Tab& tb, const Ws& ws, int* ir_sweeps, hipStream_t st);
 int launch_matvec(const Shape& S, const Tab& tb, const Ws& ws, const double* v, double* out,
                   hipStream_t st);
 int launch_copy_flags(const Tab& tb, const Ws& ws, int* info, hipStream_t st);

@@ -79,103 +79,116 @@ __device__ inline double base_entry(const Shape& S, const LTab& L, int i, double
 
 // Per-point tables of the collocation rows of point k (eq. 2b / 3).  The rows are
 // a_jk e_(j,s) - h (F_k)_(s,.) on node k and -h (Fth_k)_(s,.) on theta, weighted by d_(k,s);
-// with HF = h d F, HFt = h d Fth and the products Q1 = h^2 F^T D F + Wzz,
-// Q2 = h^2 F^T D Fth + Wzt, Q3 = h^2 Fth^T D Fth + diag(Wtt), each entry of their
-// contribution needs a few lookups.
+// with the products Q1 = h^2 F^T D F + Wzz, Q2 = h^2 F^T D Fth + Wzt and
+// Q3 = h^2 Fth^T D Fth + diag(Wtt), each entry of their contribution needs a few lookups.
 struct NodeTab {
-  double *d, *F, *Fth, *Wzz, *Wzt, *Wtt, *HF, *HFt, *Q1, *Q2, *Q3;
+  double *d, *F, *Fth, *Wzz, *Wzt, *Wtt, *Q1, *Q2, *Q3;
 };
 
-__device__ inline double node_entry(const Shape& S, const LTab& L, int k, const NodeTab& nt, int r,
-                                   int q) {
+__device__ inline double node_entry(const Shape& S, const LTab& L, int k, double h,
+                                    const NodeTab& nt, int r, int q) {
   const int ns = S.ns, np = S.np, b = S.b;
   if (r < b) {
     const int j1 = L.jdiv[r], s1 = r - j1 * ns, j2 = L.jdiv[q], s2 = q - j2 * ns;
     double a1 = S.a[j1][k], a2 = S.a[j2][k];
     double v = 0.0;
     if (s1 == s2) v += nt.d[s1] * a1 * a2;
-    if (j2 == k) v -= a1 * nt.HF[s1 * ns + s2];
-    if (j1 == k) v -= a2 * nt.HF[s2 * ns + s1];
+    if (j2 == k) v -= a1 * (h * nt.d[s1] * nt.F[s1 * ns + s2]);
+    if (j1 == k) v -= a2 * (h * nt.d[s2] * nt.F[s2 * ns + s1]);
     if (j1 == k && j2 == k) v += nt.Q1[s1 * ns + s2];
     return v;
   }
   if (q < b) {
     const int c = r - b, j1 = L.jdiv[q], s1 = q - j1 * ns;
-    double v = -S.a[j1][k] * nt.HFt[s1 * np + c];
+    double v = -S.a[j1][k] * (h * nt.d[s1] * nt.Fth[s1 * np + c]);
     if (j1 == k) v += nt.Q2[s1 * np + c];
     return v;
   }
   return nt.Q3[(r - b) * np + (q - b)];
 }
 
+// Lower-triangle index t -> (row, column) of an n x n triangle stored row by row.
+__device__ inline void tri_rc(int t, int& r, int& c) {
+  r = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+  while ((r + 1) * (r + 2) / 2 <= t) ++r;
+  while (r * (r + 1) / 2 > t) --r;
+  c = t - r * (r + 1) / 2;
+}
+
 // Build the tables of point k from the element's staged derivative values (jv, hv) and Ds.
+// Every table entry is computed by its own thread (gathers over the species' reactions or the
+// species' reactant slots), so all threads take part.
 __device__ inline void node_tables(const Shape& S, const LTab& L, int k, double h,
                                    const double* jv, const double* hv, const double* Ds_e,
                                    const NodeTab& nt) {
-  const int ns = S.ns, np = S.np, nr = S.nr;
-  for (int s = tid(); s < ns; s += nthr()) {
-    nt.d[s] = Ds_e[k * ns + s];
-    double* Fr = nt.F + s * ns;
-    double* Ftr = nt.Fth + s * np;
-    for (int q = 0; q < ns; ++q) Fr[q] = 0.0;
-    for (int c = 0; c < np; ++c) Ftr[c] = 0.0;
-    for (int q = L.sp_ptr[s]; q < L.sp_ptr[s + 1]; ++q) {
-      const int r = L.sp_r[q];
-      const double nu = L.sp_nu[q];
-      const double* jr = jv + ((k - 1) * nr + r) * 3;
-      const int q0 = L.react[2 * r], q1 = L.react[2 * r + 1], c = L.param[r];
-      if (q0 >= 0) Fr[q0] += nu * jr[0];
-      if (q1 >= 0) Fr[q1] += nu * jr[1];
-      if (c >= 0) Ftr[c] += nu * jr[2];
-    }
-  }
-  for (int q = tid(); q < ns; q += nthr()) {
-    double* Wr = nt.Wzz + q * ns;
-    double* Wtr = nt.Wzt + q * np;
-    for (int s2 = 0; s2 < ns; ++s2) Wr[s2] = 0.0;
-    for (int c = 0; c < np; ++c) Wtr[c] = 0.0;
-    for (int o = L.rq_ptr[q]; o < L.rq_ptr[q + 1]; ++o) {
-      const int r = L.rq_r[o], t = L.rq_t[o];
-      const int other = L.react[2 * r + (1 - t)], c = L.param[r];
-      const double* H = hv + ((k - 1) * nr + r) * 4;
-      if (other >= 0) Wr[other] += H[0];
-      if (c >= 0) Wtr[c] += H[1 + t];
-    }
-  }
+  const int ns = S.ns, np = S.np, nr = S.nr, nw = ns + np;
+  for (int s = tid(); s < ns; s += nthr()) nt.d[s] = Ds_e[k * ns + s];
   for (int c = tid(); c < np; c += nthr()) {
     double acc = 0.0;
     for (int o = L.pc_ptr[c]; o < L.pc_ptr[c + 1]; ++o) acc += hv[((k - 1) * nr + L.pc_r[o]) * 4 + 3];
     nt.Wtt[c] = acc;
   }
+  // F | Fth: row s = sum over the reactions of species s of nu_sr times the slot / theta partials
+  for (int t = tid(); t < ns * nw; t += nthr()) {
+    const int s = t / nw, u = t - s * nw;
+    double v = 0.0;
+    for (int o = L.sp_ptr[s]; o < L.sp_ptr[s + 1]; ++o) {
+      const int r = L.sp_r[o];
+      const double nu = L.sp_nu[o];
+      const double* jr = jv + ((k - 1) * nr + r) * 3;
+      if (u < ns) {
+        if (L.react[2 * r] == u) v += nu * jr[0];
+        if (L.react[2 * r + 1] == u) v += nu * jr[1];
+      } else if (L.param[r] == u - ns) {
+        v += nu * jr[2];
+      }
+    }
+    if (u < ns) nt.F[s * ns + u] = v;
+    else nt.Fth[s * np + (u - ns)] = v;
+  }
+  // Wzz | Wzt: row q = the weighted second derivatives of the reactions with q in a slot
+  for (int t = tid(); t < ns * nw; t += nthr()) {
+    const int q = t / nw, u = t - q * nw;
+    double v = 0.0;
+    for (int o = L.rq_ptr[q]; o < L.rq_ptr[q + 1]; ++o) {
+      const int r = L.rq_r[o], sl = L.rq_t[o];
+      const double* H = hv + ((k - 1) * nr + r) * 4;
+      if (u < ns) {
+        if (L.react[2 * r + (1 - sl)] == u) v += H[0];
+      } else if (L.param[r] == u - ns) {
+        v += H[1 + sl];
+      }
+    }
+    if (u < ns) nt.Wzz[q * ns + u] = v;
+    else nt.Wzt[q * np + (u - ns)] = v;
+  }
   __syncthreads();
-  for (int t = tid(); t < ns * ns; t += nthr()) {
-    int s = t / ns;
-    nt.HF[t] = h * nt.d[s] * nt.F[t];
-  }
-  for (int t = tid(); t < ns * np; t += nthr()) {
-    int s = t / np;
-    nt.HFt[t] = h * nt.d[s] * nt.Fth[t];
-  }
+  // Q entries: lower triangle of the (ns + np) x (ns + np) product, four partial sums each
   const double h2 = h * h;
-  const int n1 = ns * ns, n2 = ns * np, n3 = np * np;
-  for (int t = tid(); t < n1 + n2 + n3; t += nthr()) {
-    if (t < n1) {
-      int s1 = t / ns, s2 = t - s1 * ns;
-      if (s2 > s1) continue;
-      double acc = 0.0;
-      for (int s = 0; s < ns; ++s) acc += nt.d[s] * nt.F[s * ns + s1] * nt.F[s * ns + s2];
-      nt.Q1[t] = h2 * acc + nt.Wzz[t];
-    } else if (t < n1 + n2) {
-      int u = t - n1, s1 = u / np, c = u - s1 * np;
-      double acc = 0.0;
-      for (int s = 0; s < ns; ++s) acc += nt.d[s] * nt.F[s * ns + s1] * nt.Fth[s * np + c];
-      nt.Q2[u] = h2 * acc + nt.Wzt[u];
+  const int ntri = nw * (nw + 1) / 2;
+  for (int t = tid(); t < ntri; t += nthr()) {
+    int u1, u2;
+    tri_rc(t, u1, u2);
+    const double* c1 = u1 < ns ? nt.F + u1 : nt.Fth + (u1 - ns);
+    const double* c2 = u2 < ns ? nt.F + u2 : nt.Fth + (u2 - ns);
+    const int ld1 = u1 < ns ? ns : np, ld2 = u2 < ns ? ns : np;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int s = 0;
+    for (; s + 4 <= ns; s += 4) {
+      a0 += nt.d[s] * c1[s * ld1] * c2[s * ld2];
+      a1 += nt.d[s + 1] * c1[(s + 1) * ld1] * c2[(s + 1) * ld2];
+      a2 += nt.d[s + 2] * c1[(s + 2) * ld1] * c2[(s + 2) * ld2];
+      a3 += nt.d[s + 3] * c1[(s + 3) * ld1] * c2[(s + 3) * ld2];
+    }
+    for (; s < ns; ++s) a0 += nt.d[s] * c1[s * ld1] * c2[s * ld2];
+    const double acc = h2 * ((a0 + a1) + (a2 + a3));
+    if (u1 < ns) {                       // u2 <= u1 < ns
+      nt.Q1[u1 * ns + u2] = acc + nt.Wzz[u1 * ns + u2];
+    } else if (u2 < ns) {                // theta row, species column
+      nt.Q2[u2 * np + (u1 - ns)] = acc + nt.Wzt[u2 * np + (u1 - ns)];
     } else {
-      int u = t - n1 - n2, c1 = u / np, c2 = u - c1 * np;
-      if (c2 > c1) continue;
-      double acc = 0.0;
-      for (int s = 0; s < ns; ++s) acc += nt.d[s] * nt.Fth[s * np + c1] * nt.Fth[s * np + c2];
-      nt.Q3[u] = h2 * acc + (c1 == c2 ? nt.Wtt[c1] : 0.0);
+      const int c1i = u1 - ns, c2i = u2 - ns;
+      nt.Q3[c1i * np + c2i] = acc + (c1i == c2i ? nt.Wtt[c1i] : 0.0);
     }
   }
 }
@@ -250,9 +263,7 @@ __global__ void __launch_bounds__(TS* TS) k_level0r(Shape S, Tab tb, Ws ws, int 
   nt.Wzz = nt.Fth + ns * np;
   nt.Wzt = nt.Wzz + ns * ns;
   nt.Wtt = nt.Wzt + ns * np;
-  nt.HF = nt.Wtt + np;
-  nt.HFt = nt.HF + ns * ns;
-  nt.Q1 = nt.HFt + ns * np;
+  nt.Q1 = nt.Wtt + np;
   nt.Q2 = nt.Q1 + ns * ns;
   nt.Q3 = nt.Q2 + ns * np;
   LTab L;
@@ -296,7 +307,7 @@ __global__ void __launch_bounds__(TS* TS) k_level0r(Shape S, Tab tb, Ws ws, int 
 #pragma unroll
         for (int J = 0; J <= I; ++J) {
           const int r = I * TS + ty, q = J * TS + tx;
-          if (r < bp && q <= r) av[I * (I + 1) / 2 + J] += node_entry(S, L, k, nt, r, q);
+          if (r < bp && q <= r) av[I * (I + 1) / 2 + J] += node_entry(S, L, k, h, nt, r, q);
         }
     }
     if (sizeof(T) == 4) {  // FP32 factors: keep the assembled theta-theta block in FP64

@@ -12,7 +12,7 @@ namespace cl {
 
 // Right-looking elimination of the first mI columns on register-resident entries, in
 // panels of up to 4 columns: the owners copy the panel (rows >= c0) into LDS, one wave factors
-// it there, the owners take the factored columns back and every thread applies the rank-w
+// it in registers, the owners take the factored columns back and every thread applies the rank-w
 // update to its entries right of the panel.  pbuf: two R x 4 buffers (alternating panels).
 template <typename T, int TS, int NB>
 __device__ inline bool eliminate_regs(T* acc, int mI, int R, int ty, int tx, double* pbuf,
@@ -37,28 +37,49 @@ __device__ inline bool eliminate_regs(T* acc, int mI, int R, int ty, int tx, dou
       }
       __syncthreads();
       if (tid() < 64) {
+        // wave 0 factors the panel in registers: lane t holds panel rows c0 + t + 64 m
+        // (R - c0 <= 192); the pivot row values come from their owner lanes by shuffles
         const int lane = tid();
-        for (int cl = 0; cl < w; ++cl) {
-          const int c = c0 + cl;
-          if (lane == 0) {
-            double piv = P[c * 4 + cl];
-            bool good = piv > 0.0 && isfinite(piv);
-            double sq = good ? sqrt(piv) : 1.0;
-            P[c * 4 + cl] = sq;
-            misc[0] = good ? 1.0 : 0.0;
-            misc[1] = 1.0 / sq;
-          }
-          __builtin_amdgcn_wave_barrier();
-          if (misc[0] == 0.0) break;
-          const double inv = misc[1];
-          for (int r = c + 1 + lane; r < R; r += 64) P[r * 4 + cl] *= inv;
-          __builtin_amdgcn_wave_barrier();
-          for (int cl2 = cl + 1; cl2 < w; ++cl2) {
-            const double lc = P[(c0 + cl2) * 4 + cl];
-            for (int r = c0 + cl2 + lane; r < R; r += 64) P[r * 4 + cl2] -= P[r * 4 + cl] * lc;
-          }
-          __builtin_amdgcn_wave_barrier();
+        double p[3][4];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          const int r = c0 + lane + 64 * m;
+#pragma unroll
+          for (int cl = 0; cl < 4; ++cl) p[m][cl] = (r < R && cl < w) ? P[r * 4 + cl] : 0.0;
         }
+        bool good = true;
+#pragma unroll
+        for (int cl = 0; cl < 4; ++cl) {
+          if (cl < w && good) {
+            const double piv = __shfl(p[0][cl], cl);
+            good = piv > 0.0 && isfinite(piv);
+            const double sq = good ? sqrt(piv) : 1.0;
+            const double inv = 1.0 / sq;
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+              const int rl = lane + 64 * m;
+              if (rl == cl) p[m][cl] = sq;
+              else if (rl > cl) p[m][cl] *= inv;
+            }
+#pragma unroll
+            for (int cl2 = cl + 1; cl2 < 4; ++cl2) {
+              if (cl2 < w) {
+                const double lc = __shfl(p[0][cl], cl2);
+#pragma unroll
+                for (int m = 0; m < 3; ++m)
+                  if (lane + 64 * m >= cl2) p[m][cl2] -= p[m][cl] * lc;
+              }
+            }
+          }
+        }
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          const int r = c0 + lane + 64 * m;
+#pragma unroll
+          for (int cl = 0; cl < 4; ++cl)
+            if (r < R && cl < w) P[r * 4 + cl] = p[m][cl];
+        }
+        if (lane == 0) misc[0] = good ? 1.0 : 0.0;
       }
       __syncthreads();
       if (misc[0] == 0.0) return false;

@@ -100,7 +100,8 @@ def test_create_and_layout(lib):
     assert lib.colloc_table_bytes(h) % 256 == 0 and lib.colloc_table_bytes(h) > 0
     w64 = lib.colloc_workspace_bytes(h, colloc.FP64)
     w32 = lib.colloc_workspace_bytes(h, colloc.FP32_IR)
-    assert w64 > w32 > 0
+    # FP32_IR keeps room for its per-instance FP64 re-factorization
+    assert w64 == w32 > 0
     assert lib.colloc_workspace_bytes(h, 7) == 0
     assert lib.colloc_state_bytes(h) > 0
     sl = colloc.StateLayout()
