@@ -72,6 +72,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--workload", default="net20_n1000", choices=["net20_n1000", "multistart", "serving"],
+                    help="net20_n1000: one 20-species instance, FP64 (the headline line); "
+                         "multistart: 256 uneven A<->B instances batched, FP32 factors + FP64 "
+                         "refinement, graph-replayed steps, autotuned thread grids; serving: "
+                         "Poisson arrivals of uneven requests through the continuous-batching "
+                         "loop against the sequential per-instance FP64 path")
+    ap.add_argument("--requests", type=int, default=60)
+    ap.add_argument("--load", type=float, default=0.8,
+                    help="arrival rate as a fraction of the per-instance path's saturation rate")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before the timed region, copy a buffer of this size once (a plain "
                          "copy kernel of known traffic for scaling HBM counters)")
@@ -80,6 +89,11 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(instances shard trivially across GPUs; see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "multistart":
+        return bench_multistart(args)
+    if args.workload == "serving":
+        return bench_serving(args)
 
     import torch
     from paper_2607_12201_amd import colloc, workloads
@@ -149,6 +163,144 @@ def main():
     }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(inst, K, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+def _run_steps(P, state, ws, opts, steps, graph=None):
+    for _ in range(steps):
+        if graph is not None:
+            P.graph_launch(graph)
+        else:
+            P.ipm_step(state, ws, opts)
+
+
+def bench_multistart(args):
+    """Batched multi-start: 256 A<->B instances, N uniform in [200, 2000] (multiples of 10),
+    K = 3, random starting parameters; one replayed HIP graph per interior-point step, FP32
+    block factors with FP64 refinement, thread grids from the autotuner.  value = Newton
+    iterations completed per second summed over the instances.  Beside it: the plain FP64
+    per-instance path (one handle per instance, eager steps) timed on a sample of instances."""
+    import torch
+    from paper_2607_12201_amd import autotune, colloc, workloads
+
+    K = 3
+    insts = workloads.multistart_batch(256, 200, 2000)
+    P = colloc.Problem(insts, K)
+    opts = colloc.default_opts(precision=colloc.FP32_IR)
+    tiles = autotune.tune(P, precision=colloc.FP32_IR)
+    x0 = torch.tensor(np.concatenate([workloads.initial_point(i, K) for i in insts]),
+                      dtype=torch.float64, device="cuda")
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        ws, state = P.workspace(colloc.FP32_IR), P.state()
+        P.ipm_init(x0, state, ws, opts)
+        g = P.graph_create(state, ws, opts, steps=1)
+        _run_steps(P, state, ws, opts, args.warmup, g)
+        P.ipm_init(x0, state, ws, opts)
+        side.synchronize()
+        it0 = P.info(state)["iter"].astype(np.int64).sum()
+        t0 = time.perf_counter()
+        _run_steps(P, state, ws, opts, args.steps, g)
+        side.synchronize()
+        dt = time.perf_counter() - t0
+        info = P.info(state)
+        P.graph_destroy(g)
+    newton = int(info["iter"].astype(np.int64).sum() - it0)
+    # plain FP64 per-instance path on a sample of the same instances
+    sample = insts[:: max(1, len(insts) // 8)][:8]
+    o64 = colloc.default_opts()
+    tot_it, tot_t = 0, 0.0
+    for inst in sample:
+        P1 = colloc.Problem(inst, K)
+        ws1, st1 = P1.workspace(), P1.state()
+        P1.ipm_init(torch.tensor(workloads.initial_point(inst, K), dtype=torch.float64, device="cuda"),
+                    st1, ws1, o64)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _run_steps(P1, st1, ws1, o64, args.steps)
+        torch.cuda.synchronize()
+        tot_t += time.perf_counter() - t1
+        tot_it += int(P1.info(st1)[0]["iter"])
+    line = {
+        "metric": "IPM Newton steps/s (AD+KKT factor+solve), batched mixed precision",
+        "value": newton / dt,
+        "unit": "Newton steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 factors + f64 refinement",
+        "data": "synthetic",
+        "config": {"workload": "256 A<->B multi-start instances, N uniform in [200, 2000], K=3, "
+                               "FP32 block factors + FP64 refinement, graph-replayed steps",
+                   "total_elements": int(P.n_elem), "newton_steps": newton,
+                   "solved": int(np.sum(info["status"] == colloc.SOLVED)),
+                   "ir_fallbacks": int(info["ir_fallbacks"].sum()), "tiles": {
+                       k: tiles[k] for k in colloc.Problem.TILE_KERNELS},
+                   "per_instance_fp64_newton_steps_per_s": tot_it / tot_t,
+                   "per_instance_sample": len(sample)},
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_serving(args):
+    """Serving: requests with n_s uniform in 5..20 species (n_r = n_p = 2 n_s), N log-uniform in
+    [100, 2000] (multiples of 50), arriving as a Poisson process at `load` times the saturation
+    rate of the plain FP64 per-instance path (one request at a time, first come first served).
+    The batched path admits requests under an HBM budget and batches them per shape class with
+    FP32 factors + FP64 refinement.  Latency = arrival to result.  Both paths run every request
+    of the same trace; the per-instance latencies follow from its measured service times."""
+    import torch
+    from paper_2607_12201_amd import colloc, serving, workloads
+
+    _, insts = workloads.serving_trace(args.requests, 1.0, seed=11, ns_lo=5, ns_hi=20, N_lo=100,
+                                       N_hi=2000)
+    o64 = colloc.default_opts()
+    service, ok64 = [], 0
+    serving.solve_alone(insts[0], o64)       # warm-up (code load)
+    for inst in insts:
+        st, it, x, obj, dt = serving.solve_alone(inst, o64)
+        service.append(dt)
+        ok64 += st in (colloc.SOLVED, colloc.ACCEPTABLE)
+    service = np.array(service)
+    rate = args.load / service.mean()
+    rng = np.random.default_rng(12)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, len(insts)))
+    lat64 = serving.fifo_latencies(arrivals, service)
+    makespan64 = float(np.max(arrivals + lat64) - arrivals[0])
+    reqs = [serving.Request(q, float(a), inst) for q, (a, inst) in enumerate(zip(arrivals, insts))]
+    opts = colloc.default_opts(precision=colloc.FP32_IR)
+    budget = 8 * 2 ** 30
+    torch.cuda.synchronize()
+    res = serving.serve(reqs, opts, budget, steps_per_round=4)
+    summ = res.summary()
+    lat = res.latencies()
+    line = {
+        "metric": "solves/s and p50/p99 latency, continuous batching vs per-instance FP64",
+        "value": summ["requests"] / (max(r.t_done for r in reqs) - float(arrivals[0])),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": int(res.steps),
+        "warmup": 1,
+        "ms_per_step": 1e3 * res.wall / max(1, res.steps),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 factors + f64 refinement",
+        "data": "synthetic",
+        "config": {"workload": f"{len(insts)} Poisson requests, n_s 5-20, N 100-2000, K=3, "
+                               f"load {args.load} of the per-instance FP64 saturation rate",
+                   "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+                   "solved": summ["solved"], "peak_bytes": summ["peak_bytes"],
+                   "hbm_budget_bytes": budget,
+                   "per_instance_fp64": {"solves_per_s": len(insts) / makespan64,
+                                         "p50_s": float(np.percentile(lat64, 50)),
+                                         "p99_s": float(np.percentile(lat64, 99)),
+                                         "mean_service_s": float(service.mean()), "solved": int(ok64)}},
+    }
     print(json.dumps(line), flush=True)
 
 

@@ -246,9 +246,13 @@ int ipm_graph_launch(colloc_graph* g, hipStream_t stream);
 int ipm_graph_destroy(colloc_graph* g);
 
 /* Byte offsets of the state buffer's fields: x[n_total], s, y, vL, vU [m_total], zL, zU
- * [n_inst*n_p], dx[n_total], info[n_inst] (colloc_ipm_info). */
+ * [n_inst*n_p], dx[n_total], ds, dy [m_total], info[n_inst] (colloc_ipm_info), and the filter
+ * entries fth, fph [n_inst][COLLOC_FILTER_CAP].  An instance's iterate between two ipm_step
+ * calls (status RUNNING with no pending inertia retry, or finished) is its segments of x, s, y,
+ * vL, vU, zL, zU, fth, fph and its info record: copying them into another state buffer moves
+ * the instance to another batch (continuous batching). */
 typedef struct colloc_state_layout {
-  size_t x, s, y, vL, vU, zL, zU, dx, ds, dy, info;
+  size_t x, s, y, vL, vU, zL, zU, dx, ds, dy, info, fth, fph;
 } colloc_state_layout;
 int colloc_state_layout_get(const colloc_problem* p, colloc_state_layout* out);
 
@@ -260,6 +264,18 @@ enum {
 };
 int colloc_timing_enable(colloc_problem* p, int32_t enable);
 int colloc_timing_read(colloc_problem* p, double* ms, int64_t* launches, int32_t n);
+
+/* Thread-grid choice of the register-resident elimination kernels (the tuning hook of
+ * paper_2607_12201_amd.autotune).  which: 0 = element (level-0) kernel, 1 = separator-chain
+ * kernel, 2 = border kernel.  A kernel runs on a TS x TS thread grid holding its matrix in
+ * registers, ceil(rows / TS) blocks per side.  colloc_tile_options writes the usable TS for this
+ * handle's shape into ts[0..cap) and returns their count (negative on bad arguments);
+ * colloc_tile_set selects one (0 = built-in rule) and returns COLLOC_EINVAL for a TS the shape
+ * cannot use; colloc_tile_get returns the current choice (0 = built-in rule).  The choice changes
+ * which thread computes an entry, not the arithmetic: results are identical for every choice. */
+int colloc_tile_options(const colloc_problem* p, int32_t which, int32_t* ts, int32_t cap);
+int colloc_tile_set(colloc_problem* p, int32_t which, int32_t ts);
+int colloc_tile_get(const colloc_problem* p, int32_t which);
 
 /* Collocation tables computed by the library (tau[K+1], a[(K+1)*(K+1)] with a[j*(K+1)+k] =
  * l_j'(tau_k)), for inspection. */

@@ -69,7 +69,8 @@ class Layout(C.Structure):
 
 
 class StateLayout(C.Structure):
-    _fields_ = [(n, C.c_size_t) for n in ("x", "s", "y", "vL", "vU", "zL", "zU", "dx", "ds", "dy", "info")]
+    _fields_ = [(n, C.c_size_t) for n in ("x", "s", "y", "vL", "vU", "zL", "zU", "dx", "ds", "dy", "info",
+                                          "fth", "fph")]
 
 
 EXPORTS = [
@@ -78,7 +79,7 @@ EXPORTS = [
     "kkt_assemble", "kkt_factor", "kkt_solve", "kkt_matvec", "colloc_ipm_default_opts",
     "ipm_init", "ipm_step", "colloc_state_layout_get", "colloc_timing_enable",
     "colloc_timing_read", "colloc_tables", "ipm_graph_create", "ipm_graph_launch",
-    "ipm_graph_destroy",
+    "ipm_graph_destroy", "colloc_tile_options", "colloc_tile_set", "colloc_tile_get",
 ]
 
 _lib = None
@@ -117,6 +118,9 @@ def load(path: str = LIB_PATH):
         "ipm_graph_create": (i32, [vp, vp, vp, C.POINTER(IpmOpts), i32, vp, C.POINTER(vp)]),
         "ipm_graph_launch": (i32, [vp, vp]),
         "ipm_graph_destroy": (i32, [vp]),
+        "colloc_tile_options": (i32, [vp, i32, C.POINTER(i32), i32]),
+        "colloc_tile_set": (i32, [vp, i32, i32]),
+        "colloc_tile_get": (i32, [vp, i32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -160,7 +164,8 @@ def _stream():
 class Problem:
     """A batch of instances of one shape class on the current CUDA device."""
 
-    def __init__(self, instances, K: int = 3, device: str = "cuda"):
+    def __init__(self, instances, K: int = 3, device: str = "cuda", upload: bool = True):
+        """upload=False builds a host-only handle (sizes and layouts; no device call)."""
         import torch
 
         self.torch = torch
@@ -201,10 +206,12 @@ class Problem:
         self.g_off = np.array([lay.g_off[q] for q in range(self.n_inst)])
         self.Ns = np.array([lay.N[q] for q in range(self.n_inst)])
         tb = self.lib.colloc_table_bytes(h)
-        self.table = torch.empty(tb + 256, dtype=torch.uint8, device=device)
-        off = (-self.table.data_ptr()) % 256
-        self.table_view = self.table[off:off + tb]
-        _check(self.lib.colloc_upload(h, _ptr(self.table_view), _stream()), "colloc_upload")
+        self.table_bytes = int(tb)
+        if upload:
+            self.table = torch.empty(tb + 256, dtype=torch.uint8, device=device)
+            off = (-self.table.data_ptr()) % 256
+            self.table_view = self.table[off:off + tb]
+            _check(self.lib.colloc_upload(h, _ptr(self.table_view), _stream()), "colloc_upload")
         sl = StateLayout()
         _check(self.lib.colloc_state_layout_get(h, C.byref(sl)), "colloc_state_layout_get")
         self.state_layout = {n: getattr(sl, n) for n, _ in StateLayout._fields_}
@@ -231,6 +238,11 @@ class Problem:
             pass
 
     # -- buffers ----------------------------------------------------------------------
+    def device_bytes(self, precision=FP64):
+        """Device memory of this batch: tables + interior-point state + workspace."""
+        return (self.table_bytes + 256 + int(self.lib.colloc_state_bytes(self.h)) +
+                int(self.lib.colloc_workspace_bytes(self.h, precision)))
+
     def workspace(self, precision=FP64):
         n = self.lib.colloc_workspace_bytes(self.h, precision)
         return self.torch.zeros(n, dtype=self.torch.uint8, device=self.device)
@@ -308,6 +320,22 @@ class Problem:
 
     def graph_destroy(self, g):
         _check(self.lib.ipm_graph_destroy(g), "ipm_graph_destroy")
+
+    # -- tuning hook ---------------------------------------------------------------------
+    TILE_KERNELS = ("level0", "chain", "border")
+
+    def tile_options(self, which):
+        buf = (C.c_int32 * 8)()
+        n = self.lib.colloc_tile_options(self.h, self.TILE_KERNELS.index(which), buf, 8)
+        if n < 0:
+            raise RuntimeError(f"colloc_tile_options failed with code {n}")
+        return [int(buf[i]) for i in range(min(n, 8))]
+
+    def tile_set(self, which, ts):
+        _check(self.lib.colloc_tile_set(self.h, self.TILE_KERNELS.index(which), int(ts)), "colloc_tile_set")
+
+    def tile_get(self, which):
+        return int(self.lib.colloc_tile_get(self.h, self.TILE_KERNELS.index(which)))
 
     def state_vec(self, state, name, n=None):
         off = self.state_layout[name]

@@ -610,7 +610,11 @@ static IpmState state_layout(const colloc_problem* p, void* base, size_t* bytes,
   s.grad = c.take<double>(n);
   s.rhs = c.take<double>(n);
   s.fth = c.take<double>(I * CL_FILTER_CAP);
+  o = c.off - I * CL_FILTER_CAP * 8;
+  if (lay) lay->fth = o;
   s.fph = c.take<double>(I * CL_FILTER_CAP);
+  o = c.off - I * CL_FILTER_CAP * 8;
+  if (lay) lay->fph = o;
   s.tpart = c.take<double>(E * CL_MAX_LS * 3);
   s.info = c.take<colloc_ipm_info>(I);
   o = c.off - I * sizeof(colloc_ipm_info);
@@ -820,6 +824,25 @@ extern "C" int ipm_graph_destroy(colloc_graph* g) {
   if (g->graph) hipGraphDestroy(g->graph);
   delete g;
   return COLLOC_OK;
+}
+
+extern "C" int colloc_tile_options(const colloc_problem* p, int32_t which, int32_t* ts, int32_t cap) {
+  CHECK(p && which >= 0 && which <= 2 && cap >= 0 && (ts || cap == 0));
+  int tmp[8];
+  const int n = tile_options(p->S, which, tmp, 8);
+  for (int i = 0; i < n && i < cap; ++i) ts[i] = tmp[i];
+  return n;
+}
+
+extern "C" int colloc_tile_set(colloc_problem* p, int32_t which, int32_t ts) {
+  CHECK(p && which >= 0 && which <= 2 && tile_valid(p->S, which, ts));
+  p->hp.ts[which] = ts;
+  return COLLOC_OK;
+}
+
+extern "C" int colloc_tile_get(const colloc_problem* p, int32_t which) {
+  CHECK(p && which >= 0 && which <= 2);
+  return p->hp.ts[which];
 }
 
 extern "C" int colloc_timing_enable(colloc_problem* p, int32_t enable) {

@@ -874,20 +874,20 @@ template <typename T>
 static int factor_t(const Shape& S, const Tab& tb, const HostPlan& hp, const Ws& ws, bool fused,
                     phase_cb cb, void* ctx, hipStream_t st) {
   if (cb) cb(ctx, 1, 1, st);
-  if (launch_level0(S, tb, ws, sizeof(T) == 4 ? 1 : 0, fused, st)) return -4;
+  if (launch_level0(S, tb, ws, sizeof(T) == 4 ? 1 : 0, fused, hp.ts[0], st)) return -4;
   if (cb) cb(ctx, 1, 0, st);
   const int np = S.np;
   const int prec = sizeof(T) == 4 ? 1 : 0;
   if (cb) cb(ctx, 2, 1, st);
   int rc = 0;
-  if (tb.L >= 1) rc |= launch_chain(S, tb, ws, prec, 0, 1, hp.lvl[1], st);
-  for (int l = 1; l < tb.L; ++l) rc |= launch_chain(S, tb, ws, prec, 1, l, hp.st[l], st);
+  if (tb.L >= 1) rc |= launch_chain(S, tb, ws, prec, 0, 1, hp.lvl[1], hp.ts[1], st);
+  for (int l = 1; l < tb.L; ++l) rc |= launch_chain(S, tb, ws, prec, 1, l, hp.st[l], hp.ts[1], st);
   if (cb) cb(ctx, 2, 0, st);
   if (cb) cb(ctx, 3, 1, st);
   const unsigned tiles = (unsigned)cl_ceil_div(np * np, 256);
   hipLaunchKernelGGL(k_thred, dim3(ws.nchunk, tiles, tb.n_inst), dim3(256), 0, st, S, tb, ws);
   hipLaunchKernelGGL(k_thred2, dim3(tiles, tb.n_inst), dim3(256), 0, st, S, tb, ws);
-  rc |= launch_chain(S, tb, ws, prec, 2, 0, tb.n_inst, st);
+  rc |= launch_chain(S, tb, ws, prec, 2, 0, tb.n_inst, hp.ts[2], st);
   if (rc) return -4;
   if (cb) cb(ctx, 3, 0, st);
   return ok_or();

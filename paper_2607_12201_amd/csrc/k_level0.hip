@@ -1,45 +1,107 @@
-// Level-0 dispatch: picks the thread-grid size and register block count for the shape.
+// Dispatch of the register-resident elimination kernels: thread grid TS x TS (TS in 8, 16,
+// 24) with NB = ceil(rows / TS) register blocks per side.  The built-in rule picks the smallest
+// grid whose block count stays within the instantiated range; a handle may override the grid
+// per kernel (tuning).
 #include "kernels.h"
 
 namespace cl {
-void launch_level0_8_1(const Shape& S, const Tab& tb, const Ws& ws, int prec, int fused, hipStream_t st);
-void launch_level0_8_2(const Shape& S, const Tab& tb, const Ws& ws, int prec, int fused, hipStream_t st);
-void launch_level0_8_3(const Shape& S, const Tab& tb, const Ws& ws, int prec, int fused, hipStream_t st);
-void launch_level0_8_4(const Shape& S, const Tab& tb, const Ws& ws, int prec, int fused, hipStream_t st);
-void launch_level0_16_3(const Shape& S, const Tab& tb, const Ws& ws, int prec, int fused, hipStream_t st);
-void launch_level0_16_4(const Shape& S, const Tab& tb, const Ws& ws, int prec, int fused, hipStream_t st);
-void launch_level0_16_5(const Shape& S, const Tab& tb, const Ws& ws, int prec, int fused, hipStream_t st);
-void launch_level0_16_6(const Shape& S, const Tab& tb, const Ws& ws, int prec, int fused, hipStream_t st);
-void launch_level0_16_7(const Shape& S, const Tab& tb, const Ws& ws, int prec, int fused, hipStream_t st);
-void launch_level0_16_8(const Shape& S, const Tab& tb, const Ws& ws, int prec, int fused, hipStream_t st);
-void launch_level0_24_6(const Shape& S, const Tab& tb, const Ws& ws, int prec, int fused, hipStream_t st);
-void launch_level0_24_7(const Shape& S, const Tab& tb, const Ws& ws, int prec, int fused, hipStream_t st);
+void launch_level0_8_1(const Shape&, const Tab&, const Ws&, int, int, hipStream_t);
+int attrs_level0_8_1(size_t);
+void launch_chain_8_1(const Shape&, const Tab&, const Ws&, int, int, int, unsigned, size_t, hipStream_t);
+void launch_level0_8_2(const Shape&, const Tab&, const Ws&, int, int, hipStream_t);
+int attrs_level0_8_2(size_t);
+void launch_chain_8_2(const Shape&, const Tab&, const Ws&, int, int, int, unsigned, size_t, hipStream_t);
+void launch_level0_8_3(const Shape&, const Tab&, const Ws&, int, int, hipStream_t);
+int attrs_level0_8_3(size_t);
+void launch_chain_8_3(const Shape&, const Tab&, const Ws&, int, int, int, unsigned, size_t, hipStream_t);
+void launch_level0_8_4(const Shape&, const Tab&, const Ws&, int, int, hipStream_t);
+int attrs_level0_8_4(size_t);
+void launch_chain_8_4(const Shape&, const Tab&, const Ws&, int, int, int, unsigned, size_t, hipStream_t);
+void launch_level0_16_1(const Shape&, const Tab&, const Ws&, int, int, hipStream_t);
+int attrs_level0_16_1(size_t);
+void launch_chain_16_1(const Shape&, const Tab&, const Ws&, int, int, int, unsigned, size_t, hipStream_t);
+void launch_level0_16_2(const Shape&, const Tab&, const Ws&, int, int, hipStream_t);
+int attrs_level0_16_2(size_t);
+void launch_chain_16_2(const Shape&, const Tab&, const Ws&, int, int, int, unsigned, size_t, hipStream_t);
+void launch_level0_24_2(const Shape&, const Tab&, const Ws&, int, int, hipStream_t);
+int attrs_level0_24_2(size_t);
+void launch_chain_24_2(const Shape&, const Tab&, const Ws&, int, int, int, unsigned, size_t, hipStream_t);
+void launch_level0_24_3(const Shape&, const Tab&, const Ws&, int, int, hipStream_t);
+int attrs_level0_24_3(size_t);
+void launch_chain_24_3(const Shape&, const Tab&, const Ws&, int, int, int, unsigned, size_t, hipStream_t);
+void launch_level0_16_3(const Shape&, const Tab&, const Ws&, int, int, hipStream_t);
+int attrs_level0_16_3(size_t);
+void launch_chain_16_3(const Shape&, const Tab&, const Ws&, int, int, int, unsigned, size_t, hipStream_t);
+void launch_level0_16_4(const Shape&, const Tab&, const Ws&, int, int, hipStream_t);
+int attrs_level0_16_4(size_t);
+void launch_chain_16_4(const Shape&, const Tab&, const Ws&, int, int, int, unsigned, size_t, hipStream_t);
+void launch_level0_16_5(const Shape&, const Tab&, const Ws&, int, int, hipStream_t);
+int attrs_level0_16_5(size_t);
+void launch_chain_16_5(const Shape&, const Tab&, const Ws&, int, int, int, unsigned, size_t, hipStream_t);
+void launch_level0_16_6(const Shape&, const Tab&, const Ws&, int, int, hipStream_t);
+int attrs_level0_16_6(size_t);
+void launch_chain_16_6(const Shape&, const Tab&, const Ws&, int, int, int, unsigned, size_t, hipStream_t);
+void launch_level0_16_7(const Shape&, const Tab&, const Ws&, int, int, hipStream_t);
+int attrs_level0_16_7(size_t);
+void launch_chain_16_7(const Shape&, const Tab&, const Ws&, int, int, int, unsigned, size_t, hipStream_t);
+void launch_level0_16_8(const Shape&, const Tab&, const Ws&, int, int, hipStream_t);
+int attrs_level0_16_8(size_t);
+void launch_chain_16_8(const Shape&, const Tab&, const Ws&, int, int, int, unsigned, size_t, hipStream_t);
+void launch_level0_24_4(const Shape&, const Tab&, const Ws&, int, int, hipStream_t);
+int attrs_level0_24_4(size_t);
+void launch_chain_24_4(const Shape&, const Tab&, const Ws&, int, int, int, unsigned, size_t, hipStream_t);
+void launch_level0_24_5(const Shape&, const Tab&, const Ws&, int, int, hipStream_t);
+int attrs_level0_24_5(size_t);
+void launch_chain_24_5(const Shape&, const Tab&, const Ws&, int, int, int, unsigned, size_t, hipStream_t);
+void launch_level0_24_6(const Shape&, const Tab&, const Ws&, int, int, hipStream_t);
+int attrs_level0_24_6(size_t);
+void launch_chain_24_6(const Shape&, const Tab&, const Ws&, int, int, int, unsigned, size_t, hipStream_t);
+void launch_level0_24_7(const Shape&, const Tab&, const Ws&, int, int, hipStream_t);
+int attrs_level0_24_7(size_t);
+void launch_chain_24_7(const Shape&, const Tab&, const Ws&, int, int, int, unsigned, size_t, hipStream_t);
 
-int attrs_level0_8_1(size_t bytes);
-int attrs_level0_8_2(size_t bytes);
-int attrs_level0_8_3(size_t bytes);
-int attrs_level0_8_4(size_t bytes);
-int attrs_level0_16_3(size_t bytes);
-int attrs_level0_16_4(size_t bytes);
-int attrs_level0_16_5(size_t bytes);
-int attrs_level0_16_6(size_t bytes);
-int attrs_level0_16_7(size_t bytes);
-int attrs_level0_16_8(size_t bytes);
-int attrs_level0_24_6(size_t bytes);
-int attrs_level0_24_7(size_t bytes);
+namespace {
+struct Variant {
+  int ts, nb;
+  void (*level0)(const Shape&, const Tab&, const Ws&, int, int, hipStream_t);
+  int (*attrs)(size_t);
+  void (*chain)(const Shape&, const Tab&, const Ws&, int, int, int, unsigned, size_t, hipStream_t);
+};
+const Variant kVariants[] = {
+    {8, 1, launch_level0_8_1, attrs_level0_8_1, launch_chain_8_1},
+    {8, 2, launch_level0_8_2, attrs_level0_8_2, launch_chain_8_2},
+    {8, 3, launch_level0_8_3, attrs_level0_8_3, launch_chain_8_3},
+    {8, 4, launch_level0_8_4, attrs_level0_8_4, launch_chain_8_4},
+    {16, 1, launch_level0_16_1, attrs_level0_16_1, launch_chain_16_1},
+    {16, 2, launch_level0_16_2, attrs_level0_16_2, launch_chain_16_2},
+    {24, 2, launch_level0_24_2, attrs_level0_24_2, launch_chain_24_2},
+    {24, 3, launch_level0_24_3, attrs_level0_24_3, launch_chain_24_3},
+    {16, 3, launch_level0_16_3, attrs_level0_16_3, launch_chain_16_3},
+    {16, 4, launch_level0_16_4, attrs_level0_16_4, launch_chain_16_4},
+    {16, 5, launch_level0_16_5, attrs_level0_16_5, launch_chain_16_5},
+    {16, 6, launch_level0_16_6, attrs_level0_16_6, launch_chain_16_6},
+    {16, 7, launch_level0_16_7, attrs_level0_16_7, launch_chain_16_7},
+    {16, 8, launch_level0_16_8, attrs_level0_16_8, launch_chain_16_8},
+    {24, 4, launch_level0_24_4, attrs_level0_24_4, launch_chain_24_4},
+    {24, 5, launch_level0_24_5, attrs_level0_24_5, launch_chain_24_5},
+    {24, 6, launch_level0_24_6, attrs_level0_24_6, launch_chain_24_6},
+    {24, 7, launch_level0_24_7, attrs_level0_24_7, launch_chain_24_7}
+};
 
-void launch_chain_8_1(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level, unsigned grid, size_t lds, hipStream_t st);
-void launch_chain_8_2(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level, unsigned grid, size_t lds, hipStream_t st);
-void launch_chain_8_3(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level, unsigned grid, size_t lds, hipStream_t st);
-void launch_chain_8_4(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level, unsigned grid, size_t lds, hipStream_t st);
-void launch_chain_16_3(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level, unsigned grid, size_t lds, hipStream_t st);
-void launch_chain_16_4(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level, unsigned grid, size_t lds, hipStream_t st);
-void launch_chain_16_5(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level, unsigned grid, size_t lds, hipStream_t st);
-void launch_chain_16_6(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level, unsigned grid, size_t lds, hipStream_t st);
-void launch_chain_16_7(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level, unsigned grid, size_t lds, hipStream_t st);
-void launch_chain_16_8(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level, unsigned grid, size_t lds, hipStream_t st);
-void launch_chain_24_6(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level, unsigned grid, size_t lds, hipStream_t st);
-void launch_chain_24_7(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level, unsigned grid, size_t lds, hipStream_t st);
+const Variant* find_variant(int ts, int rows) {
+  const int nb = (int)cl_ceil_div(rows, ts);
+  for (const Variant& v : kVariants)
+    if (v.ts == ts && v.nb == nb) return &v;
+  return nullptr;
+}
+
+// Built-in rule: 8 x 8 up to 32 rows, 16 x 16 up to 128, 24 x 24 above.
+int default_ts(int rows) { return rows <= 32 ? 8 : (rows <= 128 ? 16 : 24); }
+
+const Variant* pick(int ts, int rows) {
+  return find_variant(ts > 0 ? ts : default_ts(rows), rows);
+}
+}  // namespace
 
 size_t level0r_lds_bytes(const Shape& S) {
   const size_t ns = S.ns, np = S.np, jl = (size_t)S.K * S.nr;
@@ -52,90 +114,54 @@ size_t level0r_lds_bytes(const Shape& S) {
 
 bool level0r_supported(const Shape& S) { return S.R <= 160 && 3 * S.ns + S.np <= 160; }
 
-int launch_level0(const Shape& S, const Tab& tb, const Ws& ws, int prec, bool fused, hipStream_t st) {
-  const int f = fused ? 1 : 0;
-  if (S.R <= 32) {
-    switch ((int)cl_ceil_div(S.R, 8)) {
-      case 1: launch_level0_8_1(S, tb, ws, prec, f, st); return 0;
-      case 2: launch_level0_8_2(S, tb, ws, prec, f, st); return 0;
-      case 3: launch_level0_8_3(S, tb, ws, prec, f, st); return 0;
-      case 4: launch_level0_8_4(S, tb, ws, prec, f, st); return 0;
+int chain_rows(const Shape& S, int which) { return which == 2 ? S.ns + S.np : 3 * S.ns + S.np; }
+
+int tile_rows(const Shape& S, int which) { return which == 0 ? S.R : chain_rows(S, which); }
+
+int tile_options(const Shape& S, int which, int* ts, int cap) {
+  const int rows = tile_rows(S, which);
+  int n = 0;
+  for (int t : {8, 16, 24})
+    if (find_variant(t, rows)) {
+      if (n < cap) ts[n] = t;
+      ++n;
     }
-  }
-  if (S.R > 128) {
-    switch ((int)cl_ceil_div(S.R, 24)) {
-      case 6: launch_level0_24_6(S, tb, ws, prec, f, st); return 0;
-      case 7: launch_level0_24_7(S, tb, ws, prec, f, st); return 0;
-    }
-    return -1;
-  }
-  switch ((int)cl_ceil_div(S.R, 16)) {
-    case 3: launch_level0_16_3(S, tb, ws, prec, f, st); return 0;
-    case 4: launch_level0_16_4(S, tb, ws, prec, f, st); return 0;
-    case 5: launch_level0_16_5(S, tb, ws, prec, f, st); return 0;
-    case 6: launch_level0_16_6(S, tb, ws, prec, f, st); return 0;
-    case 7: launch_level0_16_7(S, tb, ws, prec, f, st); return 0;
-    case 8: launch_level0_16_8(S, tb, ws, prec, f, st); return 0;
-  }
-  return -1;
+  return n;
+}
+
+bool tile_valid(const Shape& S, int which, int ts) {
+  return ts == 0 || find_variant(ts, tile_rows(S, which)) != nullptr;
+}
+
+int launch_level0(const Shape& S, const Tab& tb, const Ws& ws, int prec, bool fused, int ts,
+                  hipStream_t st) {
+  const Variant* v = pick(ts, S.R);
+  if (!v) return -1;
+  v->level0(S, tb, ws, prec, fused ? 1 : 0, st);
+  return 0;
 }
 
 int level0_prepare_attrs(const Shape& S) {
   const size_t by = level0r_lds_bytes(S);
   if (by <= 64 * 1024) return 0;
-  if (S.R <= 32) {
-    switch ((int)cl_ceil_div(S.R, 8)) {
-      case 1: return attrs_level0_8_1(by);
-      case 2: return attrs_level0_8_2(by);
-      case 3: return attrs_level0_8_3(by);
-      case 4: return attrs_level0_8_4(by);
+  bool any = false;
+  for (int t : {8, 16, 24})
+    if (const Variant* v = find_variant(t, S.R)) {
+      if (v->attrs(by)) return -1;
+      any = true;
     }
-  }
-  if (S.R > 128) {
-    switch ((int)cl_ceil_div(S.R, 24)) {
-      case 6: return attrs_level0_24_6(by);
-      case 7: return attrs_level0_24_7(by);
-    }
-    return -1;
-  }
-  switch ((int)cl_ceil_div(S.R, 16)) {
-    case 3: return attrs_level0_16_3(by);
-    case 4: return attrs_level0_16_4(by);
-    case 5: return attrs_level0_16_5(by);
-    case 6: return attrs_level0_16_6(by);
-    case 7: return attrs_level0_16_7(by);
-    case 8: return attrs_level0_16_8(by);
-  }
-  return -1;
+  return any ? 0 : -1;
 }
+
 // mode: 0 first chain level, 1 chain step `level`, 2 border; grid = work items.
-int launch_chain(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level, unsigned grid, hipStream_t st) {
+int launch_chain(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level,
+                 unsigned grid, int ts, hipStream_t st) {
   if (grid == 0) return 0;
-  const int Rl = mode == 2 ? S.ns + S.np : 3 * S.ns + S.np;
+  const int Rl = chain_rows(S, mode == 2 ? 2 : 1);
   const size_t lds = sizeof(double) * (8 * (size_t)Rl + 8);
-  if (Rl <= 32) {
-    switch ((int)cl_ceil_div(Rl, 8)) {
-      case 1: launch_chain_8_1(S, tb, ws, prec, mode, level, grid, lds, st); return 0;
-      case 2: launch_chain_8_2(S, tb, ws, prec, mode, level, grid, lds, st); return 0;
-      case 3: launch_chain_8_3(S, tb, ws, prec, mode, level, grid, lds, st); return 0;
-      case 4: launch_chain_8_4(S, tb, ws, prec, mode, level, grid, lds, st); return 0;
-    }
-  }
-  if (Rl > 128) {
-    switch ((int)cl_ceil_div(Rl, 24)) {
-      case 6: launch_chain_24_6(S, tb, ws, prec, mode, level, grid, lds, st); return 0;
-      case 7: launch_chain_24_7(S, tb, ws, prec, mode, level, grid, lds, st); return 0;
-    }
-    return -1;
-  }
-  switch ((int)cl_ceil_div(Rl, 16)) {
-    case 3: launch_chain_16_3(S, tb, ws, prec, mode, level, grid, lds, st); return 0;
-    case 4: launch_chain_16_4(S, tb, ws, prec, mode, level, grid, lds, st); return 0;
-    case 5: launch_chain_16_5(S, tb, ws, prec, mode, level, grid, lds, st); return 0;
-    case 6: launch_chain_16_6(S, tb, ws, prec, mode, level, grid, lds, st); return 0;
-    case 7: launch_chain_16_7(S, tb, ws, prec, mode, level, grid, lds, st); return 0;
-    case 8: launch_chain_16_8(S, tb, ws, prec, mode, level, grid, lds, st); return 0;
-  }
-  return -1;
+  const Variant* v = pick(ts, Rl);
+  if (!v) return -1;
+  v->chain(S, tb, ws, prec, mode, level, grid, lds, st);
+  return 0;
 }
 }  // namespace cl

@@ -9,6 +9,7 @@ struct HostPlan {
   int L;
   int lvl[64];   // lvl[l] = separators eliminated at level l (1..L)
   int st[64];    // st[l] = work items of cyclic-reduction step l (1..L-1)
+  int ts[3];     // thread grid of the element / chain / border kernels (0 = built-in rule)
 };
 
 // Workgroup size of the per-element kernels: one wave for tiny elements, four otherwise.
@@ -33,10 +34,14 @@ typedef void (*phase_cb)(void* ctx, int phase, int begin, hipStream_t st);
 size_t level0_lds_bytes(const Shape& S, int prec);        // kkt_assemble's LDS blocks
 size_t level0r_lds_bytes(const Shape& S);
 bool level0r_supported(const Shape& S);
-int launch_level0(const Shape& S, const Tab& tb, const Ws& ws, int prec, bool fused, hipStream_t st);
+int launch_level0(const Shape& S, const Tab& tb, const Ws& ws, int prec, bool fused, int ts,
+                  hipStream_t st);
 int level0_prepare_attrs(const Shape& S);
 int launch_chain(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level,
-                 unsigned grid, hipStream_t st);
+                 unsigned grid, int ts, hipStream_t st);
+// Thread-grid options of the element (which = 0), chain (1) and border (2) kernels for a shape.
+int tile_options(const Shape& S, int which, int* ts, int cap);
+bool tile_valid(const Shape& S, int which, int ts);
 int launch_assemble(const Shape& S, const Tab& tb, const Ws& ws, const double* jac,
                     const double* hess, const double* sigma_x, const double* sigma_s,
                     const double* delta_w, const double* r_x, const double* r_s,
