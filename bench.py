@@ -272,9 +272,13 @@ def bench_serving(args):
     lat64 = serving.fifo_latencies(arrivals, service)
     makespan64 = float(np.max(arrivals + lat64) - arrivals[0])
     reqs = [serving.Request(q, float(a), inst) for q, (a, inst) in enumerate(zip(arrivals, insts))]
-    opts = colloc.default_opts(precision=colloc.FP32_IR)
     budget = 8 * 2 ** 30
     torch.cuda.synchronize()
+    # same trace through the batching loop with FP64 factors (the batching effect alone)
+    reqs64 = [serving.Request(q, float(a), inst) for q, (a, inst) in enumerate(zip(arrivals, insts))]
+    res64 = serving.serve(reqs64, o64, budget, steps_per_round=4)
+    lat_b64 = res64.latencies()
+    opts = colloc.default_opts(precision=colloc.FP32_IR)
     res = serving.serve(reqs, opts, budget, steps_per_round=4)
     summ = res.summary()
     lat = res.latencies()
@@ -296,6 +300,10 @@ def bench_serving(args):
                    "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
                    "solved": summ["solved"], "peak_bytes": summ["peak_bytes"],
                    "hbm_budget_bytes": budget,
+                   "batched_fp64": {"solves_per_s": len(insts) / (max(r.t_done for r in reqs64) -
+                                                                  float(arrivals[0])),
+                                    "p50_s": float(np.percentile(lat_b64, 50)),
+                                    "p99_s": float(np.percentile(lat_b64, 99))},
                    "per_instance_fp64": {"solves_per_s": len(insts) / makespan64,
                                          "p50_s": float(np.percentile(lat64, 50)),
                                          "p99_s": float(np.percentile(lat64, 99)),

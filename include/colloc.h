@@ -126,7 +126,8 @@ typedef struct colloc_ipm_info {
   double inf_du, E0, theta_cv, phi;
   double theta_max, theta_min, dphi, alpha_min;
   double Emu, s_d, s_c;
-  int32_t ir_fallbacks, pad_;  /* FP32_IR: iterations that re-factored in FP64 */
+  int32_t ir_fallbacks, pad_;  /* FP32_IR: iterations factored in FP64 (after the first
+                                * fallback an instance stays on FP64 factors) */
 } colloc_ipm_info;
 
 /* Sizes and per-instance offsets of a handle (host arrays owned by the handle). */

@@ -238,15 +238,53 @@ __device__ inline double obj_element(const Shape& S, const Tab& tb, int64_t e, c
 // parameter t % np over the elements t / np, t / np + G, ... (G = threads / np groups); the
 // groups are then added in order, so the result depends only on N, np and the block size.
 // red: nthr() doubles of LDS; out: np doubles of LDS.
+// NS sums, then NM maxima, then NN minima, reduced together over the workgroup: a butterfly
+// over each wave (every lane ends with the same value: each pairwise step is commutative), then
+// the wave results combined in wave order.  red: at least (NS + NM + NN) * waves doubles.
+template <int NS, int NM, int NN>
+__device__ inline void block_reduce_multi(double* v, double* red) {
+  constexpr int NV = NS + NM + NN;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const double o = __shfl_xor(v[k], off);
+      v[k] = k < NS ? v[k] + o : (k < NS + NM ? fmax(v[k], o) : fmin(v[k], o));
+    }
+  }
+  const int nw = (nthr() + 63) / 64;
+  if ((tid() & 63) == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) red[(tid() / 64) * NV + k] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double a = red[k];
+    for (int w = 1; w < nw; ++w) {
+      const double o = red[w * NV + k];
+      a = k < NS ? a + o : (k < NS + NM ? fmax(a, o) : fmin(a, o));
+    }
+    v[k] = a;
+  }
+  __syncthreads();
+}
+
 __device__ inline void theta_sum(const double* part, int64_t e0, int N, int np, double* out,
                                  double* red) {
   const int G = nthr() / np;
   if (G >= 1) {
     const int c = tid() % np, g = tid() / np;
-    double acc = 0.0;
-    if (g < G)
-      for (int i = g; i < N; i += G) acc += part[(e0 + i) * np + c];
-    red[tid()] = acc;
+    double acc = 0.0, acc2 = 0.0;
+    if (g < G) {
+      int i = g;
+      for (; i + G < N; i += 2 * G) {
+        acc += part[(e0 + i) * np + c];
+        acc2 += part[(e0 + i + G) * np + c];
+      }
+      for (; i < N; i += G) acc += part[(e0 + i) * np + c];
+    }
+    red[tid()] = acc + acc2;
     __syncthreads();
     for (int c2 = tid(); c2 < np; c2 += nthr()) {
       double sum = 0.0;

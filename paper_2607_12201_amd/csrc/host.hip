@@ -229,8 +229,10 @@ extern "C" int colloc_create(const colloc_instance_desc* inst, int32_t n_inst, i
   size_t need_b = sizeof(double) * std::max<size_t>(
       (size_t)2 * ns * ns + 2 * (size_t)ns * np + (size_t)np * np + 8,
       (size_t)7 * ns * ns + 3 * (size_t)ns * np + 8);
-  need_b = std::max<size_t>(need_b, sizeof(double) * ((size_t)ns * ns + ns + np + (size_t)np * np + 256));
-  if (need > lds_limit() || need_b > lds_limit() || nr * K > 65536) {
+  need_b = std::max<size_t>(need_b, sizeof(double) * ((size_t)ns * ns + ns + np + (size_t)np * np + 1024));
+  // line-search trials: vectors, rate constants of every candidate, partial sums (no attribute)
+  const size_t need_t = sizeof(double) * (4 * (size_t)S.b + 2 * ns + 2 * np + (size_t)CL_MAX_LS * nr + 768);
+  if (need > lds_limit() || need_b > lds_limit() || need_t > 64 * 1024 || nr * K > 65536) {
     delete p;
     return COLLOC_EUNSUPPORTED;
   }

@@ -184,8 +184,9 @@ __global__ void __launch_bounds__(256) k_ipm_eval(Shape S, Tab tb, IpmState st, 
 
 // Per-instance decisions after evaluation: optimality error, termination, barrier update,
 // inertia-correction schedule.  One workgroup per instance.
-__global__ void k_ipm_decide(Shape S, Tab tb, IpmState st, Ws ws, colloc_ipm_opts o) {
-  __shared__ double red[256];
+__global__ void __launch_bounds__(1024) k_ipm_decide(Shape S, Tab tb, IpmState st, Ws ws,
+                                                     colloc_ipm_opts o) {
+  __shared__ double red[1024];
   __shared__ double sh[16];
   extern __shared__ double jty[];   // np
   const int inst = blockIdx.x;
@@ -231,18 +232,21 @@ __global__ void k_ipm_decide(Shape S, Tab tb, IpmState st, Ws ws, colloc_ipm_opt
       lgt += log(tl) + log(tu);
       if (!isfinite(rx)) m_nf = 1.0;
     }
-    s_obj = block_sum(s_obj, red);
-    s_l1pr = block_sum(s_l1pr, red);
-    s_l1y = block_sum(s_l1y, red);
-    s_l1v = block_sum(s_l1v, red);
-    s_logs = block_sum(s_logs, red);
-    m_infpr = block_max(m_infpr, red);
-    m_infdu = block_max(fmax(m_infdu, du_t), red);
-    m_cmax = block_max(fmax(m_cmax, cmx), red);
-    m_cmin = block_min(fmin(m_cmin, cmn), red);
-    m_nf = block_max(m_nf, red);
-    l1z = block_sum(l1z, red);
-    lgt = block_sum(lgt, red);
+    double v[12] = {s_obj, s_l1pr, s_l1y, s_l1v, s_logs, l1z, lgt,
+                    m_infpr, fmax(m_infdu, du_t), fmax(m_cmax, cmx), m_nf, fmin(m_cmin, cmn)};
+    block_reduce_multi<7, 4, 1>(v, red);
+    s_obj = v[0];
+    s_l1pr = v[1];
+    s_l1y = v[2];
+    s_l1v = v[3];
+    s_logs = v[4];
+    l1z = v[5];
+    lgt = v[6];
+    m_infpr = v[7];
+    m_infdu = v[8];
+    m_cmax = v[9];
+    m_nf = v[10];
+    m_cmin = v[11];
     if (tid() == 0) {
       const int m = N * b;
       double l1all = s_l1y + s_l1v + l1z;
@@ -469,13 +473,15 @@ __global__ void k_ipm_steplen(Shape S, Tab tb, IpmState st, Ws ws, colloc_ipm_op
 // Trial evaluations: thread t of the workgroup evaluates candidate alpha_max 2^-t on the
 // element's rows (constraint violation, objective, slack barrier logs).  LDS: z,dz (b each),
 // zp,dzp (ns), th,dth (np), kap? (recomputed per thread from theta trial: np exps per thread)
-__global__ void k_ipm_trial(Shape S, Tab tb, IpmState st, Ws ws, colloc_ipm_opts o) {
+__global__ void __launch_bounds__(256) k_ipm_trial(Shape S, Tab tb, IpmState st, Ws ws,
+                                                   colloc_ipm_opts o) {
   extern __shared__ double lds[];
   const int64_t e = blockIdx.x;
   const int inst = tb.elem_inst[e], i = tb.elem_loc[e];
   if (block_flag(&ws.flag[inst])) return;
   const int N = tb.inst_N[inst];
   const int ns = S.ns, b = S.b, np = S.np, nr = S.nr, K = S.K;
+  const int nls = o.max_ls;
   const int64_t xo = tb.inst_x[inst];
   const int64_t gi = tb.inst_g[inst] + (int64_t)i * b;
   double* z = lds;
@@ -486,6 +492,8 @@ __global__ void k_ipm_trial(Shape S, Tab tb, IpmState st, Ws ws, colloc_ipm_opts
   double* dth = th + np;
   double* sv = dth + np;
   double* dsv = sv + b;
+  double* kap = dsv + b;              // [nls][nr] rate constants at the trial parameters
+  double* part = kap + nls * nr;      // [3][nthr] per-thread partial sums
   for (int t = tid(); t < b; t += nthr()) {
     z[t] = st.x[xo + (int64_t)i * b + t];
     dz[t] = st.dx[xo + (int64_t)i * b + t];
@@ -501,54 +509,75 @@ __global__ void k_ipm_trial(Shape S, Tab tb, IpmState st, Ws ws, colloc_ipm_opts
     th[t] = st.x[xo + (int64_t)N * b + t];
     dth[t] = st.dx[xo + (int64_t)N * b + t];
   }
+  const double alpha0 = st.info[inst].alpha_pr;
   __syncthreads();
-  const int nls = o.max_ls;
-  const int t = tid();
-  if (t >= nls) return;
-  double alpha = st.info[inst].alpha_pr;
-  for (int q = 0; q < t; ++q) alpha *= 0.5;
+  // candidate c: alpha_max 2^-c
+  for (int t = tid(); t < nls * nr; t += nthr()) {
+    const int c = t / nr, r = t - c * nr;
+    const double alpha = ldexp(alpha0, -c);
+    const int pc = tb.param[inst * nr + r];
+    kap[t] = exp(pc >= 0 ? th[pc] + alpha * dth[pc] : tb.logk[inst * nr + r]);
+  }
+  __syncthreads();
+  // thread (candidate c, group g) covers rows g, g + G, ...; groups are summed in order below
+  const int G = nthr() / nls;
+  const int c = tid() % nls, g = tid() / nls;
   const double h = tb.elem_h[e], tr = o.tau_r;
-  double l1 = 0.0, lg = 0.0;
-  for (int row = 0; row < b; ++row) {
-    int j = row / ns, s = row - j * ns;
-    double gv;
-    if (j == 0) {
-      double zt = z[s] + alpha * dz[s];
-      gv = zt - (i == 0 ? tb.z0[inst * ns + s] : zp[s] + alpha * dzp[s]);
-    } else {
-      double acc = 0.0;
-      for (int jj = 0; jj <= K; ++jj) acc += S.a[jj][j] * (z[jj * ns + s] + alpha * dz[jj * ns + s]);
-      double f = 0.0;
-      int p0 = tb.sp_ptr[inst * (ns + 1) + s], p1 = tb.sp_ptr[inst * (ns + 1) + s + 1];
-      for (int q = p0; q < p1; ++q) {
-        int r = tb.sp_r[q];
-        int q0 = tb.react[(inst * nr + r) * 2], q1 = tb.react[(inst * nr + r) * 2 + 1];
-        int c = tb.param[inst * nr + r];
-        double kk = exp(c >= 0 ? th[c] + alpha * dth[c] : tb.logk[inst * nr + r]);
-        double u0 = q0 >= 0 ? z[j * ns + q0] + alpha * dz[j * ns + q0] : 1.0;
-        double u1 = q1 >= 0 ? z[j * ns + q1] + alpha * dz[j * ns + q1] : 1.0;
-        f += tb.sp_nu[q] * kk * u0 * u1;
+  double l1 = 0.0, lg = 0.0, ob = 0.0;
+  if (g < G) {
+    const double alpha = ldexp(alpha0, -c);
+    const double* kc = kap + c * nr;
+    for (int row = g; row < b; row += G) {
+      const int j = row / ns, s = row - j * ns;
+      double gv;
+      if (j == 0) {
+        const double zt = z[s] + alpha * dz[s];
+        gv = zt - (i == 0 ? tb.z0[inst * ns + s] : zp[s] + alpha * dzp[s]);
+      } else {
+        double acc = 0.0;
+        for (int jj = 0; jj <= K; ++jj) acc += S.a[jj][j] * (z[jj * ns + s] + alpha * dz[jj * ns + s]);
+        double f = 0.0;
+        const int p0 = tb.sp_ptr[inst * (ns + 1) + s], p1 = tb.sp_ptr[inst * (ns + 1) + s + 1];
+        for (int q = p0; q < p1; ++q) {
+          const int r = tb.sp_r[q];
+          const int q0 = tb.react[(inst * nr + r) * 2], q1 = tb.react[(inst * nr + r) * 2 + 1];
+          const double u0 = q0 >= 0 ? z[j * ns + q0] + alpha * dz[j * ns + q0] : 1.0;
+          const double u1 = q1 >= 0 ? z[j * ns + q1] + alpha * dz[j * ns + q1] : 1.0;
+          f += tb.sp_nu[q] * kc[r] * u0 * u1;
+        }
+        gv = acc - h * f;
       }
-      gv = acc - h * f;
+      const double st_ = sv[row] + alpha * dsv[row];
+      l1 += fabs(gv - st_);
+      lg += log(st_ + tr) + log(tr - st_);
     }
-    double st_ = sv[row] + alpha * dsv[row];
-    l1 += fabs(gv - st_);
-    lg += log(st_ + tr) + log(tr - st_);
+    if (g == 0) {   // objective of the element's measurements
+      const int m0 = tb.elem_mptr[e], m1 = tb.elem_mptr[e + 1];
+      for (int m = m0; m < m1; ++m) {
+        const double* w = tb.meas_w + (int64_t)m * (K + 1);
+        const int s = tb.meas_sp[m];
+        double pr = -tb.meas_ys[m];
+        for (int jj = 0; jj <= K; ++jj) pr += w[jj] * (z[jj * ns + s] + alpha * dz[jj * ns + s]);
+        ob += 0.5 * pr * pr;
+      }
+    }
   }
-  // objective of the element's measurements
-  double ob = 0.0;
-  int m0 = tb.elem_mptr[e], m1 = tb.elem_mptr[e + 1];
-  for (int m = m0; m < m1; ++m) {
-    const double* w = tb.meas_w + (int64_t)m * (K + 1);
-    int s = tb.meas_sp[m];
-    double pr = -tb.meas_ys[m];
-    for (int jj = 0; jj <= K; ++jj) pr += w[jj] * (z[jj * ns + s] + alpha * dz[jj * ns + s]);
-    ob += 0.5 * pr * pr;
+  part[tid()] = l1;
+  part[nthr() + tid()] = ob;
+  part[2 * nthr() + tid()] = lg;
+  __syncthreads();
+  if (tid() < nls) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int gg = 0; gg < G; ++gg) {
+      a0 += part[gg * nls + tid()];
+      a1 += part[nthr() + gg * nls + tid()];
+      a2 += part[2 * nthr() + gg * nls + tid()];
+    }
+    double* out = st.tpart + (e * CL_MAX_LS + tid()) * 3;
+    out[0] = a0;
+    out[1] = a1;
+    out[2] = a2;
   }
-  double* out = st.tpart + (e * CL_MAX_LS + t) * 3;
-  out[0] = l1;
-  out[1] = ob;
-  out[2] = lg;
 }
 
 // Acceptance: the candidates' partial sums are reduced over the instance's elements with a
@@ -723,10 +752,17 @@ size_t ipm_eval_lds(const Shape& S, int nt) {
 
 // FP32_IR helpers.  Materialise the theta part of the condensed right-hand side (barrier terms
 // already in st.rhs plus the element partials, fixed order) so the refinement residual sees it.
+// An instance that once needed the FP64 fallback stays on FP64 factors: its later iterations
+// are at least as ill-conditioned (the barrier terms grow as mu falls), so the FP32 attempt
+// would only add work.  It is masked out of the FP32 factor and refinement here.
 __global__ void k_fp32_prep(Shape S, Tab tb, IpmState st, Ws ws) {
   const int inst = blockIdx.x;
   const int skip = ws.flag[inst];
-  if (tid() == 0) ws.runskip[inst] = skip;
+  __syncthreads();
+  if (tid() == 0) {
+    ws.runskip[inst] = skip;
+    if (!skip && st.info[inst].ir_fallbacks > 0) ws.flag[inst] = 1;
+  }
   if (skip) return;
   const int N = tb.inst_N[inst], np = S.np;
   const int64_t e0 = tb.inst_e0[inst], xt = tb.inst_x[inst] + (int64_t)N * S.b;
@@ -764,7 +800,7 @@ int launch_ipm_step(const Shape& S, const Tab& tb, const HostPlan& hp, const Ipm
   const unsigned ne = (unsigned)tb.n_elem;
   if (cb) cb(ctx, COLLOC_PH_EVAL, 1, s);
   hipLaunchKernelGGL(k_ipm_eval, dim3(ne), dim3(nt), ipm_eval_lds(S, nt), s, S, tb, st, ws, o);
-  hipLaunchKernelGGL(k_ipm_decide, dim3(tb.n_inst), dim3(256), sizeof(double) * S.np, s, S, tb, st, ws, o);
+  hipLaunchKernelGGL(k_ipm_decide, dim3(tb.n_inst), dim3(1024), sizeof(double) * S.np, s, S, tb, st, ws, o);
   hipLaunchKernelGGL(k_ipm_prep, dim3(ne), dim3(nt),
                      sizeof(double) * (2 * S.b + S.ns + S.K * S.nr + S.np), s, S, tb, st, ws, o);
   if (cb) cb(ctx, COLLOC_PH_EVAL, 0, s);
@@ -800,7 +836,8 @@ int launch_ipm_step(const Shape& S, const Tab& tb, const HostPlan& hp, const Ipm
   hipLaunchKernelGGL(k_ipm_steplen, dim3(tb.n_inst), dim3(256), 0, s, S, tb, st, ws, o);
   if (cb) cb(ctx, COLLOC_PH_STEP, 0, s);
   if (cb) cb(ctx, COLLOC_PH_LINESEARCH, 1, s);
-  hipLaunchKernelGGL(k_ipm_trial, dim3(ne), dim3(64), sizeof(double) * (4 * S.b + 2 * S.ns + 2 * S.np), s,
+  hipLaunchKernelGGL(k_ipm_trial, dim3(ne), dim3(256),
+                     sizeof(double) * (4 * S.b + 2 * S.ns + 2 * S.np + o.max_ls * S.nr + 3 * 256), s,
                      S, tb, st, ws, o);
   hipLaunchKernelGGL(k_ipm_select, dim3(tb.n_inst), dim3(256), 0, s, S, tb, st, ws, o);
   hipLaunchKernelGGL(k_ipm_update, dim3(ne), dim3(nt), 0, s, S, tb, st, ws, o);

@@ -614,7 +614,7 @@ __global__ void k_crf_step(Shape S, Tab tb, Ws ws, const double* __restrict__ rh
 // Border solve: separator 0, theta, back to separator 0.
 // LDS: Lm (ns^2) r (ns) rt (np) Sm (np^2) red (nthr * np)
 template <typename T>
-__global__ void k_border_solve(Shape S, Tab tb, Ws ws, const double* __restrict__ rhs,
+__global__ void __launch_bounds__(1024) k_border_solve(Shape S, Tab tb, Ws ws, const double* __restrict__ rhs,
                                const double* __restrict__ rthp, double* __restrict__ dx) {
   extern __shared__ double lds[];
   const int inst = blockIdx.x;
@@ -644,13 +644,26 @@ __global__ void k_border_solve(Shape S, Tab tb, Ws ws, const double* __restrict_
   // i = t / np, t / np + G, ... (G = threads / np groups), then a fixed-order group sum
   const int G = max(1, nthr() / np);
   const int c0 = tid() % np, g0 = tid() / np;
-  double acc = 0.0;
-  if (g0 < G)
-    for (int i = g0; i < N; i += G) {
+  double acc = 0.0, acc2 = 0.0;
+  if (g0 < G) {
+    int i = g0;
+    for (; i + G < N; i += 2 * G) {     // two independent chains of loads in flight
+      acc += ws.cB[(e0 + i) * np + c0];
+      acc2 += ws.cB[(e0 + i + G) * np + c0];
+      if (i > 0) acc += ws.cBsep[(e0 + i) * np + c0];
+      acc2 += ws.cBsep[(e0 + i + G) * np + c0];
+      if (rthp) {
+        acc -= rthp[(e0 + i) * np + c0];
+        acc2 -= rthp[(e0 + i + G) * np + c0];
+      }
+    }
+    for (; i < N; i += G) {
       acc += ws.cB[(e0 + i) * np + c0];
       if (i > 0) acc += ws.cBsep[(e0 + i) * np + c0];
       if (rthp) acc -= rthp[(e0 + i) * np + c0];
     }
+    acc += acc2;
+  }
   if (np > nthr()) {  // fall back: loop parameters per thread
     acc = 0.0;
   }
@@ -920,8 +933,8 @@ static int solve_t(const Shape& S, const Tab& tb, const HostPlan& hp, const Ws& 
   for (int l = 1; l < tb.L; ++l)
     if (hp.st[l] > 0)
       hipLaunchKernelGGL(k_crf_step<T>, dim3(hp.st[l]), dim3(snt), clds, st, S, tb, ws, rhs, l);
-  size_t blds = sizeof(double) * (S.ns * S.ns + S.ns + S.np + S.np * S.np + 256);
-  hipLaunchKernelGGL(k_border_solve<T>, dim3(tb.n_inst), dim3(256), blds, st, S, tb, ws, rhs,
+  size_t blds = sizeof(double) * (S.ns * S.ns + S.ns + S.np + S.np * S.np + 1024);
+  hipLaunchKernelGGL(k_border_solve<T>, dim3(tb.n_inst), dim3(1024), blds, st, S, tb, ws, rhs,
                      rthp, dx);
   for (int l = tb.L; l >= 1; --l) {
     int n = hp.lvl[l];
