@@ -24,6 +24,23 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 (vector and matrix), 256 CU x 2.4 GHz x 128 flop/clk
 PEAK_HBM_GBS = 8000.0
 
+# HBM bytes per launch of the element kernel at this workload, from FETCH_SIZE and WRITE_SIZE
+# counter passes scaled by a 256 MiB calibration copy (profiles/level0_net20_n1000_traffic.md).
+# Valid only for the kernel source they were taken on (fingerprint) and its 24 x 24 grid.
+L0_TRAFFIC = {"sha": "d3ed95570437730d", "tile": 24, "bytes": 90484262.0}
+L0_SOURCES = ["level0_impl.h", "regchol.h", "elem.h", "common.h", "kernels.h", "k_level0_x.hip"]
+
+
+def level0_traffic(tile):
+    import hashlib
+    h = hashlib.sha256()
+    for n in L0_SOURCES:
+        with open(os.path.join(ROOT, "paper_2607_12201_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest()[:16] == L0_TRAFFIC["sha"] and tile == L0_TRAFFIC["tile"]:
+        return L0_TRAFFIC["bytes"]
+    return None
+
 
 def level0_flops(ns, np_, K):
     """Algorithmic flops of one element's dense condensed block factorization:
@@ -68,7 +85,7 @@ def cpu_baseline(inst, K, seconds=20.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=60)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -103,32 +120,44 @@ def main():
     x0 = workloads.initial_point(inst, K)
     P = colloc.Problem(inst, K)
     opts = colloc.default_opts()
-    ws, state = P.workspace(), P.state()
-    x0d = torch.tensor(x0, dtype=torch.float64, device="cuda")
-    P.ipm_init(x0d, state, ws, opts)
-    for _ in range(args.warmup):
-        P.ipm_step(state, ws, opts)
-    torch.cuda.synchronize()
-    if args.calib_copy_mib:
-        n = args.calib_copy_mib * 2 ** 20 // 8
-        src = torch.ones(n, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-    P.ipm_init(x0d, state, ws, opts)          # timed region starts from the same point
-    torch.cuda.synchronize()
-    it0 = int(P.info(state)[0]["iter"])
-    P.timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        P.ipm_step(state, ws, opts)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ph_ms, ph_n = P.timing_read()
-    P.timing(False)
-    info = P.info(state)[0]
+    from paper_2607_12201_amd import autotune
+    tiles = autotune.tune(P)           # thread grids per kernel (device-timed, cached per shape)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        ws, state = P.workspace(), P.state()
+        x0d = torch.tensor(x0, dtype=torch.float64, device="cuda")
+        # one interior-point step captured as a HIP graph, replayed once per step
+        graph = P.graph_create(state, ws, opts, steps=1)
+        P.ipm_init(x0d, state, ws, opts)
+        for _ in range(args.warmup):
+            P.graph_launch(graph)
+        side.synchronize()
+        if args.calib_copy_mib:
+            n = args.calib_copy_mib * 2 ** 20 // 8
+            src = torch.ones(n, dtype=torch.float64, device="cuda")
+            dst = torch.empty_like(src)
+            dst.copy_(src)
+            side.synchronize()
+            del src, dst
+        P.ipm_init(x0d, state, ws, opts)          # timed region starts from the same point
+        side.synchronize()
+        it0 = int(P.info(state)[0]["iter"])
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            P.graph_launch(graph)
+        side.synchronize()
+        dt = time.perf_counter() - t0
+        info = P.info(state)[0]
+        # the same steps again, eager, with the library's per-phase HIP events (the events are
+        # recorded on this stream around each phase; a graph replay records none)
+        P.ipm_init(x0d, state, ws, opts)
+        P.timing(True)
+        for _ in range(args.steps):
+            P.ipm_step(state, ws, opts)
+        side.synchronize()
+        ph_ms, ph_n = P.timing_read()
+        P.timing(False)
+        P.graph_destroy(graph)
     newton = int(info["iter"]) - it0
     value = newton / dt
     ms_per_step = 1e3 * dt / args.steps
@@ -151,12 +180,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": "random mass-action network, 20 species, 40 reactions, 40 params, "
                                "N=1000 Radau elements K=3, FP64 plain IPM, one instance",
-                   "newton_steps": newton, "ipm_step_calls": args.steps,
+                   "newton_steps": newton, "ipm_step_calls": args.steps, "graph_replay": True,
                    "final_status": int(info["status"]), "iter_end": int(info["iter"]),
+                   "tiles": {k: tiles[k] for k in colloc.Problem.TILE_KERNELS},
                    "phase_ms_per_call": {k: ph_ms[k] / max(1, ph_n[k]) for k in ph_ms}},
         "roofline": {"bound": "alu", "kernel": "k_level0 (fused assembly + element condensation)",
                      "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": level0_traffic(tiles["level0"]),
                      "avg_launch_ms": l0_ms,
                      "algorithmic_flops_per_launch": flops,
                      "algorithmic_bytes_per_launch": level0_bytes(P.ns, P.np_, K) * E},

@@ -1,5 +1,5 @@
 // Dispatch of the register-resident elimination kernels: thread grid TS x TS (TS in 8, 16,
-// 24) with NB = ceil(rows / TS) register blocks per side.  The built-in rule picks the smallest
+// 20, 24) with NB = ceil(rows / TS) register blocks per side.  The built-in rule picks the smallest
 // grid whose block count stays within the instantiated range; a handle may override the grid
 // per kernel (tuning).
 #include "kernels.h"
@@ -59,6 +59,18 @@ void launch_chain_24_6(const Shape&, const Tab&, const Ws&, int, int, int, unsig
 void launch_level0_24_7(const Shape&, const Tab&, const Ws&, int, int, hipStream_t);
 int attrs_level0_24_7(size_t);
 void launch_chain_24_7(const Shape&, const Tab&, const Ws&, int, int, int, unsigned, size_t, hipStream_t);
+void launch_level0_20_5(const Shape&, const Tab&, const Ws&, int, int, hipStream_t);
+int attrs_level0_20_5(size_t);
+void launch_chain_20_5(const Shape&, const Tab&, const Ws&, int, int, int, unsigned, size_t, hipStream_t);
+void launch_level0_20_6(const Shape&, const Tab&, const Ws&, int, int, hipStream_t);
+int attrs_level0_20_6(size_t);
+void launch_chain_20_6(const Shape&, const Tab&, const Ws&, int, int, int, unsigned, size_t, hipStream_t);
+void launch_level0_20_7(const Shape&, const Tab&, const Ws&, int, int, hipStream_t);
+int attrs_level0_20_7(size_t);
+void launch_chain_20_7(const Shape&, const Tab&, const Ws&, int, int, int, unsigned, size_t, hipStream_t);
+void launch_level0_20_8(const Shape&, const Tab&, const Ws&, int, int, hipStream_t);
+int attrs_level0_20_8(size_t);
+void launch_chain_20_8(const Shape&, const Tab&, const Ws&, int, int, int, unsigned, size_t, hipStream_t);
 
 namespace {
 struct Variant {
@@ -85,7 +97,11 @@ const Variant kVariants[] = {
     {24, 4, launch_level0_24_4, attrs_level0_24_4, launch_chain_24_4},
     {24, 5, launch_level0_24_5, attrs_level0_24_5, launch_chain_24_5},
     {24, 6, launch_level0_24_6, attrs_level0_24_6, launch_chain_24_6},
-    {24, 7, launch_level0_24_7, attrs_level0_24_7, launch_chain_24_7}
+    {24, 7, launch_level0_24_7, attrs_level0_24_7, launch_chain_24_7},
+    {20, 5, launch_level0_20_5, attrs_level0_20_5, launch_chain_20_5},
+    {20, 6, launch_level0_20_6, attrs_level0_20_6, launch_chain_20_6},
+    {20, 7, launch_level0_20_7, attrs_level0_20_7, launch_chain_20_7},
+    {20, 8, launch_level0_20_8, attrs_level0_20_8, launch_chain_20_8}
 };
 
 const Variant* find_variant(int ts, int rows) {
@@ -95,8 +111,9 @@ const Variant* find_variant(int ts, int rows) {
   return nullptr;
 }
 
-// Built-in rule: 8 x 8 up to 32 rows, 16 x 16 up to 128, 24 x 24 above.
-int default_ts(int rows) { return rows <= 32 ? 8 : (rows <= 128 ? 16 : 24); }
+// Built-in rule: 8 x 8 up to 32 rows, 16 x 16 up to 128, 20 x 20 up to 160 (seven waves and
+// at most 128 registers, so two elements share a compute unit), 24 x 24 above.
+int default_ts(int rows) { return rows <= 32 ? 8 : (rows <= 128 ? 16 : (rows <= 160 ? 20 : 24)); }
 
 const Variant* pick(int ts, int rows) {
   return find_variant(ts > 0 ? ts : default_ts(rows), rows);
@@ -121,7 +138,7 @@ int tile_rows(const Shape& S, int which) { return which == 0 ? S.R : chain_rows(
 int tile_options(const Shape& S, int which, int* ts, int cap) {
   const int rows = tile_rows(S, which);
   int n = 0;
-  for (int t : {8, 16, 24})
+  for (int t : {8, 16, 20, 24})
     if (find_variant(t, rows)) {
       if (n < cap) ts[n] = t;
       ++n;
@@ -145,7 +162,7 @@ int level0_prepare_attrs(const Shape& S) {
   const size_t by = level0r_lds_bytes(S);
   if (by <= 64 * 1024) return 0;
   bool any = false;
-  for (int t : {8, 16, 24})
+  for (int t : {8, 16, 20, 24})
     if (const Variant* v = find_variant(t, S.R)) {
       if (v->attrs(by)) return -1;
       any = true;
