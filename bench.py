@@ -24,22 +24,25 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 (vector and matrix), 256 CU x 2.4 GHz x 128 flop/clk
 PEAK_HBM_GBS = 8000.0
 
-# HBM bytes per launch of the element kernel at this workload, from FETCH_SIZE and WRITE_SIZE
-# counter passes scaled by a 256 MiB calibration copy (profiles/level0_net20_n1000_traffic.md).
-# Valid only for the kernel source they were taken on (fingerprint) and its 24 x 24 grid.
-L0_TRAFFIC = {"sha": "d3ed95570437730d", "tile": 24, "bytes": 90484262.0}
-L0_SOURCES = ["level0_impl.h", "regchol.h", "elem.h", "common.h", "kernels.h", "k_level0_x.hip"]
+# HBM bytes per launch of the element kernel at this workload, per thread grid, from FETCH_SIZE and
+# WRITE_SIZE counter passes scaled by a 256 MiB calibration copy (profiles/level0_*_traffic.md).
+# An entry holds only for the kernel source it was taken on (fingerprint of the shared headers
+# and the translation unit that instantiates that grid).
+L0_COMMON = ["level0_impl.h", "regchol.h", "elem.h", "common.h", "kernels.h"]
+L0_TRAFFIC = {24: {"tu": "k_level0_x.hip", "sha": "d3ed95570437730d", "bytes": 90484262.0},
+              20: {"tu": "k_level0_u.hip", "sha": "c9def52039f72486", "bytes": 90330000.0}}
 
 
 def level0_traffic(tile):
     import hashlib
+    ent = L0_TRAFFIC.get(tile)
+    if ent is None:
+        return None
     h = hashlib.sha256()
-    for n in L0_SOURCES:
+    for n in L0_COMMON + [ent["tu"]]:
         with open(os.path.join(ROOT, "paper_2607_12201_amd", "csrc", n), "rb") as f:
             h.update(f.read())
-    if h.hexdigest()[:16] == L0_TRAFFIC["sha"] and tile == L0_TRAFFIC["tile"]:
-        return L0_TRAFFIC["bytes"]
-    return None
+    return ent["bytes"] if h.hexdigest()[:16] == ent["sha"] else None
 
 
 def level0_flops(ns, np_, K):

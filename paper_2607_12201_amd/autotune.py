@@ -74,28 +74,39 @@ def tune(P, precision=colloc.FP64, reps=4, cache_path=DEFAULT_CACHE, force=False
             P.tile_set(k, cache[key][k])
         return cache[key]
     x0, opts, ws, st = _ipm_setup(P, precision, torch)
+
+    def measure(which, ts):
+        P.tile_set(which, ts)
+        P.ipm_init(x0, st, ws, opts)
+        for _ in range(2):               # first iterations, code load
+            P.ipm_step(st, ws, opts)
+        torch.cuda.synchronize()
+        P.timing(True)
+        for _ in range(reps):
+            P.ipm_step(st, ws, opts)
+        torch.cuda.synchronize()
+        ms, n = P.timing_read()
+        P.timing(False)
+        ph = PHASE_OF[which]
+        return ms[ph] / max(1, n[ph])
+
+    # bring the device to its working clocks before anything is compared
+    P.ipm_init(x0, st, ws, opts)
+    for _ in range(3 * reps):
+        P.ipm_step(st, ws, opts)
+    torch.cuda.synchronize()
     result = {"ms": {}}
     for which in colloc.Problem.TILE_KERNELS:
-        best, best_ms = 0, float("inf")
-        for ts in P.tile_options(which):
-            P.tile_set(which, ts)
-            P.ipm_init(x0, st, ws, opts)
-            for _ in range(2):               # warm-up (code load, first iterations)
-                P.ipm_step(st, ws, opts)
-            torch.cuda.synchronize()
-            P.timing(True)
-            for _ in range(reps):
-                P.ipm_step(st, ws, opts)
-            torch.cuda.synchronize()
-            ms, n = P.timing_read()
-            P.timing(False)
-            ph = PHASE_OF[which]
-            t = ms[ph] / max(1, n[ph])
-            result["ms"][f"{which}:{ts}"] = t
+        cands = P.tile_options(which)
+        best_of = {ts: float("inf") for ts in cands}
+        for rnd in range(3):             # interleaved rounds, best time per candidate
+            for ts in (cands if rnd % 2 == 0 else cands[::-1]):
+                best_of[ts] = min(best_of[ts], measure(which, ts))
+        best = min(cands, key=lambda t: best_of[t])
+        for ts in cands:
+            result["ms"][f"{which}:{ts}"] = best_of[ts]
             if verbose:
-                print(f"autotune {key} {which} ts={ts}: {t:.4f} ms per launch", flush=True)
-            if t < best_ms:
-                best, best_ms = ts, t
+                print(f"autotune {key} {which} ts={ts}: {best_of[ts]:.4f} ms per phase", flush=True)
         P.tile_set(which, best)
         result[which] = best
     if cache_path:
