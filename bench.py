@@ -239,6 +239,23 @@ def bench_multistart(args):
         info = P.info(state)
         P.graph_destroy(g)
     newton = int(info["iter"].astype(np.int64).sum() - it0)
+    # the same batch with FP64 factors (batching alone, no mixed precision)
+    o64b = colloc.default_opts()
+    autotune.tune(P, precision=colloc.FP64)
+    with torch.cuda.stream(side):
+        ws64, st64 = P.workspace(colloc.FP64), P.state()
+        P.ipm_init(x0, st64, ws64, o64b)
+        g64 = P.graph_create(st64, ws64, o64b, steps=1)
+        _run_steps(P, st64, ws64, o64b, args.warmup, g64)
+        P.ipm_init(x0, st64, ws64, o64b)
+        side.synchronize()
+        i64 = P.info(st64)["iter"].astype(np.int64).sum()
+        t0 = time.perf_counter()
+        _run_steps(P, st64, ws64, o64b, args.steps, g64)
+        side.synchronize()
+        dt64 = time.perf_counter() - t0
+        newton64 = int(P.info(st64)["iter"].astype(np.int64).sum() - i64)
+        P.graph_destroy(g64)
     # plain FP64 per-instance path on a sample of the same instances
     sample = insts[:: max(1, len(insts) // 8)][:8]
     o64 = colloc.default_opts()
@@ -273,6 +290,7 @@ def bench_multistart(args):
                    "solved": int(np.sum(info["status"] == colloc.SOLVED)),
                    "ir_fallbacks": int(info["ir_fallbacks"].sum()), "tiles": {
                        k: tiles[k] for k in colloc.Problem.TILE_KERNELS},
+                   "batched_fp64_newton_steps_per_s": newton64 / dt64,
                    "per_instance_fp64_newton_steps_per_s": tot_it / tot_t,
                    "per_instance_sample": len(sample)},
     }

@@ -272,8 +272,10 @@ int colloc_timing_read(colloc_problem* p, double* ms, int64_t* launches, int32_t
  * registers, ceil(rows / TS) blocks per side.  colloc_tile_options writes the usable TS for this
  * handle's shape into ts[0..cap) and returns their count (negative on bad arguments);
  * colloc_tile_set selects one (0 = built-in rule) and returns COLLOC_EINVAL for a TS the shape
- * cannot use; colloc_tile_get returns the current choice (0 = built-in rule).  The choice changes
- * which thread computes an entry, not the arithmetic: results are identical for every choice. */
+ * cannot use; colloc_tile_get returns the current choice (0 = built-in rule).  For the chain
+ * kernel TS = 1 selects its blocked LDS variant (FP64 factors only), whose
+ * arithmetic differs from the register-resident one in rounding only.  Among the TS x TS grids the
+ * choice changes which thread computes an entry, not the arithmetic: results are identical. */
 int colloc_tile_options(const colloc_problem* p, int32_t which, int32_t* ts, int32_t cap);
 int colloc_tile_set(colloc_problem* p, int32_t which, int32_t ts);
 int colloc_tile_get(const colloc_problem* p, int32_t which);

@@ -48,68 +48,250 @@ __device__ inline double sep_G(const Shape& S, const Ws& ws, const SepSrc& c, in
   return v;
 }
 
+// One separator of a chain level (or the border item): which instance and separator, whether it
+// is eliminated at this level, and where its current blocks come from.
+struct ChainItem {
+  bool valid, elim;
+  int inst, s, N;
+  int64_t e0, es;
+  SepSrc src;
+  int64_t eL, eR;             // coupling sources (E1 rows or stored Schur couplings), -1 = none
+  bool eL_is_e1, eR_is_e1;
+};
+
+__device__ inline ChainItem chain_item(const Tab& tb, int mode, int level) {
+  ChainItem c;
+  c.valid = true;
+  c.elim = true;
+  if (mode == CH_FIRST) {
+    const int it = tb.cr_ptr[0] + blockIdx.x;
+    if (it >= tb.cr_ptr[1]) {
+      c.valid = false;
+      return c;
+    }
+    c.inst = tb.cr_inst[it];
+    c.s = tb.cr_j[it];
+  } else if (mode == CH_STEP) {
+    const int it = tb.st_ptr[level - 1] + blockIdx.x;
+    if (it >= tb.st_ptr[level]) {
+      c.valid = false;
+      return c;
+    }
+    c.inst = tb.st_inst[it];
+    c.s = tb.st_s[it];
+    c.elim = ((c.s >> level) & 1) != 0;
+  } else {
+    c.inst = blockIdx.x;
+    c.s = 0;
+  }
+  const int s = c.s;
+  c.N = tb.inst_N[c.inst];
+  const int N = c.N;
+  c.e0 = tb.inst_e0[c.inst];
+  c.es = c.e0 + s;
+  c.src.es = c.es;
+  c.src.j1 = -1;
+  c.src.j2 = -1;
+  c.eL = c.eR = -1;
+  c.eL_is_e1 = c.eR_is_e1 = false;
+  if (mode == CH_FIRST) {
+    c.src.add_next = s + 1 < N;
+    c.eL = c.es;
+    c.eL_is_e1 = true;
+    if (s + 1 < N) {
+      c.eR = c.es + 1;
+      c.eR_is_e1 = true;
+    }
+  } else if (mode == CH_STEP) {
+    const int half = 1 << (level - 1);
+    c.src.add_next = (level == 1) && (s + 1 < N);
+    if (s > 0) c.src.j1 = c.e0 + s - half;
+    if (s + half < N) c.src.j2 = c.e0 + s + half;
+    if (c.elim) {
+      c.eL = c.src.j1;
+      if (s + 2 * half < N) c.eR = c.src.j2;
+    }
+  } else {
+    const int L = tb.L;
+    c.src.add_next = (L <= 1) && (N > 1);
+    const int jl = L >= 1 ? (1 << (L - 1)) : N;
+    if (jl < N) c.src.j2 = c.e0 + jl;
+  }
+  return c;
+}
+
+// A separator that survives this level: add the contributions, keep the block for later.
+template <typename T>
+__device__ inline void chain_survivor(const Shape& S, const Ws& ws, const SepSrc& src) {
+  const int ns = S.ns, np = S.np;
+  T* dss = (T*)ws.dss + src.es * ns * ns;
+  T* bsv = (T*)ws.bs + src.es * ns * np;
+  for (int t = tid(); t < ns * ns; t += nthr()) dss[t] = (T)sep_T<T>(S, ws, src, t / ns, t % ns);
+  for (int t = tid(); t < ns * np; t += nthr()) bsv[t] = (T)sep_G<T>(S, ws, src, t / np, t % np);
+}
+
+// Off-diagonal row a of a separator's local matrix in pivot column q: left neighbour rows
+// (E_L[q][a] = K(s_q, l_a)), right neighbour rows (E_R[a][q] = K(r_a, s_q)), parameter rows.
+template <typename T>
+__device__ inline double chain_offdiag(const Shape& S, const Ws& ws, const ChainItem& c, int a, int q) {
+  const int ns = S.ns;
+  if (a < ns) {
+    if (c.eL < 0) return 0.0;
+    return c.eL_is_e1 ? ld<T>(ws.e1, c.eL * ns * ns + q * ns + a) : ld<T>(ws.cE, c.eL * ns * ns + q * ns + a);
+  }
+  if (a < 2 * ns) {
+    const int b = a - ns;
+    if (c.eR < 0) return 0.0;
+    return c.eR_is_e1 ? ld<T>(ws.e1, c.eR * ns * ns + b * ns + q) : ld<T>(ws.cE, c.eR * ns * ns + b * ns + q);
+  }
+  return sep_G<T>(S, ws, c.src, q, a - 2 * ns);
+}
+
+// Elimination of one separator by blocks, in LDS (FP64): Cholesky of the separator block T_s
+// by one wave, then U = L_s^{-1} [E_L E_R G]^T row by row (one thread per row), then the Schur
+// contributions -U^T U as register-blocked dot products over the ns pivot columns.  It needs few
+// workgroup barriers but has long dependent chains in its serial parts; the autotuner times it
+// against the register-resident grids (at 20 species it is the slower one).  Outputs are those
+// of k_chain (lsep, ul, ur, ub and the contributions cTl, cE, cTr, cGl, cGr, thcr).
+// LDS: Tm (ns x ns) | X (Rt x ns, Rt = 2 ns + np) | rd (ns) | misc (8)
+template <typename T>
+__global__ void __launch_bounds__(256) k_chain_blk(Shape S, Tab tb, Ws ws, int mode, int level) {
+  static_assert(sizeof(T) == 8, "FP64 only");
+  extern __shared__ double lds[];
+  const ChainItem c = chain_item(tb, mode, level);
+  if (!c.valid) return;
+  if (block_flag(&ws.flag[c.inst])) return;
+  if (!c.elim) {
+    chain_survivor<double>(S, ws, c.src);
+    return;
+  }
+  const int ns = S.ns, np = S.np, Rt = 2 * ns + np;
+  double* Tm = lds;
+  double* X = Tm + ns * ns;
+  double* rd = X + Rt * ns;
+  double* misc = rd + ns;
+  for (int t = tid(); t < ns * ns; t += nthr()) {
+    const int a = t / ns, b = t - a * ns;
+    Tm[t] = b <= a ? sep_T<double>(S, ws, c.src, a, b) : 0.0;
+  }
+  for (int t = tid(); t < Rt * ns; t += nthr()) {
+    const int a = t / ns, q = t - a * ns;
+    X[t] = chain_offdiag<double>(S, ws, c, a, q);
+  }
+  __syncthreads();
+  if (tid() < 64) {   // Cholesky of T_s: lane i keeps row i
+    const int lane = tid();
+    for (int k = 0; k < ns; ++k) {
+      if (lane == 0) {
+        const double piv = Tm[k * ns + k];
+        const bool good = piv > 0.0 && isfinite(piv);
+        const double sq = good ? sqrt(piv) : 1.0;
+        Tm[k * ns + k] = sq;
+        misc[0] = good ? 1.0 : 0.0;
+        misc[1] = 1.0 / sq;
+      }
+      __builtin_amdgcn_wave_barrier();
+      if (misc[0] == 0.0) break;
+      const double inv = misc[1];
+      if (lane > k && lane < ns) Tm[lane * ns + k] *= inv;
+      __builtin_amdgcn_wave_barrier();
+      if (lane > k && lane < ns) {
+        const double lik = Tm[lane * ns + k];
+        for (int j = k + 1; j <= lane; ++j) Tm[lane * ns + j] -= lik * Tm[j * ns + k];
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+    if (lane < ns) rd[lane] = 1.0 / Tm[lane * ns + lane];
+  }
+  __syncthreads();
+  if (misc[0] == 0.0) {
+    if (tid() == 0) atomicOr(&ws.flag[c.inst], 1);
+    return;
+  }
+  for (int a = tid(); a < Rt; a += nthr()) {   // U row a = L_s^{-1} x_a
+    double* xa = X + a * ns;
+    for (int j = 0; j < ns; ++j) {
+      double v = xa[j];
+      for (int k = 0; k < j; ++k) v -= xa[k] * Tm[j * ns + k];
+      xa[j] = v * rd[j];
+    }
+  }
+  __syncthreads();
+  const int64_t es = c.es;
+  double* lsep = (double*)ws.lsep + es * ns * ns;
+  double* ul = (double*)ws.ul + es * ns * ns;
+  double* ur = (double*)ws.ur + es * ns * ns;
+  double* ub = (double*)ws.ub + es * ns * np;
+  for (int t = tid(); t < ns * ns; t += nthr()) {
+    const int a = t / ns, q = t - a * ns;
+    if (q <= a) lsep[t] = Tm[t];
+  }
+  for (int t = tid(); t < Rt * ns; t += nthr()) {
+    const int a = t / ns, q = t - a * ns;
+    const double v = X[t];
+    if (a < ns) ul[q * ns + a] = v;
+    else if (a < 2 * ns) ur[q * ns + (a - ns)] = v;
+    else ub[q * np + (a - 2 * ns)] = v;
+  }
+  // Schur contributions -U_a^T U_b (b <= a), 2 x 2 row blocks per thread
+  double* cTl = (double*)ws.cTl + es * ns * ns;
+  double* cTr = (double*)ws.cTr + es * ns * ns;
+  double* cE = (double*)ws.cE + es * ns * ns;
+  double* cGl = (double*)ws.cGl + es * ns * np;
+  double* cGr = (double*)ws.cGr + es * ns * np;
+  double* th = ws.thcr + es * np * np;
+  const int nb2 = (Rt + 1) / 2, nblk = nb2 * (nb2 + 1) / 2;
+  for (int t = tid(); t < nblk; t += nthr()) {
+    int bi = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+    while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
+    while (bi * (bi + 1) / 2 > t) --bi;
+    const int bj = t - bi * (bi + 1) / 2;
+    const int a0 = 2 * bi, b0 = 2 * bj;
+    const double* x0 = X + a0 * ns;
+    const double* x1 = X + (a0 + 1 < Rt ? a0 + 1 : a0) * ns;
+    const double* y0 = X + b0 * ns;
+    const double* y1 = X + (b0 + 1 < Rt ? b0 + 1 : b0) * ns;
+    double s00 = 0.0, s01 = 0.0, s10 = 0.0, s11 = 0.0;
+    for (int q = 0; q < ns; ++q) {
+      const double u0 = x0[q], u1 = x1[q], w0 = y0[q], w1 = y1[q];
+      s00 += u0 * w0;
+      s01 += u0 * w1;
+      s10 += u1 * w0;
+      s11 += u1 * w1;
+    }
+    const double vals[4] = {s00, s01, s10, s11};
+    for (int k = 0; k < 4; ++k) {
+      const int a = a0 + (k >> 1), b = b0 + (k & 1);
+      if (a >= Rt || b >= Rt || b > a) continue;
+      const double v = -vals[k];
+      const int ag = a < ns ? 1 : (a < 2 * ns ? 2 : 3);
+      const int bg = b < ns ? 1 : (b < 2 * ns ? 2 : 3);
+      const int aa = a - (ag - 1) * ns, bb = b - (bg - 1) * ns;
+      if (ag == 1) cTl[aa * ns + bb] = v;
+      else if (ag == 2 && bg == 1) cE[aa * ns + bb] = v;
+      else if (ag == 2) cTr[aa * ns + bb] = v;
+      else if (bg == 1) cGl[bb * np + (a - 2 * ns)] = v;
+      else if (bg == 2) cGr[bb * np + (a - 2 * ns)] = v;
+      else th[(a - 2 * ns) * np + (b - 2 * ns)] = v;
+    }
+  }
+}
+
 template <typename T, int TS, int NB>
 __global__ void __launch_bounds__(TS* TS) k_chain(Shape S, Tab tb, Ws ws, int mode, int level) {
   extern __shared__ double lds[];
   constexpr int NBLK = NB * (NB + 1) / 2;
   const int ns = S.ns, np = S.np;
-  int inst, s;
-  bool elim = true;
-  if (mode == CH_FIRST) {
-    const int it = tb.cr_ptr[0] + blockIdx.x;
-    if (it >= tb.cr_ptr[1]) return;
-    inst = tb.cr_inst[it];
-    s = tb.cr_j[it];
-  } else if (mode == CH_STEP) {
-    const int it = tb.st_ptr[level - 1] + blockIdx.x;
-    if (it >= tb.st_ptr[level]) return;
-    inst = tb.st_inst[it];
-    s = tb.st_s[it];
-    elim = ((s >> level) & 1) != 0;
-  } else {
-    inst = blockIdx.x;
-    s = 0;
-  }
+  const ChainItem ci = chain_item(tb, mode, level);
+  if (!ci.valid) return;
+  const int inst = ci.inst;
   if (block_flag(&ws.flag[inst])) return;
-  const int N = tb.inst_N[inst];
-  const int64_t e0 = tb.inst_e0[inst], es = e0 + s;
-
-  // sources of the separator's current block
-  SepSrc src;
-  src.es = es;
-  src.j1 = -1;
-  src.j2 = -1;
-  int64_t eL = -1, eR = -1;     // coupling sources (E1 rows or stored Schur couplings)
-  bool eL_is_e1 = false, eR_is_e1 = false;
-  if (mode == CH_FIRST) {
-    src.add_next = s + 1 < N;
-    eL = es;
-    eL_is_e1 = true;
-    if (s + 1 < N) {
-      eR = es + 1;
-      eR_is_e1 = true;
-    }
-  } else if (mode == CH_STEP) {
-    const int half = 1 << (level - 1);
-    src.add_next = (level == 1) && (s + 1 < N);
-    if (s > 0) src.j1 = e0 + s - half;
-    if (s + half < N) src.j2 = e0 + s + half;
-    if (elim) {
-      eL = src.j1;
-      if (s + 2 * half < N) eR = src.j2;
-    }
-  } else {
-    const int L = tb.L;
-    src.add_next = (L <= 1) && (N > 1);
-    const int jl = L >= 1 ? (1 << (L - 1)) : N;
-    if (jl < N) src.j2 = e0 + jl;
-  }
-
-  if (!elim) {   // survivor: add the contributions and keep the block for a later level
-    T* dss = (T*)ws.dss + es * ns * ns;
-    T* bsv = (T*)ws.bs + es * ns * np;
-    for (int t = tid(); t < ns * ns; t += nthr()) dss[t] = (T)sep_T<T>(S, ws, src, t / ns, t % ns);
-    for (int t = tid(); t < ns * np; t += nthr()) bsv[t] = (T)sep_G<T>(S, ws, src, t / np, t % np);
+  const int64_t es = ci.es;
+  const SepSrc& src = ci.src;
+  const int64_t eL = ci.eL, eR = ci.eR;
+  const bool eL_is_e1 = ci.eL_is_e1, eR_is_e1 = ci.eR_is_e1;
+  if (!ci.elim) {
+    chain_survivor<T>(S, ws, src);
     return;
   }
 

@@ -559,7 +559,7 @@ __global__ void k_crf_first(Shape S, Tab tb, Ws ws, const double* __restrict__ r
   const T* UB = (const T*)ws.ub + ej * ns * np;
   for (int c = tid(); c < np; c += nthr()) {
     double acc = 0.0;
-    for (int p = 0; p < ns; ++p) acc += (double)UB[p * np + c] * r[p];
+    acc = dot4(UB + c, np, r, ns);
     ws.cBsep[ej * np + c] = acc;
   }
 }
@@ -586,12 +586,12 @@ __global__ void k_crf_step(Shape S, Tab tb, Ws ws, const double* __restrict__ rh
     if (h1) {
       const T* U = (const T*)ws.ur + (e0 + j1) * ns * ns;
       const double* yv = ws.ysep + (e0 + j1) * ns;
-      for (int p = 0; p < ns; ++p) v -= (double)U[p * ns + a] * yv[p];
+      v -= dot4(U + a, ns, yv, ns);
     }
     if (h2) {
       const T* U = (const T*)ws.ul + (e0 + j2) * ns * ns;
       const double* yv = ws.ysep + (e0 + j2) * ns;
-      for (int p = 0; p < ns; ++p) v -= (double)U[p * ns + a] * yv[p];
+      v -= dot4(U + a, ns, yv, ns);
     }
     r[a] = v;
   }
@@ -606,7 +606,7 @@ __global__ void k_crf_step(Shape S, Tab tb, Ws ws, const double* __restrict__ rh
   const T* UB = (const T*)ws.ub + es * ns * np;
   for (int c = tid(); c < np; c += nthr()) {
     double acc = 0.0;
-    for (int p = 0; p < ns; ++p) acc += (double)UB[p * np + c] * r[p];
+    acc = dot4(UB + c, np, r, ns);
     ws.cBsep[es * np + c] = acc;
   }
 }
@@ -636,7 +636,7 @@ __global__ void __launch_bounds__(1024) k_border_solve(Shape S, Tab tb, Ws ws, c
     if (jl < N) {
       const T* U = (const T*)ws.ul + (e0 + jl) * ns * ns;
       const double* yv = ws.ysep + (e0 + jl) * ns;
-      for (int p = 0; p < ns; ++p) v -= (double)U[p * ns + a] * yv[p];
+      v -= dot4(U + a, ns, yv, ns);
     }
     r[a] = v;
   }
@@ -684,7 +684,7 @@ __global__ void __launch_bounds__(1024) k_border_solve(Shape S, Tab tb, Ws ws, c
       }
     }
     double u = 0.0;
-    for (int p = 0; p < ns; ++p) u += (double)UB0[p * np + c] * r[p];
+    u = dot4(UB0 + c, np, r, ns);
     rt[c] = rhs[xoff + (int64_t)N * S.b + c] - sum - u;
   }
   __syncthreads();
@@ -695,7 +695,7 @@ __global__ void __launch_bounds__(1024) k_border_solve(Shape S, Tab tb, Ws ws, c
   __syncthreads();
   for (int a = tid(); a < ns; a += nthr()) {
     double v = r[a];
-    for (int c = 0; c < np; ++c) v -= (double)UB0[a * np + c] * rt[c];
+    v -= dot4(UB0 + a * np, 1, rt, np);
     r[a] = v;
   }
   __syncthreads();
@@ -727,13 +727,13 @@ __global__ void k_cr_bwd(Shape S, Tab tb, Ws ws, int level) {
     const T* UR = (const T*)ws.ur + ej * ns * ns;
     const T* UB = (const T*)ws.ub + ej * ns * np;
     const double* xl = ws.xsep + (e0 + j - half) * ns;
-    for (int q = 0; q < ns; ++q) v -= (double)UL[a * ns + q] * xl[q];
+    v -= dot4(UL + a * ns, 1, xl, ns);
     if (j + half < N) {
       const double* xr = ws.xsep + (e0 + j + half) * ns;
-      for (int q = 0; q < ns; ++q) v -= (double)UR[a * ns + q] * xr[q];
+      v -= dot4(UR + a * ns, 1, xr, ns);
     }
     const double* xt = ws.xth + inst * np;
-    for (int c = 0; c < np; ++c) v -= (double)UB[a * np + c] * xt[c];
+    v -= dot4(UB + a * np, 1, xt, np);
     r[a] = v;
   }
   __syncthreads();

@@ -3,6 +3,7 @@
 // grid whose block count stays within the instantiated range; a handle may override the grid
 // per kernel (tuning).
 #include "kernels.h"
+#include "chain_impl.h"
 
 namespace cl {
 void launch_level0_8_1(const Shape&, const Tab&, const Ws&, int, int, hipStream_t);
@@ -135,9 +136,21 @@ int chain_rows(const Shape& S, int which) { return which == 2 ? S.ns + S.np : 3 
 
 int tile_rows(const Shape& S, int which) { return which == 0 ? S.R : chain_rows(S, which); }
 
+size_t chain_blk_lds_bytes(const Shape& S) {
+  const size_t ns = S.ns, Rt = 2 * (size_t)S.ns + S.np;
+  return sizeof(double) * (ns * ns + Rt * ns + ns + 8);
+}
+
+// The blocked LDS variant of the chain kernel (selected as TS = 1, FP64 factors only).
+bool chain_blk_ok(const Shape& S) { return chain_blk_lds_bytes(S) <= 64 * 1024 && S.ns <= 64; }
+
 int tile_options(const Shape& S, int which, int* ts, int cap) {
   const int rows = tile_rows(S, which);
   int n = 0;
+  if (which == 1 && chain_blk_ok(S)) {
+    if (n < cap) ts[n] = 1;
+    ++n;
+  }
   for (int t : {8, 16, 20, 24})
     if (find_variant(t, rows)) {
       if (n < cap) ts[n] = t;
@@ -147,6 +160,7 @@ int tile_options(const Shape& S, int which, int* ts, int cap) {
 }
 
 bool tile_valid(const Shape& S, int which, int ts) {
+  if (ts == 1) return which == 1 && chain_blk_ok(S);
   return ts == 0 || find_variant(ts, tile_rows(S, which)) != nullptr;
 }
 
@@ -174,9 +188,15 @@ int level0_prepare_attrs(const Shape& S) {
 int launch_chain(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level,
                  unsigned grid, int ts, hipStream_t st) {
   if (grid == 0) return 0;
+  // the blocked LDS variant of the FP64 chain levels when chosen (TS = 1)
+  if (prec == 0 && mode != 2 && ts == 1 && chain_blk_ok(S)) {
+    hipLaunchKernelGGL(k_chain_blk<double>, dim3(grid), dim3(256), chain_blk_lds_bytes(S), st, S, tb,
+                       ws, mode, level);
+    return 0;
+  }
   const int Rl = chain_rows(S, mode == 2 ? 2 : 1);
   const size_t lds = sizeof(double) * (8 * (size_t)Rl + 8);
-  const Variant* v = pick(ts, Rl);
+  const Variant* v = pick(ts == 1 ? 0 : ts, Rl);
   if (!v) return -1;
   v->chain(S, tb, ws, prec, mode, level, grid, lds, st);
   return 0;
