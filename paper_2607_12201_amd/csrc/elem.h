@@ -126,15 +126,12 @@ __device__ inline void jtu_rows(const Shape& S, const Tab& tb, int inst, double 
     int j = t / ns, s = t - j * ns;
     double acc = (j == 0) ? u[s] : 0.0;
     for (int k = 1; k <= K; ++k) acc += S.a[j][k] * u[k * ns + s];
-    if (j >= 1) {
+    if (j >= 1) {   // reactant slots of species s (a 2A reaction lists both slots)
       double f = 0.0;
-      for (int r = 0; r < nr; ++r) {
-        int q0 = tb.react[(inst * nr + r) * 2], q1 = tb.react[(inst * nr + r) * 2 + 1];
-        const double* jr = jac + ((j - 1) * nr + r) * 3;
-        double w = 0.0;
-        if (q0 == s) w += jr[0];
-        if (q1 == s) w += jr[1];
-        if (w != 0.0) f += w * phi[(j - 1) * nr + r];
+      const int o0 = tb.rq_ptr[inst * (ns + 1) + s], o1 = tb.rq_ptr[inst * (ns + 1) + s + 1];
+      for (int o = o0; o < o1; ++o) {
+        const int r = tb.rq_r[o];
+        f += jac[((j - 1) * nr + r) * 3 + tb.rq_t[o]] * phi[(j - 1) * nr + r];
       }
       acc -= h * f;
     }
@@ -142,11 +139,14 @@ __device__ inline void jtu_rows(const Shape& S, const Tab& tb, int inst, double 
     outz[t] = acc;
   }
   if (outth) {
-    for (int c = tid(); c < S.np; c += nthr()) {
+    for (int c = tid(); c < S.np; c += nthr()) {   // reactions of parameter c
       double acc = 0.0;
+      const int o0 = tb.pc_ptr[inst * (S.np + 1) + c], o1 = tb.pc_ptr[inst * (S.np + 1) + c + 1];
       for (int k = 1; k <= K; ++k)
-        for (int r = 0; r < nr; ++r)
-          if (tb.param[inst * nr + r] == c) acc += jac[((k - 1) * nr + r) * 3 + 2] * phi[(k - 1) * nr + r];
+        for (int o = o0; o < o1; ++o) {
+          const int r = tb.pc_r[o];
+          acc += jac[((k - 1) * nr + r) * 3 + 2] * phi[(k - 1) * nr + r];
+        }
       outth[c] = -h * acc;
     }
   }
@@ -161,19 +161,15 @@ __device__ inline void wv_rows(const Shape& S, const Tab& tb, int inst, int64_t 
   for (int t = tid(); t < S.b; t += nthr()) {
     int j = t / ns, s = t - j * ns;
     double acc = 0.0;
-    if (j >= 1) {
-      for (int r = 0; r < nr; ++r) {
-        int q0 = tb.react[(inst * nr + r) * 2], q1 = tb.react[(inst * nr + r) * 2 + 1];
-        int c = tb.param[inst * nr + r];
+    if (j >= 1) {   // reactant slots of species s
+      const int o0 = tb.rq_ptr[inst * (ns + 1) + s], o1 = tb.rq_ptr[inst * (ns + 1) + s + 1];
+      for (int o = o0; o < o1; ++o) {
+        const int r = tb.rq_r[o], sl = tb.rq_t[o];
+        const int other = tb.react[(inst * nr + r) * 2 + (1 - sl)];
+        const int c = tb.param[inst * nr + r];
         const double* H = hess + ((j - 1) * nr + r) * 4;
-        if (q0 == s) {
-          if (q1 >= 0) acc += H[0] * v[j * ns + q1];
-          if (c >= 0) acc += H[1] * vth[c];
-        }
-        if (q1 == s) {
-          if (q0 >= 0) acc += H[0] * v[j * ns + q0];
-          if (c >= 0) acc += H[2] * vth[c];
-        }
+        if (other >= 0) acc += H[0] * v[j * ns + other];
+        if (c >= 0) acc += H[1 + sl] * vth[c];
       }
     }
     int m0 = tb.elem_mptr[e], m1 = tb.elem_mptr[e + 1];
@@ -187,11 +183,12 @@ __device__ inline void wv_rows(const Shape& S, const Tab& tb, int inst, int64_t 
     outz[t] = acc;
   }
   if (outth) {
-    for (int c = tid(); c < S.np; c += nthr()) {
+    for (int c = tid(); c < S.np; c += nthr()) {   // reactions of parameter c
       double acc = 0.0;
+      const int o0 = tb.pc_ptr[inst * (S.np + 1) + c], o1 = tb.pc_ptr[inst * (S.np + 1) + c + 1];
       for (int k = 1; k <= K; ++k)
-        for (int r = 0; r < nr; ++r) {
-          if (tb.param[inst * nr + r] != c) continue;
+        for (int o = o0; o < o1; ++o) {
+          const int r = tb.pc_r[o];
           int q0 = tb.react[(inst * nr + r) * 2], q1 = tb.react[(inst * nr + r) * 2 + 1];
           const double* H = hess + ((k - 1) * nr + r) * 4;
           if (q0 >= 0) acc += H[1] * v[k * ns + q0];

@@ -585,6 +585,7 @@ __global__ void __launch_bounds__(256) k_ipm_trial(Shape S, Tab tb, IpmState st,
 // the candidates in order with the filter rules and updates the filter.
 __global__ void k_ipm_select(Shape S, Tab tb, IpmState st, Ws ws, colloc_ipm_opts o) {
   __shared__ double cth[CL_MAX_LS], cph[CL_MAX_LS];
+  __shared__ int cfl[CL_MAX_LS];
   __shared__ double r0[256], r1[256], r2[256];
   const int inst = blockIdx.x;
   colloc_ipm_info I = st.info[inst];
@@ -634,21 +635,28 @@ __global__ void k_ipm_select(Shape S, Tab tb, IpmState st, Ws ws, colloc_ipm_opt
     cph[t] = ob - I.mu * lg;
   }
   __syncthreads();
+  // filter acceptability of every candidate, in parallel (thread t: candidate t)
+  const double* fth = st.fth + inst * CL_FILTER_CAP;
+  const double* fph = st.fph + inst * CL_FILTER_CAP;
+  if (t < nls) {
+    const double tht = cth[t], pht = cph[t];
+    bool okf = isfinite(tht) && isfinite(pht);
+    for (int f = 0; okf && f < I.filter_len; ++f)
+      if (!(tht < fth[f] || pht < fph[f])) okf = false;
+    cfl[t] = okf ? 1 : 0;
+  }
+  __syncthreads();
   if (t != 0) return;
   const double thc = I.theta_cv, phc = I.phi, dp = I.dphi;
   double alpha = I.alpha_pr;
   int acc = -1;
   bool ftype = false;
   int ntrial = 0;
-  const double* fth = st.fth + inst * CL_FILTER_CAP;
-  const double* fph = st.fph + inst * CL_FILTER_CAP;
   for (int q = 0; q < nls; ++q) {
     if (alpha < I.alpha_min) break;
     ++ntrial;
-    double tht = cth[q], pht = cph[q];
-    bool okf = isfinite(tht) && isfinite(pht);
-    for (int f = 0; okf && f < I.filter_len; ++f)
-      if (!(tht < fth[f] || pht < fph[f])) okf = false;
+    const double tht = cth[q], pht = cph[q];
+    const bool okf = cfl[q] != 0;
     if (okf) {
       bool sw = dp < 0 && alpha * pow(-dp, o.s_phi) > o.delta_sw * pow(thc, o.s_theta);
       bool arm = pht <= phc + o.eta_phi * alpha * dp;
