@@ -147,6 +147,55 @@ __device__ inline double chain_offdiag(const Shape& S, const Ws& ws, const Chain
   return sep_G<T>(S, ws, c.src, q, a - 2 * ns);
 }
 
+// The separator columns of a chain item's local matrix (its first ns columns, all Rl rows),
+// gathered into X (row-major, Rl x ns) by all threads.  In each pass a thread loads one entry
+// of every row group (T_s with its added terms, the neighbour couplings, G_s with its added
+// terms) from valid addresses (the separator's own block where a term does not apply), then
+// selects and stores them, so a pass costs one memory latency.  X[Rl * ns] is a dummy slot for
+// threads past the end of a group.  Terms are added in the order of sep_T / sep_G.
+template <typename T>
+__device__ inline void chain_stage(const Shape& S, const Ws& ws, const ChainItem& c, bool border,
+                                   int Rl, int th0, double* X) {
+  const int ns = S.ns, np = S.np;
+  const int64_t n2 = (int64_t)ns * ns, ng = (int64_t)ns * np;
+  const bool an = c.src.add_next, h1 = c.src.j1 >= 0, h2 = c.src.j2 >= 0;
+  const bool hL = !border && c.eL >= 0, hR = !border && c.eR >= 0;
+  const T* tw = (const T*)ws.dss + c.es * n2;
+  const T* t1 = an ? (const T*)ws.tprev + (c.es + 1) * n2 : tw;
+  const T* t2 = h1 ? (const T*)ws.cTr + c.src.j1 * n2 : tw;
+  const T* t3 = h2 ? (const T*)ws.cTl + c.src.j2 * n2 : tw;
+  const T* gw = (const T*)ws.bs + c.es * ng;
+  const T* g1 = an ? (const T*)ws.gprev + (c.es + 1) * ng : gw;
+  const T* g2 = h1 ? (const T*)ws.cGr + c.src.j1 * ng : gw;
+  const T* g3 = h2 ? (const T*)ws.cGl + c.src.j2 * ng : gw;
+  const T* pl = hL ? (const T*)(c.eL_is_e1 ? ws.e1 : ws.cE) + c.eL * n2 : tw;
+  const T* pr = hR ? (const T*)(c.eR_is_e1 ? ws.e1 : ws.cE) + c.eR * n2 : tw;
+  const int nT = ns * ns, nG = np * ns, nmax = nT > nG ? nT : nG, dummy = Rl * ns;
+  for (int t0 = 0; t0 < nmax; t0 += nthr()) {
+    const int t = t0 + tid();
+    const bool vT = t < nT, vG = t < nG;
+    const int tT = vT ? t : 0, tG = vG ? t : 0;
+    const int a = tT / ns, q = tT - a * ns;       // separator-column entry (a, q)
+    const int cg = tG / ns, qg = tG - cg * ns;    // theta row cg, separator column qg
+    const int iG = qg * np + cg;
+    const double xT0 = (double)tw[tT], xT1 = (double)t1[tT], xT2 = (double)t2[tT], xT3 = (double)t3[tT];
+    const double xL = (double)pl[q * ns + a], xR = (double)pr[a * ns + q];
+    const double xG0 = (double)gw[iG], xG1 = (double)g1[iG], xG2 = (double)g2[iG], xG3 = (double)g3[iG];
+    double vt = xT0;
+    vt += an ? xT1 : 0.0;
+    vt += h1 ? xT2 : 0.0;
+    vt += h2 ? xT3 : 0.0;
+    double vg = xG0;
+    vg += an ? xG1 : 0.0;
+    vg += h1 ? xG2 : 0.0;
+    vg += h2 ? xG3 : 0.0;
+    X[vT ? a * ns + q : dummy] = vt;
+    X[vG ? (th0 + cg) * ns + qg : dummy] = vg;
+    X[vT && !border ? (ns + a) * ns + q : dummy] = hL ? xL : 0.0;
+    X[vT && !border ? (2 * ns + a) * ns + q : dummy] = hR ? xR : 0.0;
+  }
+}
+
 // Elimination of one separator by blocks, in LDS (FP64): Cholesky of the separator block T_s
 // by one wave, then U = L_s^{-1} [E_L E_R G]^T row by row (one thread per row), then the Schur
 // contributions -U^T U as register-blocked dot products over the ns pivot columns.  It needs few
@@ -287,11 +336,8 @@ __global__ void __launch_bounds__(TS* TS) k_chain(Shape S, Tab tb, Ws ws, int mo
   const int inst = ci.inst;
   if (block_flag(&ws.flag[inst])) return;
   const int64_t es = ci.es;
-  const SepSrc& src = ci.src;
-  const int64_t eL = ci.eL, eR = ci.eR;
-  const bool eL_is_e1 = ci.eL_is_e1, eR_is_e1 = ci.eR_is_e1;
   if (!ci.elim) {
-    chain_survivor<T>(S, ws, src);
+    chain_survivor<T>(S, ws, ci.src);
     return;
   }
 
@@ -301,32 +347,44 @@ __global__ void __launch_bounds__(TS* TS) k_chain(Shape S, Tab tb, Ws ws, int mo
   const int ty = threadIdx.x / TS, tx = threadIdx.x % TS;
   double* pbuf = lds;
   double* misc = pbuf + 8 * Rl;
+  const bool border = mode == CH_BORDER;
+  double* X = misc + 8;                                 // Rl x ns separator columns + 1
+  chain_stage<T>(S, ws, ci, border, Rl, th0, X);
+  __syncthreads();
   double av[NBLK];
+  if (border) {
+    // separator columns from X, the reduced parameter block straight from memory
+    const double* Sg = ws.S + (int64_t)inst * np * np;
 #pragma unroll
-  for (int I = 0; I < NB; ++I)
+    for (int I = 0; I < NB; ++I)
 #pragma unroll
-    for (int J = 0; J <= I; ++J) {
-      const int r = I * TS + ty, q = J * TS + tx;
-      double v = 0.0;
-      if (r < Rl && q <= r) {
-        if (q < ns) {
-          if (r < ns) {
-            v = sep_T<T>(S, ws, src, r, q);
-          } else if (r >= th0) {
-            v = sep_G<T>(S, ws, src, q, r - th0);
-          } else if (r < 2 * ns) {          // left neighbour row a: E_L[q][a] = K(s_q, l_a)
-            const int a = r - ns;
-            if (eL >= 0) v = eL_is_e1 ? ld<T>(ws.e1, eL * ns * ns + q * ns + a) : ld<T>(ws.cE, eL * ns * ns + q * ns + a);
-          } else {                          // right neighbour row a: E_R[a][q] = K(r_a, s_q)
-            const int a = r - 2 * ns;
-            if (eR >= 0) v = eR_is_e1 ? ld<T>(ws.e1, eR * ns * ns + a * ns + q) : ld<T>(ws.cE, eR * ns * ns + a * ns + q);
-          }
-        } else if (mode == CH_BORDER) {     // theta-theta: reduced parameter block
-          v = ws.S[(int64_t)inst * np * np + (r - ns) * np + (q - ns)];
-        }
+      for (int J = 0; J <= I; ++J) {
+        const int r = I * TS + ty, q = J * TS + tx;
+        const bool in = r < Rl && q <= r, qs = q < ns;
+        const double xs = Sg[in && !qs ? (r - ns) * np + (q - ns) : 0];
+        const double xx = X[in && qs ? r * ns + q : 0];
+        av[I * (I + 1) / 2 + J] = pick(in, pick(qs, xx, xs), 0.0);
       }
-      av[I * (I + 1) / 2 + J] = v;
+  } else {
+    // column block 0 holds separator columns; the blocks right of it only when the separator
+    // is wider than the grid
+#pragma unroll
+    for (int I = 0; I < NB; ++I) {
+      const int r = I * TS + ty, q = tx;
+      const bool in = r < Rl && q <= r && q < ns;
+      const double xx = X[in ? r * ns + q : 0];
+      av[I * (I + 1) / 2] = in ? xx : 0.0;
     }
+#pragma unroll
+    for (int I = 1; I < NB; ++I)
+#pragma unroll
+      for (int J = 1; J <= I; ++J) {
+        const int r = I * TS + ty, q = J * TS + tx;
+        const bool in = r < Rl && q <= r && q < ns;
+        const double xx = X[in ? r * ns + q : 0];
+        av[I * (I + 1) / 2 + J] = in ? xx : 0.0;
+      }
+  }
 
   bool ok;
   if constexpr (sizeof(T) == 8) {

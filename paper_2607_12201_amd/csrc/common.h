@@ -83,6 +83,7 @@ struct Ws {
   double* S;                  // [n_inst][np*np] parameter Schur complement / its factor
   double* thred;              // [n_inst][nchunk][np*np] reduction partials
   int nchunk;                 // chunks per instance (max over the batch)
+  double* thv;                // [n_inst][nchunk][np] theta right-hand-side chunk partials
   double* yI;                 // [n_elem][mI]
   double* cS;                 // [n_elem][ns]
   double* cP;                 // [n_elem][ns]

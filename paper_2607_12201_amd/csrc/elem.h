@@ -8,6 +8,11 @@ namespace cl {
 __device__ inline int tid() { return threadIdx.x; }
 __device__ inline int nthr() { return blockDim.x; }
 
+// c ? a : b kept as a select.  A plain conditional whose operand is a single-use load may be
+// turned into a branch around that load, which then waits for it inside the branch; gathers
+// that issue several loads before using any of them pick their results with this.
+__device__ inline double pick(bool c, double a, double b) { return __builtin_unpredictable(c) ? a : b; }
+
 // Per-instance skip flag read once per workgroup: other workgroups of the same launch may set
 // it concurrently, so every wave takes the decision from one LDS copy (uniform control flow
 // around the barriers that follow).

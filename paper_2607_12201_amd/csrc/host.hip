@@ -222,6 +222,7 @@ extern "C" int colloc_create(const colloc_instance_desc* inst, int32_t n_inst, i
   int nt = elem_threads(S);
   size_t need = std::max<size_t>(level0_lds_bytes(S, 0), ipm_eval_lds(S, nt));
   need = std::max<size_t>(need, level0r_lds_bytes(S));
+  need = std::max<size_t>(need, std::max(chain_lds_bytes(S, 1), chain_lds_bytes(S, 2)));
   if (!level0r_supported(S)) {
     delete p;
     return COLLOC_EUNSUPPORTED;
@@ -230,6 +231,8 @@ extern "C" int colloc_create(const colloc_instance_desc* inst, int32_t n_inst, i
       (size_t)2 * ns * ns + 2 * (size_t)ns * np + (size_t)np * np + 8,
       (size_t)7 * ns * ns + 3 * (size_t)ns * np + 8);
   need_b = std::max<size_t>(need_b, sizeof(double) * ((size_t)ns * ns + ns + np + (size_t)np * np + 1024));
+  need_b = std::max<size_t>(need_b, sep_solve_lds(S));
+  need_b = std::max<size_t>(need_b, border_solve_lds(S));
   // line-search trials: vectors, rate constants of every candidate, partial sums (no attribute)
   const size_t need_t = sizeof(double) * (4 * (size_t)S.b + 2 * ns + 2 * np + (size_t)CL_MAX_LS * nr + 768);
   if (need > lds_limit() || need_b > lds_limit() || need_t > 64 * 1024 || nr * K > 65536) {
@@ -556,6 +559,7 @@ static Ws ws_layout(const colloc_problem* p, int prec, void* base, size_t* bytes
   w.S = c.take<double>(I * S.np * S.np);
   w.nchunk = p->nchunk;
   w.thred = c.take<double>(I * p->nchunk * S.np * S.np);
+  w.thv = c.take<double>(I * p->nchunk * S.np);
   w.yI = c.take<double>(E * S.mI);
   w.cS = c.take<double>(E * S.ns);
   w.cP = c.take<double>(E * S.ns);

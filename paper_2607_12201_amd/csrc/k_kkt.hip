@@ -429,11 +429,21 @@ __global__ void k_thred(Shape S, Tab tb, Ws ws) {
   const int r = t / np, q = t % np;
   if (q > r) return;
   const int64_t e0 = tb.inst_e0[inst];
+  // all loads of the chunk issued together (the last valid element stands in past the end;
+  // separator 0 has no chain part), then added in element order
+  double xa[CL_THCHUNK], xc[CL_THCHUNK];
+#pragma unroll
+  for (int u = 0; u < CL_THCHUNK; ++u) {
+    const int64_t ei = e0 + min(i0 + u, i1 - 1);
+    xa[u] = ws.ath[ei * np * np + t];
+    xc[u] = ws.thcr[ei * np * np + t];
+  }
   double acc = 0.0;
-#pragma unroll 4
-  for (int i = i0; i < i1; ++i) {
-    acc += ws.ath[(e0 + i) * np * np + t];
-    if (i > 0) acc += ws.thcr[(e0 + i) * np * np + t];
+#pragma unroll
+  for (int u = 0; u < CL_THCHUNK; ++u) {
+    const int i = i0 + u;
+    acc += pick(i < i1, xa[u], 0.0);
+    acc += pick(i < i1 && i > 0, xc[u], 0.0);
   }
   ws.thred[((int64_t)inst * ws.nchunk + chunk) * np * np + t] = acc;
 }
@@ -537,62 +547,96 @@ __device__ inline double sep_rhs_initial(const Shape& S, const Ws& ws, const dou
   return v;
 }
 
-// LDS: Lm (ns^2) r (ns)
-template <typename T>
-__global__ void k_crf_first(Shape S, Tab tb, Ws ws, const double* __restrict__ rhs) {
-  extern __shared__ double lds[];
-  const int it = tb.cr_ptr[0] + blockIdx.x;
-  if (it >= tb.cr_ptr[1]) return;
-  const int inst = tb.cr_inst[it], j = tb.cr_j[it];
-  if (block_flag(&ws.flag[inst])) return;
-  const int ns = S.ns, np = S.np, N = tb.inst_N[inst];
-  const int64_t e0 = tb.inst_e0[inst], ej = e0 + j;
-  double* Lm = lds;
-  double* r = Lm + ns * ns;
-  load_blk(Lm, (const T*)ws.lsep + ej * ns * ns, ns * ns);
-  for (int a = tid(); a < ns; a += nthr())
-    r[a] = sep_rhs_initial(S, ws, rhs, tb.inst_x[inst], ej, j, j + 1 < N, a);
-  __syncthreads();
-  if (tid() < 64) wave_trsv_l(RowMajor{Lm, ns}, ns, r);
-  __syncthreads();
-  for (int t = tid(); t < ns; t += nthr()) ws.ysep[ej * ns + t] = r[t];
-  const T* UB = (const T*)ws.ub + ej * ns * np;
-  for (int c = tid(); c < np; c += nthr()) {
-    double acc = 0.0;
-    acc = dot4(UB + c, np, r, ns);
-    ws.cBsep[ej * np + c] = acc;
-  }
+// LDS of the separator solve kernels: three ns x ns blocks, the ns x np border rows, four
+// ns-vectors, an np-vector and a dummy slot.
+size_t sep_solve_lds(const Shape& S) {
+  const size_t ns = S.ns, np = S.np;
+  return sizeof(double) * (3 * ns * ns + ns * np + 4 * ns + np + 1);
+}
+constexpr int kSepThreads = 256;    // most threads per item
+constexpr int kSepUnroll = 4;       // block entries per thread per staging pass
+// Threads per item: enough for one staging pass over the largest block, in whole waves.
+static int sep_solve_threads(const Shape& S) {
+  const int n2 = S.ns * S.ns, ng = S.ns * S.np;
+  const int need = ((n2 > ng ? n2 : ng) + kSepUnroll - 1) / kSepUnroll;
+  return need <= 64 ? 64 : (need <= 128 ? 128 : kSepThreads);
+}
+
+// One forward step of the separator chain (the first level when `first`): gathers everything
+// the item needs in one flat pass per 256 entries (every load issued before the first store,
+// index 0 past a block's end, a valid address for absent terms, a dummy LDS slot as the store
+// target), then r = rhs_s - U_R(j1)^T y(j1) - U_L(j2)^T y(j2); an eliminated separator solves
+// y_s = L_s^{-1} r and forms its border term U_B^T y_s, a survivor keeps r for the next level.
+// An item's instance data, read before the skip-flag barrier so the loads overlap.
+struct SepInst {
+  int N;
+  int64_t e0, x;
+};
+__device__ inline SepInst sep_inst(const Tab& tb, int inst) {
+  return SepInst{tb.inst_N[inst], tb.inst_e0[inst], tb.inst_x[inst]};
 }
 
 template <typename T>
-__global__ void k_crf_step(Shape S, Tab tb, Ws ws, const double* __restrict__ rhs, int level) {
+__device__ inline void sep_forward(const Shape& S, const Tab& tb, const Ws& ws, const double* rhs,
+                                   int inst, const SepInst& si, int s, int level, bool first) {
   extern __shared__ double lds[];
-  const int it = tb.st_ptr[level - 1] + blockIdx.x;
-  if (it >= tb.st_ptr[level]) return;
-  const int inst = tb.st_inst[it], s = tb.st_s[it];
-  if (block_flag(&ws.flag[inst])) return;
-  const int ns = S.ns, np = S.np, N = tb.inst_N[inst];
-  const int64_t e0 = tb.inst_e0[inst], es = e0 + s;
-  const int half = 1 << (level - 1);
-  const int j1 = s - half, j2 = s + half;
-  const bool h1 = s > 0, h2 = j2 < N;
-  const bool elim = ((s >> level) & 1) != 0;
+  const int ns = S.ns, np = S.np, N = si.N;
+  const int n2 = ns * ns, ng = ns * np;
+  const int64_t e0 = si.e0, es = e0 + s;
+  const int half = first ? 1 : 1 << (level - 1);
+  const bool h1 = !first && s > 0, h2 = !first && s + half < N;
+  const bool elim = first || ((s >> level) & 1) != 0;
+  const bool init = first || level == 1, has_next = s + 1 < N;
+  const int64_t e1 = h1 ? es - half : es, e2 = h2 ? es + half : es;
   double* Lm = lds;
-  double* r = Lm + ns * ns;
-  if (elim) load_blk(Lm, (const T*)ws.lsep + es * ns * ns, ns * ns);
+  double* U1 = Lm + n2;
+  double* U2 = U1 + n2;
+  double* UB = U2 + n2;
+  double* y1 = UB + ng;
+  double* y2 = y1 + ns;
+  double* r = y2 + ns;
+  double* dum = r + 2 * ns + np;
+  const T* lsrc = (const T*)ws.lsep + es * n2;
+  const T* u1src = (const T*)ws.ur + e1 * n2;
+  const T* u2src = (const T*)ws.ul + e2 * n2;
+  const T* ubsrc = (const T*)ws.ub + es * ng;
+  const double* rh = rhs + si.x + (int64_t)s * S.b + S.mI;
+  const double* cs = ws.cS + es * ns;
+  const double* cp = ws.cP + (has_next ? es + 1 : es) * ns;
+  const double* rc = ws.rcur + es * ns;
+  const int nmax = n2 > ng ? n2 : ng;
+  for (int t0 = 0; t0 < nmax; t0 += kSepUnroll * nthr()) {
+    double xl[kSepUnroll], xu1[kSepUnroll], xu2[kSepUnroll], xb[kSepUnroll];
+#pragma unroll
+    for (int u = 0; u < kSepUnroll; ++u) {
+      const int t = t0 + u * nthr() + tid();
+      const int i2 = t < n2 ? t : 0, ig = t < ng ? t : 0;
+      xl[u] = (double)lsrc[i2];
+      xu1[u] = (double)u1src[i2];
+      xu2[u] = (double)u2src[i2];
+      xb[u] = (double)ubsrc[ig];
+    }
+    const int t = t0 + tid(), iv = t < ns ? t : 0;
+    const double xy1 = ws.ysep[e1 * ns + iv], xy2 = ws.ysep[e2 * ns + iv];
+    const double xr = rh[iv], xs = cs[iv], xp = cp[iv], xc = rc[iv];
+    const double r0 = pick(init, (xr - xs) - pick(has_next, xp, 0.0), xc);
+#pragma unroll
+    for (int u = 0; u < kSepUnroll; ++u) {
+      const int tu = t0 + u * nthr() + tid();
+      *(tu < n2 ? Lm + tu : dum) = xl[u];
+      *(tu < n2 ? U1 + tu : dum) = xu1[u];
+      *(tu < n2 ? U2 + tu : dum) = xu2[u];
+      *(tu < ng ? UB + tu : dum) = xb[u];
+    }
+    *(t < ns ? y1 + t : dum) = xy1;
+    *(t < ns ? y2 + t : dum) = xy2;
+    *(t < ns ? r + t : dum) = r0;
+  }
+  __syncthreads();
   for (int a = tid(); a < ns; a += nthr()) {
-    double v = level == 1 ? sep_rhs_initial(S, ws, rhs, tb.inst_x[inst], es, s, s + 1 < N, a)
-                          : ws.rcur[es * ns + a];
-    if (h1) {
-      const T* U = (const T*)ws.ur + (e0 + j1) * ns * ns;
-      const double* yv = ws.ysep + (e0 + j1) * ns;
-      v -= dot4(U + a, ns, yv, ns);
-    }
-    if (h2) {
-      const T* U = (const T*)ws.ul + (e0 + j2) * ns * ns;
-      const double* yv = ws.ysep + (e0 + j2) * ns;
-      v -= dot4(U + a, ns, yv, ns);
-    }
+    double v = r[a];
+    if (h1) v -= dot4(U1 + a, ns, y1, ns);
+    if (h2) v -= dot4(U2 + a, ns, y2, ns);
     r[a] = v;
   }
   __syncthreads();
@@ -603,89 +647,173 @@ __global__ void k_crf_step(Shape S, Tab tb, Ws ws, const double* __restrict__ rh
   if (tid() < 64) wave_trsv_l(RowMajor{Lm, ns}, ns, r);
   __syncthreads();
   for (int t = tid(); t < ns; t += nthr()) ws.ysep[es * ns + t] = r[t];
-  const T* UB = (const T*)ws.ub + es * ns * np;
+  for (int c = tid(); c < np; c += nthr()) ws.cBsep[es * np + c] = dot4(UB + c, np, r, ns);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kSepThreads) k_crf_first(Shape S, Tab tb, Ws ws, const double* __restrict__ rhs) {
+  const int it = tb.cr_ptr[0] + blockIdx.x;
+  if (it >= tb.cr_ptr[1]) return;
+  const int inst = tb.cr_inst[it], j = tb.cr_j[it];
+  const SepInst si = sep_inst(tb, inst);
+  if (block_flag(&ws.flag[inst])) return;
+  sep_forward<T>(S, tb, ws, rhs, inst, si, j, 1, true);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kSepThreads) k_crf_step(Shape S, Tab tb, Ws ws, const double* __restrict__ rhs, int level) {
+  const int it = tb.st_ptr[level - 1] + blockIdx.x;
+  if (it >= tb.st_ptr[level]) return;
+  const int inst = tb.st_inst[it], s = tb.st_s[it];
+  const SepInst si = sep_inst(tb, inst);
+  if (block_flag(&ws.flag[inst])) return;
+  sep_forward<T>(S, tb, ws, rhs, inst, si, s, level, false);
+}
+
+// Theta partial sums of an instance over chunks of CL_THCHUNK elements, in element order:
+// out[inst][chunk][c] = sum_i (a[e_i][c] + [i > 0] b[e_i][c] - d[e_i][c]) with b and d optional
+// (null).  All loads of a chunk are issued together (the chunk's last element stands in past
+// the instance's end).  Grid (chunk, instance).
+__global__ void k_thpart(Shape S, Tab tb, Ws ws, const double* __restrict__ a,
+                         const double* __restrict__ b, const double* __restrict__ d,
+                         double* __restrict__ out) {
+  const int inst = blockIdx.y, chunk = blockIdx.x;
+  const int N = tb.inst_N[inst], np = S.np;
+  const int i0 = chunk * CL_THCHUNK;
+  if (i0 >= N) return;
+  const int i1 = min(N, i0 + CL_THCHUNK);
+  const int64_t e0 = tb.inst_e0[inst];
+  const double* bb = b ? b : a;
+  const double* dd = d ? d : a;
+  double* o = out + ((int64_t)inst * ws.nchunk + chunk) * np;
   for (int c = tid(); c < np; c += nthr()) {
+    double xa[CL_THCHUNK], xb[CL_THCHUNK], xd[CL_THCHUNK];
+#pragma unroll
+    for (int u = 0; u < CL_THCHUNK; ++u) {
+      const int64_t ei = (e0 + min(i0 + u, i1 - 1)) * np + c;
+      xa[u] = a[ei];
+      xb[u] = bb[ei];
+      xd[u] = dd[ei];
+    }
     double acc = 0.0;
-    acc = dot4(UB + c, np, r, ns);
-    ws.cBsep[es * np + c] = acc;
+#pragma unroll
+    for (int u = 0; u < CL_THCHUNK; ++u) {
+      const int i = i0 + u;
+      acc += pick(i < i1, xa[u], 0.0);
+      acc += pick(b != nullptr && i < i1 && i > 0, xb[u], 0.0);
+      acc -= pick(d != nullptr && i < i1, xd[u], 0.0);
+    }
+    o[c] = acc;
   }
 }
 
-// Border solve: separator 0, theta, back to separator 0.
-// LDS: Lm (ns^2) r (ns) rt (np) Sm (np^2) red (nthr * np)
+// Sum of the chunk partials of parameter c of an instance, in chunk order.
+__device__ inline double thpart_sum(const Ws& ws, const double* part, int inst, int N, int np, int c) {
+  const int nch = (int)cl_ceil_div(N, CL_THCHUNK);
+  const double* p = part + (int64_t)inst * ws.nchunk * np + c;
+  double acc = 0.0;
+#pragma unroll 8
+  for (int ch = 0; ch < nch; ++ch) acc += p[(int64_t)ch * np];
+  return acc;
+}
+
+// LDS of the border solve: L_0 and the upper coupling block (ns x ns each), the parameter
+// factor (np x np), the border rows (ns x np), y, r (ns), rt (np), the group sums (1024) and a
+// dummy slot.
+size_t border_solve_lds(const Shape& S) {
+  const size_t ns = S.ns, np = S.np;
+  return sizeof(double) * (2 * ns * ns + np * np + ns * np + 2 * ns + np + 1024 + 1);
+}
+
+// Border solve: separator 0, theta, back to separator 0.  Everything the instance needs is
+// gathered in one staging phase (two entries of each block per thread and pass); the theta
+// right-hand side sums the chunk partials of k_thpart (thread (c, g) takes chunks g, g + G, ...;
+// the G group sums are added in group order).
 template <typename T>
 __global__ void __launch_bounds__(1024) k_border_solve(Shape S, Tab tb, Ws ws, const double* __restrict__ rhs,
-                               const double* __restrict__ rthp, double* __restrict__ dx) {
+                                                      double* __restrict__ dx) {
   extern __shared__ double lds[];
   const int inst = blockIdx.x;
+  const SepInst si = sep_inst(tb, inst);
   if (block_flag(&ws.flag[inst])) return;
-  const int ns = S.ns, np = S.np, N = tb.inst_N[inst];
-  const int64_t e0 = tb.inst_e0[inst];
-  const int64_t xoff = tb.inst_x[inst];
-  double* Lm = lds;
-  double* r = Lm + ns * ns;
-  double* rt = r + ns;
-  double* Sm = rt + np;
-  double* red = Sm + np * np;
-  load_blk(Lm, (const T*)ws.lsep + e0 * ns * ns, ns * ns);
-  for (int t = tid(); t < np * np; t += nthr()) Sm[t] = ws.S[(int64_t)inst * np * np + t];
+  const int ns = S.ns, np = S.np, N = si.N;
+  const int n2 = ns * ns, ng = ns * np, nq = np * np;
+  const int64_t e0 = si.e0, xoff = si.x;
   const int L = tb.L;
   const int jl = L >= 1 ? (1 << (L - 1)) : N;
-  for (int a = tid(); a < ns; a += nthr()) {
-    double v = L <= 1 ? sep_rhs_initial(S, ws, rhs, xoff, e0, 0, N > 1, a) : ws.rcur[e0 * ns + a];
-    if (jl < N) {
-      const T* U = (const T*)ws.ul + (e0 + jl) * ns * ns;
-      const double* yv = ws.ysep + (e0 + jl) * ns;
-      v -= dot4(U + a, ns, yv, ns);
+  const bool hj = jl < N, init = L <= 1, has_next = N > 1;
+  double* Lm = lds;
+  double* U = Lm + n2;
+  double* Sm = U + n2;
+  double* UB = Sm + nq;
+  double* y = UB + ng;
+  double* r = y + ns;
+  double* rt = r + ns;
+  double* red = rt + np;
+  double* dum = red + 1024;
+  const T* lsrc = (const T*)ws.lsep + e0 * n2;
+  const T* usrc = (const T*)ws.ul + (hj ? e0 + jl : e0) * n2;
+  const double* ssrc = ws.S + (int64_t)inst * nq;
+  const T* ubsrc = (const T*)ws.ub + e0 * ng;
+  const double* ys = ws.ysep + (hj ? e0 + jl : e0) * ns;
+  const double* rh = rhs + xoff + S.mI;
+  const double* cs = ws.cS + e0 * ns;
+  const double* cp = ws.cP + (has_next ? e0 + 1 : e0) * ns;
+  const double* rc = ws.rcur + e0 * ns;
+  const double* rth = rhs + xoff + (int64_t)N * S.b;
+  int nmax = n2 > ng ? n2 : ng;
+  nmax = nq > nmax ? nq : nmax;
+  for (int t0 = 0; t0 < nmax; t0 += 2 * nthr()) {
+    double xl[2], xu[2], xs[2], xb[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int t = t0 + u * nthr() + tid();
+      const int i2 = t < n2 ? t : 0, ig = t < ng ? t : 0, iq = t < nq ? t : 0;
+      xl[u] = (double)lsrc[i2];
+      xu[u] = (double)usrc[i2];
+      xs[u] = ssrc[iq];
+      xb[u] = (double)ubsrc[ig];
     }
+    const int t = t0 + tid(), iv = t < ns ? t : 0, ip = t < np ? t : 0;
+    const double xy = ys[iv], xr = rh[iv], xc = cs[iv], xp = cp[iv], xcur = rc[iv], xt = rth[ip];
+    const double r0 = pick(init, (xr - xc) - pick(has_next, xp, 0.0), xcur);
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int tu = t0 + u * nthr() + tid();
+      *(tu < n2 ? Lm + tu : dum) = xl[u];
+      *(tu < n2 ? U + tu : dum) = xu[u];
+      *(tu < nq ? Sm + tu : dum) = xs[u];
+      *(tu < ng ? UB + tu : dum) = xb[u];
+    }
+    *(t < ns ? y + t : dum) = xy;
+    *(t < ns ? r + t : dum) = r0;
+    *(t < np ? rt + t : dum) = xt;
+  }
+  // theta right-hand side: chunk partials, G = threads / np groups
+  const int G = nthr() / np;
+  const int c0 = tid() % np, g0 = tid() / np;
+  const int nch = (int)cl_ceil_div(N, CL_THCHUNK);
+  double acc = 0.0;
+  if (g0 < G) {
+    const double* p = ws.thv + (int64_t)inst * ws.nchunk * np + c0;
+#pragma unroll 4
+    for (int ch = g0; ch < nch; ch += G) acc += p[(int64_t)ch * np];
+  }
+  red[tid()] = acc;
+  __syncthreads();
+  for (int a = tid(); a < ns; a += nthr()) {
+    double v = r[a];
+    if (hj) v -= dot4(U + a, ns, y, ns);
     r[a] = v;
   }
-  // theta right-hand side partial sums: thread t covers parameter t % np over the elements
-  // i = t / np, t / np + G, ... (G = threads / np groups), then a fixed-order group sum
-  const int G = max(1, nthr() / np);
-  const int c0 = tid() % np, g0 = tid() / np;
-  double acc = 0.0, acc2 = 0.0;
-  if (g0 < G) {
-    int i = g0;
-    for (; i + G < N; i += 2 * G) {     // two independent chains of loads in flight
-      acc += ws.cB[(e0 + i) * np + c0];
-      acc2 += ws.cB[(e0 + i + G) * np + c0];
-      if (i > 0) acc += ws.cBsep[(e0 + i) * np + c0];
-      acc2 += ws.cBsep[(e0 + i + G) * np + c0];
-      if (rthp) {
-        acc -= rthp[(e0 + i) * np + c0];
-        acc2 -= rthp[(e0 + i + G) * np + c0];
-      }
-    }
-    for (; i < N; i += G) {
-      acc += ws.cB[(e0 + i) * np + c0];
-      if (i > 0) acc += ws.cBsep[(e0 + i) * np + c0];
-      if (rthp) acc -= rthp[(e0 + i) * np + c0];
-    }
-    acc += acc2;
-  }
-  if (np > nthr()) {  // fall back: loop parameters per thread
-    acc = 0.0;
-  }
-  red[tid()] = (g0 < G) ? acc : 0.0;
   __syncthreads();
   if (tid() < 64) wave_trsv_l(RowMajor{Lm, ns}, ns, r);
   __syncthreads();
-  const T* UB0 = (const T*)ws.ub + e0 * ns * np;
   for (int c = tid(); c < np; c += nthr()) {
     double sum = 0.0;
-    if (np <= nthr()) {
-      for (int g = 0; g < G; ++g) sum += red[g * np + c];
-    } else {
-      for (int i = 0; i < N; ++i) {
-        sum += ws.cB[(e0 + i) * np + c];
-        if (i > 0) sum += ws.cBsep[(e0 + i) * np + c];
-        if (rthp) sum -= rthp[(e0 + i) * np + c];
-      }
-    }
-    double u = 0.0;
-    u = dot4(UB0 + c, np, r, ns);
-    rt[c] = rhs[xoff + (int64_t)N * S.b + c] - sum - u;
+    for (int g = 0; g < G; ++g) sum += red[g * np + c];
+    const double u = dot4(UB + c, np, r, ns);
+    rt[c] = rt[c] - sum - u;
   }
   __syncthreads();
   if (tid() < 64) {
@@ -695,7 +823,7 @@ __global__ void __launch_bounds__(1024) k_border_solve(Shape S, Tab tb, Ws ws, c
   __syncthreads();
   for (int a = tid(); a < ns; a += nthr()) {
     double v = r[a];
-    v -= dot4(UB0 + a * np, 1, rt, np);
+    v -= dot4(UB + a * np, 1, rt, np);
     r[a] = v;
   }
   __syncthreads();
@@ -708,31 +836,71 @@ __global__ void __launch_bounds__(1024) k_border_solve(Shape S, Tab tb, Ws ws, c
   for (int a = tid(); a < ns; a += nthr()) ws.xsep[e0 * ns + a] = r[a];
 }
 
+// Backward step of the separator chain: x_j = L_j^{-T} (y_j - U_L x(j - half) - U_R x(j + half)
+// - U_B x_theta), with the item's blocks and vectors gathered in one staging phase as in the
+// forward step.
 template <typename T>
-__global__ void k_cr_bwd(Shape S, Tab tb, Ws ws, int level) {
+__global__ void __launch_bounds__(kSepThreads) k_cr_bwd(Shape S, Tab tb, Ws ws, int level) {
   extern __shared__ double lds[];
   const int it = tb.cr_ptr[level - 1] + blockIdx.x;
   if (it >= tb.cr_ptr[level]) return;
   const int inst = tb.cr_inst[it], j = tb.cr_j[it];
+  const SepInst si = sep_inst(tb, inst);
   if (block_flag(&ws.flag[inst])) return;
-  const int ns = S.ns, np = S.np, N = tb.inst_N[inst];
-  const int64_t e0 = tb.inst_e0[inst], ej = e0 + j;
+  const int ns = S.ns, np = S.np, N = si.N;
+  const int n2 = ns * ns, ng = ns * np;
+  const int64_t e0 = si.e0, ej = e0 + j;
   const int half = 1 << (level - 1);
+  const bool hr = j + half < N;
   double* Lm = lds;
-  double* r = Lm + ns * ns;
-  load_blk(Lm, (const T*)ws.lsep + ej * ns * ns, ns * ns);
-  for (int a = tid(); a < ns; a += nthr()) {
-    double v = ws.ysep[ej * ns + a];
-    const T* UL = (const T*)ws.ul + ej * ns * ns;
-    const T* UR = (const T*)ws.ur + ej * ns * ns;
-    const T* UB = (const T*)ws.ub + ej * ns * np;
-    const double* xl = ws.xsep + (e0 + j - half) * ns;
-    v -= dot4(UL + a * ns, 1, xl, ns);
-    if (j + half < N) {
-      const double* xr = ws.xsep + (e0 + j + half) * ns;
-      v -= dot4(UR + a * ns, 1, xr, ns);
+  double* UL = Lm + n2;
+  double* UR = UL + n2;
+  double* UB = UR + n2;
+  double* xl = UB + ng;
+  double* xr = xl + ns;
+  double* r = xr + ns;
+  double* xt = r + 2 * ns;
+  double* dum = xt + np;
+  const T* lsrc = (const T*)ws.lsep + ej * n2;
+  const T* ulsrc = (const T*)ws.ul + ej * n2;
+  const T* ursrc = (const T*)ws.ur + ej * n2;
+  const T* ubsrc = (const T*)ws.ub + ej * ng;
+  const double* xls = ws.xsep + (ej - half) * ns;
+  const double* xrs = ws.xsep + (hr ? ej + half : ej) * ns;
+  const double* ys = ws.ysep + ej * ns;
+  const double* xts = ws.xth + inst * np;
+  const int nmax = n2 > ng ? n2 : ng;
+  for (int t0 = 0; t0 < nmax; t0 += kSepUnroll * nthr()) {
+    double xlm[kSepUnroll], xul[kSepUnroll], xur[kSepUnroll], xub[kSepUnroll];
+#pragma unroll
+    for (int u = 0; u < kSepUnroll; ++u) {
+      const int t = t0 + u * nthr() + tid();
+      const int i2 = t < n2 ? t : 0, ig = t < ng ? t : 0;
+      xlm[u] = (double)lsrc[i2];
+      xul[u] = (double)ulsrc[i2];
+      xur[u] = (double)ursrc[i2];
+      xub[u] = (double)ubsrc[ig];
     }
-    const double* xt = ws.xth + inst * np;
+    const int t = t0 + tid(), iv = t < ns ? t : 0, ip = t < np ? t : 0;
+    const double vl = xls[iv], vr = xrs[iv], vy = ys[iv], vt = xts[ip];
+#pragma unroll
+    for (int u = 0; u < kSepUnroll; ++u) {
+      const int tu = t0 + u * nthr() + tid();
+      *(tu < n2 ? Lm + tu : dum) = xlm[u];
+      *(tu < n2 ? UL + tu : dum) = xul[u];
+      *(tu < n2 ? UR + tu : dum) = xur[u];
+      *(tu < ng ? UB + tu : dum) = xub[u];
+    }
+    *(t < ns ? xl + t : dum) = vl;
+    *(t < ns ? xr + t : dum) = vr;
+    *(t < ns ? r + t : dum) = vy;
+    *(t < np ? xt + t : dum) = vt;
+  }
+  __syncthreads();
+  for (int a = tid(); a < ns; a += nthr()) {
+    double v = r[a];
+    v -= dot4(UL + a * ns, 1, xl, ns);
+    if (hr) v -= dot4(UR + a * ns, 1, xr, ns);
     v -= dot4(UB + a * np, 1, xt, np);
     r[a] = v;
   }
@@ -922,20 +1090,21 @@ template <typename T>
 static int solve_t(const Shape& S, const Tab& tb, const HostPlan& hp, const Ws& ws,
                    const double* rhs, const double* rthp, double* dx, phase_cb cb, void* ctx,
                    hipStream_t st) {
-  int snt = sep_threads(S);
   if (cb) cb(ctx, 4, 1, st);
   const size_t tri = (size_t)S.mI * (S.mI + 1) / 2;
   hipLaunchKernelGGL(k_l0_fwd<T>, dim3((unsigned)tb.n_elem), dim3(64), sizeof(double) * (tri + S.mI),
                      st, S, tb, ws, rhs);
-  size_t clds = sizeof(double) * (S.ns * S.ns + S.ns);
+  const size_t clds = sep_solve_lds(S);
+  const int snt = sep_solve_threads(S);
   if (tb.L >= 1 && hp.lvl[1] > 0)
     hipLaunchKernelGGL(k_crf_first<T>, dim3(hp.lvl[1]), dim3(snt), clds, st, S, tb, ws, rhs);
   for (int l = 1; l < tb.L; ++l)
     if (hp.st[l] > 0)
       hipLaunchKernelGGL(k_crf_step<T>, dim3(hp.st[l]), dim3(snt), clds, st, S, tb, ws, rhs, l);
-  size_t blds = sizeof(double) * (S.ns * S.ns + S.ns + S.np + S.np * S.np + 1024);
-  hipLaunchKernelGGL(k_border_solve<T>, dim3(tb.n_inst), dim3(1024), blds, st, S, tb, ws, rhs,
-                     rthp, dx);
+  hipLaunchKernelGGL(k_thpart, dim3(ws.nchunk, tb.n_inst), dim3(64), 0, st, S, tb, ws, ws.cB,
+                     ws.cBsep, rthp, ws.thv);
+  hipLaunchKernelGGL(k_border_solve<T>, dim3(tb.n_inst), dim3(1024), border_solve_lds(S), st, S,
+                     tb, ws, rhs, dx);
   for (int l = tb.L; l >= 1; --l) {
     int n = hp.lvl[l];
     if (n > 0) hipLaunchKernelGGL(k_cr_bwd<T>, dim3(n), dim3(snt), clds, st, S, tb, ws, l);
@@ -1104,6 +1273,16 @@ int kkt_prepare_attrs(const Shape& S) {
   int rc = 0;
   rc |= set_lds((const void*)k_assemble<double>, l64 > r ? l64 : r, "k_assemble<double>");
   rc |= set_lds((const void*)k_assemble<float>, l32 > r ? l32 : r, "k_assemble<float>");
+  const size_t c = sep_solve_lds(S);
+  rc |= set_lds((const void*)k_crf_first<double>, c, "k_crf_first<double>");
+  rc |= set_lds((const void*)k_crf_first<float>, c, "k_crf_first<float>");
+  rc |= set_lds((const void*)k_crf_step<double>, c, "k_crf_step<double>");
+  rc |= set_lds((const void*)k_crf_step<float>, c, "k_crf_step<float>");
+  rc |= set_lds((const void*)k_cr_bwd<double>, c, "k_cr_bwd<double>");
+  rc |= set_lds((const void*)k_cr_bwd<float>, c, "k_cr_bwd<float>");
+  const size_t bl = border_solve_lds(S);
+  rc |= set_lds((const void*)k_border_solve<double>, bl, "k_border_solve<double>");
+  rc |= set_lds((const void*)k_border_solve<float>, bl, "k_border_solve<float>");
   return rc;
 }
 }  // namespace cl

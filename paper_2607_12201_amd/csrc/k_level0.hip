@@ -123,16 +123,23 @@ const Variant* pick(int ts, int rows) {
 
 size_t level0r_lds_bytes(const Shape& S) {
   const size_t ns = S.ns, np = S.np, jl = (size_t)S.K * S.nr;
-  size_t nd = 8 * (size_t)S.R + 8 + S.b + 7 * jl + ns + 3 * ns * ns + 3 * ns * np + np + np * np +
-              S.lsp + (size_t)S.mmax * (S.K + 1);
+  size_t nd = 8 * (size_t)S.R + 8 + S.b + (CL_KMAX + 1) * (CL_KMAX + 1) + 1 + 7 * jl + ns +
+              3 * ns * ns + 3 * ns * np + np + np * np + S.lsp + (size_t)S.mmax * (S.K + 1);
   size_t ni = 3 * (size_t)S.nr + 2 * (ns + 1) + (np + 1) + S.lsp + 2 * (size_t)S.lrq + S.lpc +
-              S.mmax + S.R;
+              S.mmax + S.R + 1;
   return sizeof(double) * nd + sizeof(int) * ni;
 }
 
 bool level0r_supported(const Shape& S) { return S.R <= 160 && 3 * S.ns + S.np <= 160; }
 
 int chain_rows(const Shape& S, int which) { return which == 2 ? S.ns + S.np : 3 * S.ns + S.np; }
+
+// Chain kernels: two R x 4 panel buffers, flags, the staged separator columns (R x ns) and a
+// dummy slot.
+size_t chain_lds_bytes(const Shape& S, int which) {
+  const size_t Rl = chain_rows(S, which);
+  return sizeof(double) * (8 * Rl + 8 + Rl * S.ns + 1);
+}
 
 int tile_rows(const Shape& S, int which) { return which == 0 ? S.R : chain_rows(S, which); }
 
@@ -172,16 +179,16 @@ int launch_level0(const Shape& S, const Tab& tb, const Ws& ws, int prec, bool fu
   return 0;
 }
 
+// Dynamic LDS above 64 KB needs the kernel attribute; it is set on every grid that the element
+// or chain kernels may use for this shape.
 int level0_prepare_attrs(const Shape& S) {
-  const size_t by = level0r_lds_bytes(S);
+  const size_t by = std::max(level0r_lds_bytes(S), std::max(chain_lds_bytes(S, 1), chain_lds_bytes(S, 2)));
   if (by <= 64 * 1024) return 0;
-  bool any = false;
-  for (int t : {8, 16, 20, 24})
-    if (const Variant* v = find_variant(t, S.R)) {
-      if (v->attrs(by)) return -1;
-      any = true;
-    }
-  return any ? 0 : -1;
+  for (int rows : {S.R, chain_rows(S, 1), chain_rows(S, 2)})
+    for (int t : {8, 16, 20, 24})
+      if (const Variant* v = find_variant(t, rows))
+        if (v->attrs(by)) return -1;
+  return 0;
 }
 
 // mode: 0 first chain level, 1 chain step `level`, 2 border; grid = work items.
@@ -195,7 +202,7 @@ int launch_chain(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode
     return 0;
   }
   const int Rl = chain_rows(S, mode == 2 ? 2 : 1);
-  const size_t lds = sizeof(double) * (8 * (size_t)Rl + 8);
+  const size_t lds = chain_lds_bytes(S, mode == 2 ? 2 : 1);
   const Variant* v = pick(ts == 1 ? 0 : ts, Rl);
   if (!v) return -1;
   v->chain(S, tb, ws, prec, mode, level, grid, lds, st);

@@ -12,6 +12,8 @@ void launch_level0_16_7(const Shape& S, const Tab& tb, const Ws& ws, int prec, i
 int attrs_level0_16_7(size_t bytes) {
   if (hipFuncSetAttribute((const void*)k_level0r<double, 16, 7>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
   if (hipFuncSetAttribute((const void*)k_level0r<float, 16, 7>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_chain<double, 16, 7>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_chain<float, 16, 7>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
   return 0;
 }
 void launch_chain_16_7(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level, unsigned grid, size_t lds, hipStream_t st) {
@@ -25,6 +27,8 @@ void launch_level0_16_8(const Shape& S, const Tab& tb, const Ws& ws, int prec, i
 int attrs_level0_16_8(size_t bytes) {
   if (hipFuncSetAttribute((const void*)k_level0r<double, 16, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
   if (hipFuncSetAttribute((const void*)k_level0r<float, 16, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_chain<double, 16, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_chain<float, 16, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
   return 0;
 }
 void launch_chain_16_8(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level, unsigned grid, size_t lds, hipStream_t st) {

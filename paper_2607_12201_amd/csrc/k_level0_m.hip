@@ -12,6 +12,8 @@ void launch_level0_16_3(const Shape& S, const Tab& tb, const Ws& ws, int prec, i
 int attrs_level0_16_3(size_t bytes) {
   if (hipFuncSetAttribute((const void*)k_level0r<double, 16, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
   if (hipFuncSetAttribute((const void*)k_level0r<float, 16, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_chain<double, 16, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_chain<float, 16, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
   return 0;
 }
 void launch_chain_16_3(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level, unsigned grid, size_t lds, hipStream_t st) {
@@ -25,6 +27,8 @@ void launch_level0_16_4(const Shape& S, const Tab& tb, const Ws& ws, int prec, i
 int attrs_level0_16_4(size_t bytes) {
   if (hipFuncSetAttribute((const void*)k_level0r<double, 16, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
   if (hipFuncSetAttribute((const void*)k_level0r<float, 16, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_chain<double, 16, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_chain<float, 16, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
   return 0;
 }
 void launch_chain_16_4(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level, unsigned grid, size_t lds, hipStream_t st) {
@@ -38,6 +42,8 @@ void launch_level0_16_5(const Shape& S, const Tab& tb, const Ws& ws, int prec, i
 int attrs_level0_16_5(size_t bytes) {
   if (hipFuncSetAttribute((const void*)k_level0r<double, 16, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
   if (hipFuncSetAttribute((const void*)k_level0r<float, 16, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_chain<double, 16, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_chain<float, 16, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
   return 0;
 }
 void launch_chain_16_5(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level, unsigned grid, size_t lds, hipStream_t st) {
@@ -51,6 +57,8 @@ void launch_level0_16_6(const Shape& S, const Tab& tb, const Ws& ws, int prec, i
 int attrs_level0_16_6(size_t bytes) {
   if (hipFuncSetAttribute((const void*)k_level0r<double, 16, 6>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
   if (hipFuncSetAttribute((const void*)k_level0r<float, 16, 6>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_chain<double, 16, 6>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_chain<float, 16, 6>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
   return 0;
 }
 void launch_chain_16_6(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level, unsigned grid, size_t lds, hipStream_t st) {

@@ -12,6 +12,8 @@ void launch_level0_8_1(const Shape& S, const Tab& tb, const Ws& ws, int prec, in
 int attrs_level0_8_1(size_t bytes) {
   if (hipFuncSetAttribute((const void*)k_level0r<double, 8, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
   if (hipFuncSetAttribute((const void*)k_level0r<float, 8, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_chain<double, 8, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_chain<float, 8, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
   return 0;
 }
 void launch_chain_8_1(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level, unsigned grid, size_t lds, hipStream_t st) {
@@ -25,6 +27,8 @@ void launch_level0_8_2(const Shape& S, const Tab& tb, const Ws& ws, int prec, in
 int attrs_level0_8_2(size_t bytes) {
   if (hipFuncSetAttribute((const void*)k_level0r<double, 8, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
   if (hipFuncSetAttribute((const void*)k_level0r<float, 8, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_chain<double, 8, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_chain<float, 8, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
   return 0;
 }
 void launch_chain_8_2(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level, unsigned grid, size_t lds, hipStream_t st) {
@@ -38,6 +42,8 @@ void launch_level0_8_3(const Shape& S, const Tab& tb, const Ws& ws, int prec, in
 int attrs_level0_8_3(size_t bytes) {
   if (hipFuncSetAttribute((const void*)k_level0r<double, 8, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
   if (hipFuncSetAttribute((const void*)k_level0r<float, 8, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_chain<double, 8, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_chain<float, 8, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
   return 0;
 }
 void launch_chain_8_3(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level, unsigned grid, size_t lds, hipStream_t st) {
@@ -51,6 +57,8 @@ void launch_level0_8_4(const Shape& S, const Tab& tb, const Ws& ws, int prec, in
 int attrs_level0_8_4(size_t bytes) {
   if (hipFuncSetAttribute((const void*)k_level0r<double, 8, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
   if (hipFuncSetAttribute((const void*)k_level0r<float, 8, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_chain<double, 8, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_chain<float, 8, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
   return 0;
 }
 void launch_chain_8_4(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level, unsigned grid, size_t lds, hipStream_t st) {

@@ -12,6 +12,8 @@ void launch_level0_20_5(const Shape& S, const Tab& tb, const Ws& ws, int prec, i
 int attrs_level0_20_5(size_t bytes) {
   if (hipFuncSetAttribute((const void*)k_level0r<double, 20, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
   if (hipFuncSetAttribute((const void*)k_level0r<float, 20, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_chain<double, 20, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_chain<float, 20, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
   return 0;
 }
 void launch_chain_20_5(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level, unsigned grid, size_t lds, hipStream_t st) {
@@ -25,6 +27,8 @@ void launch_level0_20_6(const Shape& S, const Tab& tb, const Ws& ws, int prec, i
 int attrs_level0_20_6(size_t bytes) {
   if (hipFuncSetAttribute((const void*)k_level0r<double, 20, 6>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
   if (hipFuncSetAttribute((const void*)k_level0r<float, 20, 6>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_chain<double, 20, 6>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_chain<float, 20, 6>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
   return 0;
 }
 void launch_chain_20_6(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level, unsigned grid, size_t lds, hipStream_t st) {
@@ -38,6 +42,8 @@ void launch_level0_20_7(const Shape& S, const Tab& tb, const Ws& ws, int prec, i
 int attrs_level0_20_7(size_t bytes) {
   if (hipFuncSetAttribute((const void*)k_level0r<double, 20, 7>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
   if (hipFuncSetAttribute((const void*)k_level0r<float, 20, 7>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_chain<double, 20, 7>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_chain<float, 20, 7>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
   return 0;
 }
 void launch_chain_20_7(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level, unsigned grid, size_t lds, hipStream_t st) {
@@ -51,6 +57,8 @@ void launch_level0_20_8(const Shape& S, const Tab& tb, const Ws& ws, int prec, i
 int attrs_level0_20_8(size_t bytes) {
   if (hipFuncSetAttribute((const void*)k_level0r<double, 20, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
   if (hipFuncSetAttribute((const void*)k_level0r<float, 20, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_chain<double, 20, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_chain<float, 20, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
   return 0;
 }
 void launch_chain_20_8(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level, unsigned grid, size_t lds, hipStream_t st) {

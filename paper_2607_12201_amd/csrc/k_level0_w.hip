@@ -12,6 +12,8 @@ void launch_level0_24_4(const Shape& S, const Tab& tb, const Ws& ws, int prec, i
 int attrs_level0_24_4(size_t bytes) {
   if (hipFuncSetAttribute((const void*)k_level0r<double, 24, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
   if (hipFuncSetAttribute((const void*)k_level0r<float, 24, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_chain<double, 24, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_chain<float, 24, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
   return 0;
 }
 void launch_chain_24_4(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level, unsigned grid, size_t lds, hipStream_t st) {
@@ -25,6 +27,8 @@ void launch_level0_24_5(const Shape& S, const Tab& tb, const Ws& ws, int prec, i
 int attrs_level0_24_5(size_t bytes) {
   if (hipFuncSetAttribute((const void*)k_level0r<double, 24, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
   if (hipFuncSetAttribute((const void*)k_level0r<float, 24, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_chain<double, 24, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_chain<float, 24, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
   return 0;
 }
 void launch_chain_24_5(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level, unsigned grid, size_t lds, hipStream_t st) {

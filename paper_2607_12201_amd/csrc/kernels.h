@@ -17,10 +17,8 @@ inline int elem_threads(const Shape& S) {
   int w = S.b + S.np;
   return w <= 32 ? 64 : (w <= 96 ? 128 : 256);
 }
-inline int sep_threads(const Shape& S) {
-  int w = S.ns > S.np ? S.ns : S.np;
-  return w <= 64 ? 64 : 128;
-}
+size_t sep_solve_lds(const Shape& S);      // separator-chain solve kernels
+size_t border_solve_lds(const Shape& S);   // border solve kernel
 
 int launch_eval(const Shape& S, const Tab& tb, const Ws& ws, const double* x, double* obj,
                 double* g, hipStream_t st);
@@ -33,6 +31,7 @@ typedef void (*phase_cb)(void* ctx, int phase, int begin, hipStream_t st);
 
 size_t level0_lds_bytes(const Shape& S, int prec);        // kkt_assemble's LDS blocks
 size_t level0r_lds_bytes(const Shape& S);
+size_t chain_lds_bytes(const Shape& S, int which);   // which: 1 chain levels, 2 border
 bool level0r_supported(const Shape& S);
 int launch_level0(const Shape& S, const Tab& tb, const Ws& ws, int prec, bool fused, int ts,
                   hipStream_t st);

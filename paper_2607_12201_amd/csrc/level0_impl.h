@@ -24,34 +24,68 @@ struct LTab {
   int nmeas;
 };
 
-__device__ inline void stage_tables(const Shape& S, const Tab& tb, int inst, int64_t e, LTab& L) {
-  const int ns = S.ns, np = S.np, nr = S.nr, K = S.K;
-  for (int t = tid(); t < 2 * nr; t += nthr()) L.react[t] = tb.react[inst * nr * 2 + t];
-  for (int t = tid(); t < nr; t += nthr()) L.param[t] = tb.param[inst * nr + t];
-  const int sp0 = tb.sp_ptr[inst * (ns + 1)], rq0 = tb.rq_ptr[inst * (ns + 1)];
-  const int pc0 = tb.pc_ptr[inst * (np + 1)];
-  for (int t = tid(); t <= ns; t += nthr()) {
-    L.sp_ptr[t] = tb.sp_ptr[inst * (ns + 1) + t] - sp0;
-    L.rq_ptr[t] = tb.rq_ptr[inst * (ns + 1) + t] - rq0;
+// Stage the element's inputs in LDS: Ds of its rows (d0), the reaction partials (jv, hv), the
+// instance tables, its measurements, the collocation weights (La, row j = a[j][.]) and the
+// row -> node map.  One flat pass per nthr entries: every thread loads entry t of each array
+// (index 0 past an array's end, a valid fallback address for an empty array), and only then
+// stores, to a dummy slot past the end, so a pass costs one memory latency.
+__device__ inline void stage_element(const Shape& S, const Tab& tb, const Ws& ws, int inst,
+                                     int64_t e, int i, LTab& L, double* d0, double* jv, double* hv,
+                                     double* La, double* ddum, int* idum) {
+  const int ns = S.ns, np = S.np, nr = S.nr, K = S.K, b = S.b, jl = K * nr;
+  constexpr int NA = (CL_KMAX + 1) * (CL_KMAX + 1);
+  const int* spp = tb.sp_ptr + inst * (ns + 1);
+  const int* rqp = tb.rq_ptr + inst * (ns + 1);
+  const int* pcp = tb.pc_ptr + inst * (np + 1);
+  const int sp0 = spp[0], rq0 = rqp[0], pc0 = pcp[0];
+  const int nsp = spp[ns] - sp0, nrq = rqp[ns] - rq0, npc = pcp[np] - pc0;
+  const int m0 = tb.elem_mptr[e], nm = tb.elem_mptr[e + 1] - m0, nmw = nm * (K + 1);
+  L.nmeas = nm;
+  const int64_t gi = tb.inst_g[inst] + (int64_t)i * b;
+  const int* ifb = tb.elem_inst + e;       // valid fallbacks for empty lists
+  const double* dfb = tb.elem_h + e;
+  const int* spr = nsp > 0 ? tb.sp_r + sp0 : ifb;
+  const double* spn = nsp > 0 ? tb.sp_nu + sp0 : dfb;
+  const int* rqr = nrq > 0 ? tb.rq_r + rq0 : ifb;
+  const int* rqt = nrq > 0 ? tb.rq_t + rq0 : ifb;
+  const int* pcr = npc > 0 ? tb.pc_r + pc0 : ifb;
+  const int* msp = nm > 0 ? tb.meas_sp + m0 : ifb;
+  const double* mw = nm > 0 ? tb.meas_w + (int64_t)m0 * (K + 1) : dfb;
+  const double* Ds = ws.Ds + gi;
+  const double* jac = ws.jac + e * 3 * jl;
+  const double* hes = ws.hess + e * 4 * jl;
+  const int* rea = tb.react + inst * nr * 2;
+  const int* par = tb.param + inst * nr;
+  int nmax = b;
+  for (int n : {4 * jl, 2 * nr, ns + 1, np + 1, nsp, nrq, npc, nmw, S.R, NA}) nmax = n > nmax ? n : nmax;
+  for (int t0 = 0; t0 < nmax; t0 += nthr()) {
+    const int t = t0 + tid();
+    auto ix = [t](int n) { return t < n ? t : 0; };
+    const double xd = Ds[ix(b)], xj = jac[ix(3 * jl)], xh = hes[ix(4 * jl)], xn = spn[ix(nsp)],
+                 xw = mw[ix(nmw)];
+    const int xre = rea[ix(2 * nr)], xpa = par[ix(nr)], xsp = spp[ix(ns + 1)], xrq = rqp[ix(ns + 1)],
+              xpc = pcp[ix(np + 1)], xsr = spr[ix(nsp)], xqr = rqr[ix(nrq)], xqt = rqt[ix(nrq)],
+              xpr = pcr[ix(npc)], xms = msp[ix(nm)];
+    const int ta = ix(NA);
+    const double xa = S.a[ta / (CL_KMAX + 1)][ta % (CL_KMAX + 1)];
+    *(t < b ? d0 + t : ddum) = xd;
+    *(t < 3 * jl ? jv + t : ddum) = xj;
+    *(t < 4 * jl ? hv + t : ddum) = xh;
+    *(t < nsp ? L.sp_nu + t : ddum) = xn;
+    *(t < nmw ? L.mw + t : ddum) = xw;
+    *(t < NA ? La + t : ddum) = xa;
+    *(t < 2 * nr ? L.react + t : idum) = xre;
+    *(t < nr ? L.param + t : idum) = xpa;
+    *(t <= ns ? L.sp_ptr + t : idum) = xsp - sp0;
+    *(t <= ns ? L.rq_ptr + t : idum) = xrq - rq0;
+    *(t <= np ? L.pc_ptr + t : idum) = xpc - pc0;
+    *(t < nsp ? L.sp_r + t : idum) = xsr;
+    *(t < nrq ? L.rq_r + t : idum) = xqr;
+    *(t < nrq ? L.rq_t + t : idum) = xqt;
+    *(t < npc ? L.pc_r + t : idum) = xpr;
+    *(t < nm ? L.msp + t : idum) = xms;
+    *(t < S.R ? L.jdiv + t : idum) = t / ns;
   }
-  for (int t = tid(); t <= np; t += nthr()) L.pc_ptr[t] = tb.pc_ptr[inst * (np + 1) + t] - pc0;
-  const int nsp = tb.sp_ptr[inst * (ns + 1) + ns] - sp0;
-  const int nrq = tb.rq_ptr[inst * (ns + 1) + ns] - rq0;
-  const int npc = tb.pc_ptr[inst * (np + 1) + np] - pc0;
-  for (int t = tid(); t < nsp; t += nthr()) {
-    L.sp_r[t] = tb.sp_r[sp0 + t];
-    L.sp_nu[t] = tb.sp_nu[sp0 + t];
-  }
-  for (int t = tid(); t < nrq; t += nthr()) {
-    L.rq_r[t] = tb.rq_r[rq0 + t];
-    L.rq_t[t] = tb.rq_t[rq0 + t];
-  }
-  for (int t = tid(); t < npc; t += nthr()) L.pc_r[t] = tb.pc_r[pc0 + t];
-  const int m0 = tb.elem_mptr[e], m1 = tb.elem_mptr[e + 1];
-  L.nmeas = m1 - m0;
-  for (int t = tid(); t < m1 - m0; t += nthr()) L.msp[t] = tb.meas_sp[m0 + t];
-  for (int t = tid(); t < (m1 - m0) * (K + 1); t += nthr()) L.mw[t] = tb.meas_w[(int64_t)m0 * (K + 1) + t];
-  for (int t = tid(); t < S.R; t += nthr()) L.jdiv[t] = t / ns;
 }
 
 // node-0 rows (initial condition / continuity), measurement Hessian, dw on z; P couplings.
@@ -85,12 +119,12 @@ struct NodeTab {
   double *d, *F, *Fth, *Wzz, *Wzt, *Wtt, *Q1, *Q2, *Q3;
 };
 
-__device__ inline double node_entry(const Shape& S, const LTab& L, int k, double h,
+__device__ inline double node_entry(const Shape& S, const LTab& L, const double* La, int k, double h,
                                     const NodeTab& nt, int r, int q) {
   const int ns = S.ns, np = S.np, b = S.b;
   if (r < b) {
     const int j1 = L.jdiv[r], s1 = r - j1 * ns, j2 = L.jdiv[q], s2 = q - j2 * ns;
-    double a1 = S.a[j1][k], a2 = S.a[j2][k];
+    const double a1 = La[j1 * (CL_KMAX + 1) + k], a2 = La[j2 * (CL_KMAX + 1) + k];
     double v = 0.0;
     if (s1 == s2) v += nt.d[s1] * a1 * a2;
     if (j2 == k) v -= a1 * (h * nt.d[s1] * nt.F[s1 * ns + s2]);
@@ -100,7 +134,7 @@ __device__ inline double node_entry(const Shape& S, const LTab& L, int k, double
   }
   if (q < b) {
     const int c = r - b, j1 = L.jdiv[q], s1 = q - j1 * ns;
-    double v = -S.a[j1][k] * (h * nt.d[s1] * nt.Fth[s1 * np + c]);
+    double v = -La[j1 * (CL_KMAX + 1) + k] * (h * nt.d[s1] * nt.Fth[s1 * np + c]);
     if (j1 == k) v += nt.Q2[s1 * np + c];
     return v;
   }
@@ -254,7 +288,8 @@ __global__ void __launch_bounds__(TS* TS) k_level0r(Shape S, Tab tb, Ws ws, int 
   double* pbuf = lds;                 // 2 R 4
   double* misc = pbuf + 8 * R;        // 8
   double* d0 = misc + 8;              // b (Ds of the element's rows)
-  double* jv = d0 + b;                // 3 K nr
+  double* La = d0 + b;                // (KMAX + 1)^2 collocation weights, then a dummy slot
+  double* jv = La + (CL_KMAX + 1) * (CL_KMAX + 1) + 1;   // 3 K nr
   double* hv = jv + 3 * jl;           // 4 K nr
   NodeTab nt;
   nt.d = hv + 4 * jl;
@@ -281,15 +316,12 @@ __global__ void __launch_bounds__(TS* TS) k_level0r(Shape S, Tab tb, Ws ws, int 
   L.pc_r = L.rq_t + S.lrq;
   L.msp = L.pc_r + S.lpc;
   L.jdiv = L.msp + S.mmax;
+  int* idum = L.jdiv + R;
   double av[NBLK];
 
   if (fused) {
-    const int64_t gi = tb.inst_g[inst] + (int64_t)i * b;
     const double h = tb.elem_h[e], dw = ws.dw[inst];
-    for (int t = tid(); t < b; t += nthr()) d0[t] = ws.Ds[gi + t];
-    for (int t = tid(); t < 3 * jl; t += nthr()) jv[t] = ws.jac[e * 3 * jl + t];
-    for (int t = tid(); t < 4 * jl; t += nthr()) hv[t] = ws.hess[e * 4 * jl + t];
-    stage_tables(S, tb, inst, e, L);
+    stage_element(S, tb, ws, inst, e, i, L, d0, jv, hv, La, La + (CL_KMAX + 1) * (CL_KMAX + 1), idum);
     __syncthreads();
 #pragma unroll
     for (int I = 0; I < NB; ++I)
@@ -307,7 +339,7 @@ __global__ void __launch_bounds__(TS* TS) k_level0r(Shape S, Tab tb, Ws ws, int 
 #pragma unroll
         for (int J = 0; J <= I; ++J) {
           const int r = I * TS + ty, q = J * TS + tx;
-          if (r < bp && q <= r) av[I * (I + 1) / 2 + J] += node_entry(S, L, k, h, nt, r, q);
+          if (r < bp && q <= r) av[I * (I + 1) / 2 + J] += node_entry(S, L, La, k, h, nt, r, q);
         }
     }
     if (sizeof(T) == 4) {  // FP32 factors: keep the assembled theta-theta block in FP64
