@@ -346,7 +346,7 @@ __global__ void __launch_bounds__(TS* TS) k_chain(Shape S, Tab tb, Ws ws, int mo
   const int th0 = (mode == CH_BORDER) ? ns : 3 * ns;   // first theta row
   const int ty = threadIdx.x / TS, tx = threadIdx.x % TS;
   double* pbuf = lds;
-  double* misc = pbuf + 8 * Rl;
+  double* misc = pbuf + elim_lds_doubles(Rl);
   const bool border = mode == CH_BORDER;
   double* X = misc + 8;                                 // Rl x ns separator columns + 1
   chain_stage<T>(S, ws, ci, border, Rl, th0, X);

@@ -123,7 +123,7 @@ const Variant* pick(int ts, int rows) {
 
 size_t level0r_lds_bytes(const Shape& S) {
   const size_t ns = S.ns, np = S.np, jl = (size_t)S.K * S.nr;
-  size_t nd = 8 * (size_t)S.R + 8 + S.b + (CL_KMAX + 1) * (CL_KMAX + 1) + 1 + 7 * jl + ns +
+  size_t nd = (size_t)elim_lds_doubles(S.R) + 8 + S.b + (CL_KMAX + 1) * (CL_KMAX + 1) + 1 + 7 * jl + ns +
               3 * ns * ns + 3 * ns * np + np + np * np + S.lsp + (size_t)S.mmax * (S.K + 1);
   size_t ni = 3 * (size_t)S.nr + 2 * (ns + 1) + (np + 1) + S.lsp + 2 * (size_t)S.lrq + S.lpc +
               S.mmax + S.R + 1;
@@ -134,11 +134,11 @@ bool level0r_supported(const Shape& S) { return S.R <= 160 && 3 * S.ns + S.np <=
 
 int chain_rows(const Shape& S, int which) { return which == 2 ? S.ns + S.np : 3 * S.ns + S.np; }
 
-// Chain kernels: two R x 4 panel buffers, flags, the staged separator columns (R x ns) and a
+// Chain kernels: the elimination buffers, flags, the staged separator columns (R x ns) and a
 // dummy slot.
 size_t chain_lds_bytes(const Shape& S, int which) {
   const size_t Rl = chain_rows(S, which);
-  return sizeof(double) * (8 * Rl + 8 + Rl * S.ns + 1);
+  return sizeof(double) * (elim_lds_doubles((int)Rl) + 8 + Rl * S.ns + 1);
 }
 
 int tile_rows(const Shape& S, int which) { return which == 0 ? S.R : chain_rows(S, which); }

@@ -285,8 +285,8 @@ __global__ void __launch_bounds__(TS* TS) k_level0r(Shape S, Tab tb, Ws ws, int 
   const int ns = S.ns, np = S.np, b = S.b, R = S.R, bp = S.b + S.np;
   const int ty = threadIdx.x / TS, tx = threadIdx.x % TS;
   const int jl = S.K * S.nr;
-  double* pbuf = lds;                 // 2 R 4
-  double* misc = pbuf + 8 * R;        // 8
+  double* pbuf = lds;                 // elimination buffers
+  double* misc = pbuf + elim_lds_doubles(R);   // 8
   double* d0 = misc + 8;              // b (Ds of the element's rows)
   double* La = d0 + b;                // (KMAX + 1)^2 collocation weights, then a dummy slot
   double* jv = La + (CL_KMAX + 1) * (CL_KMAX + 1) + 1;   // 3 K nr

@@ -10,13 +10,31 @@
 
 namespace cl {
 
+// Value of x held by lane `lane` of the wave (lane uniform): two scalar lane reads, far cheaper
+// than an LDS permute.
+__device__ inline double lane_value(double x, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// LDS of eliminate_regs for R rows: two R x 4 panel buffers and the zero-padded copy
+// (TS * NB <= R + 23 rows by 4).
+__host__ __device__ constexpr int elim_lds_doubles(int R) { return 8 * R + 4 * (R + 24); }
+
 // Right-looking elimination of the first mI columns on register-resident entries, in
 // panels of up to 4 columns: the owners copy the panel (rows >= c0) into LDS, one wave factors
 // it in registers, the owners take the factored columns back and every thread applies the rank-w
-// update to its entries right of the panel.  pbuf: two R x 4 buffers (alternating panels).
+// update to its entries right of the panel.  pbuf: two R x 4 buffers (alternating panels,
+// column-major), then Z: the factored panel again over rows J*TS .. NB*TS with zeros in the
+// rows above the trailing block and below R, so the update reads its multipliers without masks
+// (one buffer suffices: it is written after the barrier that every thread reaches only once its
+// previous update is done).
 template <typename T, int TS, int NB>
 __device__ inline bool eliminate_regs(T* acc, int mI, int R, int ty, int tx, double* pbuf,
                                       double* misc) {
+  constexpr int RZ = TS * NB;
+  double* Z = pbuf + 8 * R;
   int buf = 0;
 #pragma unroll
   for (int J = 0; J < NB; ++J) {
@@ -32,53 +50,63 @@ __device__ inline bool eliminate_regs(T* acc, int mI, int R, int ty, int tx, dou
 #pragma unroll
         for (int I = J; I < NB; ++I) {
           const int r = I * TS + ty;
-          if (r >= q && r < R) P[r * 4 + cl_own] = (double)acc[I * (I + 1) / 2 + J];
+          if (r >= q && r < R) P[cl_own * R + r] = (double)acc[I * (I + 1) / 2 + J];
         }
       }
       __syncthreads();
       if (tid() < 64) {
         // wave 0 factors the panel in registers: lane t holds panel rows c0 + t + 64 m
-        // (R - c0 <= 192); the pivot row values come from their owner lanes by shuffles
+        // (R - c0 <= 192); the pivot row values come from their owner lanes by lane reads.
+        // Per-row choices are selects, not branches; row groups past R are skipped whole.
         const int lane = tid();
         double p[3][4];
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
           const int r = c0 + lane + 64 * m;
+          const int rr = r < R ? r : 0;
 #pragma unroll
-          for (int cl = 0; cl < 4; ++cl) p[m][cl] = (r < R && cl < w) ? P[r * 4 + cl] : 0.0;
+          for (int cl = 0; cl < 4; ++cl) p[m][cl] = pick(r < R && cl < w, P[cl * R + rr], 0.0);
         }
         bool good = true;
 #pragma unroll
         for (int cl = 0; cl < 4; ++cl) {
           if (cl < w && good) {
-            const double piv = __shfl(p[0][cl], cl);
+            // pivot and 1/sqrt(pivot) once per column on the wave-uniform value
+            const double piv = lane_value(p[0][cl], cl);
             good = piv > 0.0 && isfinite(piv);
-            const double sq = good ? sqrt(piv) : 1.0;
-            const double inv = 1.0 / sq;
+            const double inv = good ? rsqrt(piv) : 1.0;
+            const double sq = good ? piv * inv : 1.0;
 #pragma unroll
             for (int m = 0; m < 3; ++m) {
               const int rl = lane + 64 * m;
-              if (rl == cl) p[m][cl] = sq;
-              else if (rl > cl) p[m][cl] *= inv;
+              p[m][cl] = pick(rl == cl, sq, pick(rl > cl, p[m][cl] * inv, p[m][cl]));
             }
 #pragma unroll
             for (int cl2 = cl + 1; cl2 < 4; ++cl2) {
               if (cl2 < w) {
-                const double lc = __shfl(p[0][cl], cl2);
+                const double lc = lane_value(p[0][cl], cl2);
 #pragma unroll
                 for (int m = 0; m < 3; ++m)
-                  if (lane + 64 * m >= cl2) p[m][cl2] -= p[m][cl] * lc;
+                  p[m][cl2] = pick(lane + 64 * m >= cl2, p[m][cl2] - p[m][cl] * lc, p[m][cl2]);
               }
             }
           }
         }
+        double* dum = misc + 7;
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
+          if (c0 + 64 * m >= RZ) break;
           const int r = c0 + lane + 64 * m;
 #pragma unroll
-          for (int cl = 0; cl < 4; ++cl)
-            if (r < R && cl < w) P[r * 4 + cl] = p[m][cl];
+          for (int cl = 0; cl < 4; ++cl) {
+            *(r < R && cl < w ? P + cl * R + r : dum) = p[m][cl];
+            *(r < RZ ? Z + cl * RZ + r : dum) = pick(r >= c0 + w && r < R && cl < w, p[m][cl], 0.0);
+          }
         }
+        // rows of earlier panels of this block column
+        const int rz = J * TS + lane;
+#pragma unroll
+        for (int cl = 0; cl < 4; ++cl) *(rz < c0 ? Z + cl * RZ + rz : dum) = 0.0;
         if (lane == 0) misc[0] = good ? 1.0 : 0.0;
       }
       __syncthreads();
@@ -88,17 +116,15 @@ __device__ inline bool eliminate_regs(T* acc, int mI, int R, int ty, int tx, dou
 #pragma unroll
         for (int I = J; I < NB; ++I) {
           const int r = I * TS + ty;
-          if (r >= q && r < R) acc[I * (I + 1) / 2 + J] = (T)P[r * 4 + cl_own];
+          if (r >= q && r < R) acc[I * (I + 1) / 2 + J] = (T)P[cl_own * R + r];
         }
       }
-      const int cend = c0 + w;
       for (int cl = 0; cl < w; ++cl) {
         T cr[NB], cq[NB];
 #pragma unroll
         for (int I = J; I < NB; ++I) {
-          const int r = I * TS + ty, q = I * TS + tx;
-          cr[I] = (r >= cend && r < R) ? (T)P[r * 4 + cl] : (T)0;
-          cq[I] = (q >= cend && q < R) ? (T)P[q * 4 + cl] : (T)0;
+          cr[I] = (T)Z[cl * RZ + I * TS + ty];
+          cq[I] = (T)Z[cl * RZ + I * TS + tx];
         }
 #pragma unroll
         for (int I = J; I < NB; ++I)
