@@ -124,9 +124,10 @@ const Variant* pick(int ts, int rows) {
 size_t level0r_lds_bytes(const Shape& S) {
   const size_t ns = S.ns, np = S.np, jl = (size_t)S.K * S.nr;
   size_t nd = (size_t)elim_lds_doubles(S.R) + 8 + S.b + (CL_KMAX + 1) * (CL_KMAX + 1) + 1 + 7 * jl + ns +
-              3 * ns * ns + 3 * ns * np + np + np * np + S.lsp + (size_t)S.mmax * (S.K + 1);
+              3 * ns * ns + 3 * ns * np + np + np * np + 3 * (size_t)S.lsp + 2 * (size_t)S.lrq +
+              S.lsp + (size_t)S.mmax * (S.K + 1);
   size_t ni = 3 * (size_t)S.nr + 2 * (ns + 1) + (np + 1) + S.lsp + 2 * (size_t)S.lrq + S.lpc +
-              S.mmax + S.R + 1;
+              S.mmax + S.R + 1 + 3 * (size_t)S.lsp + 2 * (size_t)S.lrq;
   return sizeof(double) * nd + sizeof(int) * ni;
 }
 

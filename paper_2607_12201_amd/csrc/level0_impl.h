@@ -117,6 +117,11 @@ __device__ inline double base_entry(const Shape& S, const LTab& L, int i, double
 // Q3 = h^2 Fth^T D Fth + diag(Wtt), each entry of their contribution needs a few lookups.
 struct NodeTab {
   double *d, *F, *Fth, *Wzz, *Wzt, *Wtt, *Q1, *Q2, *Q3;
+  // per list entry of the point: species-reaction entries (slot columns u1, u2 and parameter
+  // column with their values nu * d rate / d .) and reactant-slot entries (partner column and
+  // parameter column with the second-derivative values)
+  double *sv1, *sv2, *svp, *qv, *qvp;
+  int *su1, *su2, *sup, *qu, *qup;
 };
 
 __device__ inline double node_entry(const Shape& S, const LTab& L, const double* La, int k, double h,
@@ -150,51 +155,72 @@ __device__ inline void tri_rc(int t, int& r, int& c) {
 }
 
 // Build the tables of point k from the element's staged derivative values (jv, hv) and Ds.
-// Every table entry is computed by its own thread (gathers over the species' reactions or the
-// species' reactant slots), so all threads take part.
+// First every list entry gets its contributions (one thread each); then each F / Wzz entry
+// sums the entries of its row with selects (no branches, independent loads), in list order;
+// then the products Q, one entry per thread.
 __device__ inline void node_tables(const Shape& S, const LTab& L, int k, double h,
                                    const double* jv, const double* hv, const double* Ds_e,
                                    const NodeTab& nt) {
   const int ns = S.ns, np = S.np, nr = S.nr, nw = ns + np;
+  const int nsp = L.sp_ptr[ns], nrq = L.rq_ptr[ns];
   for (int s = tid(); s < ns; s += nthr()) nt.d[s] = Ds_e[k * ns + s];
   for (int c = tid(); c < np; c += nthr()) {
     double acc = 0.0;
     for (int o = L.pc_ptr[c]; o < L.pc_ptr[c + 1]; ++o) acc += hv[((k - 1) * nr + L.pc_r[o]) * 4 + 3];
     nt.Wtt[c] = acc;
   }
+  for (int o = tid(); o < nsp; o += nthr()) {
+    const int r = L.sp_r[o];
+    const double nu = L.sp_nu[o];
+    const double* jr = jv + ((k - 1) * nr + r) * 3;
+    nt.su1[o] = L.react[2 * r];
+    nt.su2[o] = L.react[2 * r + 1];
+    nt.sup[o] = L.param[r];
+    nt.sv1[o] = nu * jr[0];
+    nt.sv2[o] = nu * jr[1];
+    nt.svp[o] = nu * jr[2];
+  }
+  for (int o = tid(); o < nrq; o += nthr()) {
+    const int r = L.rq_r[o], sl = L.rq_t[o];
+    const double* H = hv + ((k - 1) * nr + r) * 4;
+    nt.qu[o] = L.react[2 * r + (1 - sl)];
+    nt.qup[o] = L.param[r];
+    nt.qv[o] = H[0];
+    nt.qvp[o] = H[1 + sl];
+  }
+  __syncthreads();
   // F | Fth: row s = sum over the reactions of species s of nu_sr times the slot / theta partials
   for (int t = tid(); t < ns * nw; t += nthr()) {
     const int s = t / nw, u = t - s * nw;
+    const bool isz = u < ns;
+    const int uc = u - ns;
     double v = 0.0;
+#pragma unroll 2
     for (int o = L.sp_ptr[s]; o < L.sp_ptr[s + 1]; ++o) {
-      const int r = L.sp_r[o];
-      const double nu = L.sp_nu[o];
-      const double* jr = jv + ((k - 1) * nr + r) * 3;
-      if (u < ns) {
-        if (L.react[2 * r] == u) v += nu * jr[0];
-        if (L.react[2 * r + 1] == u) v += nu * jr[1];
-      } else if (L.param[r] == u - ns) {
-        v += nu * jr[2];
-      }
+      const int u1 = nt.su1[o], u2 = nt.su2[o], up = nt.sup[o];
+      const double v1 = nt.sv1[o], v2 = nt.sv2[o], vp = nt.svp[o];
+      v += pick(isz && u1 == u, v1, 0.0);
+      v += pick(isz && u2 == u, v2, 0.0);
+      v += pick(!isz && up == uc, vp, 0.0);
     }
-    if (u < ns) nt.F[s * ns + u] = v;
-    else nt.Fth[s * np + (u - ns)] = v;
+    if (isz) nt.F[s * ns + u] = v;
+    else nt.Fth[s * np + uc] = v;
   }
   // Wzz | Wzt: row q = the weighted second derivatives of the reactions with q in a slot
   for (int t = tid(); t < ns * nw; t += nthr()) {
     const int q = t / nw, u = t - q * nw;
+    const bool isz = u < ns;
+    const int uc = u - ns;
     double v = 0.0;
+#pragma unroll 2
     for (int o = L.rq_ptr[q]; o < L.rq_ptr[q + 1]; ++o) {
-      const int r = L.rq_r[o], sl = L.rq_t[o];
-      const double* H = hv + ((k - 1) * nr + r) * 4;
-      if (u < ns) {
-        if (L.react[2 * r + (1 - sl)] == u) v += H[0];
-      } else if (L.param[r] == u - ns) {
-        v += H[1 + sl];
-      }
+      const int qu = nt.qu[o], qp = nt.qup[o];
+      const double qv = nt.qv[o], qvp = nt.qvp[o];
+      v += pick(isz && qu == u, qv, 0.0);
+      v += pick(!isz && qp == uc, qvp, 0.0);
     }
-    if (u < ns) nt.Wzz[q * ns + u] = v;
-    else nt.Wzt[q * np + (u - ns)] = v;
+    if (isz) nt.Wzz[q * ns + u] = v;
+    else nt.Wzt[q * np + uc] = v;
   }
   __syncthreads();
   // Q entries: lower triangle of the (ns + np) x (ns + np) product, four partial sums each
@@ -275,8 +301,10 @@ __device__ inline void store_regs(const Shape& S, const Ws& ws, int64_t e, int i
     }
 }
 
+// The 20 x 20 grid (seven waves) is held to four waves per SIMD (at most 128 registers) so two
+// elements share a compute unit.
 template <typename T, int TS, int NB>
-__global__ void __launch_bounds__(TS* TS) k_level0r(Shape S, Tab tb, Ws ws, int fused) {
+__global__ void __launch_bounds__(TS* TS) __attribute__((amdgpu_waves_per_eu(TS == 20 ? 4 : 1))) k_level0r(Shape S, Tab tb, Ws ws, int fused) {
   extern __shared__ double lds[];
   constexpr int NBLK = NB * (NB + 1) / 2;
   const int64_t e = blockIdx.x;
@@ -301,8 +329,13 @@ __global__ void __launch_bounds__(TS* TS) k_level0r(Shape S, Tab tb, Ws ws, int 
   nt.Q1 = nt.Wtt + np;
   nt.Q2 = nt.Q1 + ns * ns;
   nt.Q3 = nt.Q2 + ns * np;
+  nt.sv1 = nt.Q3 + np * np;
+  nt.sv2 = nt.sv1 + S.lsp;
+  nt.svp = nt.sv2 + S.lsp;
+  nt.qv = nt.svp + S.lsp;
+  nt.qvp = nt.qv + S.lrq;
   LTab L;
-  L.sp_nu = nt.Q3 + np * np;
+  L.sp_nu = nt.qvp + S.lrq;
   L.mw = L.sp_nu + S.lsp;
   int* ib = (int*)(L.mw + S.mmax * (S.K + 1));
   L.react = ib;
@@ -317,6 +350,11 @@ __global__ void __launch_bounds__(TS* TS) k_level0r(Shape S, Tab tb, Ws ws, int 
   L.msp = L.pc_r + S.lpc;
   L.jdiv = L.msp + S.mmax;
   int* idum = L.jdiv + R;
+  nt.su1 = idum + 1;
+  nt.su2 = nt.su1 + S.lsp;
+  nt.sup = nt.su2 + S.lsp;
+  nt.qu = nt.sup + S.lsp;
+  nt.qup = nt.qu + S.lrq;
   double av[NBLK];
 
   if (fused) {
