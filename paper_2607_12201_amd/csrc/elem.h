@@ -338,4 +338,14 @@ __device__ inline double block_min(double v, double* red) {
   return r;
 }
 
+// Sum of the chunk partials of parameter c of an instance, in chunk order.
+__device__ inline double thpart_sum(const Ws& ws, const double* part, int inst, int N, int np, int c) {
+  const int nch = (int)cl_ceil_div(N, CL_THCHUNK);
+  const double* p = part + (int64_t)inst * ws.nchunk * np + c;
+  double acc = 0.0;
+#pragma unroll 8
+  for (int ch = 0; ch < nch; ++ch) acc += p[(int64_t)ch * np];
+  return acc;
+}
+
 }  // namespace cl

@@ -774,11 +774,8 @@ __global__ void k_fp32_prep(Shape S, Tab tb, IpmState st, Ws ws) {
   if (skip) return;
   const int N = tb.inst_N[inst], np = S.np;
   const int64_t e0 = tb.inst_e0[inst], xt = tb.inst_x[inst] + (int64_t)N * S.b;
-  for (int c = tid(); c < np; c += nthr()) {
-    double acc = st.rhs[xt + c];
-    for (int i = 0; i < N; ++i) acc += ws.rthp[(e0 + i) * np + c];
-    st.rhs[xt + c] = acc;
-  }
+  (void)e0;
+  for (int c = tid(); c < np; c += nthr()) st.rhs[xt + c] += thpart_sum(ws, ws.thv, inst, N, np, c);
 }
 
 // Instances whose FP32 factor failed or whose refinement did not converge re-factor in FP64.
@@ -821,6 +818,7 @@ int launch_ipm_step(const Shape& S, const Tab& tb, const HostPlan& hp, const Ipm
   } else {
     // FP32 block factors, FP64 refinement; per-instance FP64 re-factorization where the FP32
     // factor fails or the refinement does not reach its target
+    launch_thpart(S, tb, ws, ws.rthp, nullptr, nullptr, ws.thv, s);
     hipLaunchKernelGGL(k_fp32_prep, dim3(tb.n_inst), dim3(64), 0, s, S, tb, st, ws);
     rc = launch_factor_nc(S, tb, hp, ws, 1, true, cb, ctx, s);
     if (rc) return rc;

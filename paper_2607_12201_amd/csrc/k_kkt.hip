@@ -273,9 +273,9 @@ __global__ void k_rhs_theta(Shape S, Tab tb, Ws ws, const double* __restrict__ r
   const int N = tb.inst_N[inst];
   const int64_t e0 = tb.inst_e0[inst];
   const int64_t xt = tb.inst_x[inst] + (int64_t)N * S.b;
+  (void)e0;
   for (int c = tid(); c < S.np; c += nthr()) {
-    double acc = 0.0;
-    for (int i = 0; i < N; ++i) acc += ws.rthp[(e0 + i) * S.np + c];
+    const double acc = thpart_sum(ws, ws.thv, inst, N, S.np, c);
     rhs[xt + c] = -r_x[xt + c] + acc;
     ws.sxdw[inst * S.np + c] = sigma_x[inst * S.np + c] + delta_w[inst];
   }
@@ -707,16 +707,6 @@ __global__ void k_thpart(Shape S, Tab tb, Ws ws, const double* __restrict__ a,
   }
 }
 
-// Sum of the chunk partials of parameter c of an instance, in chunk order.
-__device__ inline double thpart_sum(const Ws& ws, const double* part, int inst, int N, int np, int c) {
-  const int nch = (int)cl_ceil_div(N, CL_THCHUNK);
-  const double* p = part + (int64_t)inst * ws.nchunk * np + c;
-  double acc = 0.0;
-#pragma unroll 8
-  for (int ch = 0; ch < nch; ++ch) acc += p[(int64_t)ch * np];
-  return acc;
-}
-
 // LDS of the border solve: L_0 and the upper coupling block (ns x ns each), the parameter
 // factor (np x np), the border rows (ns x np), y, r (ns), rt (np), the group sums (1024) and a
 // dummy slot.
@@ -1022,15 +1012,20 @@ __global__ void k_mv3(Shape S, Tab tb, Ws ws, const double* __restrict__ v, doub
   const int N = tb.inst_N[inst];
   const int64_t e0 = tb.inst_e0[inst];
   const int64_t xt = tb.inst_x[inst] + (int64_t)N * S.b;
+  (void)e0;
   for (int c = tid(); c < S.np; c += nthr()) {
-    double acc = 0.0;
-    for (int i = 0; i < N; ++i) acc += ws.rthp[(e0 + i) * S.np + c];
+    const double acc = thpart_sum(ws, ws.thv, inst, N, S.np, c);
     out[xt + c] = acc + ws.sxdw[inst * S.np + c] * v[xt + c];
   }
 }
 
 // ---------------------------------------------------------------- launches
 static inline int ok_or() { return hipGetLastError() == hipSuccess ? 0 : -3; }
+
+void launch_thpart(const Shape& S, const Tab& tb, const Ws& ws, const double* a, const double* b,
+                   const double* d, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_thpart, dim3(ws.nchunk, tb.n_inst), dim3(64), 0, st, S, tb, ws, a, b, d, out);
+}
 
 int launch_assemble(const Shape& S, const Tab& tb, const Ws& ws, const double* jac,
                     const double* hess, const double* sigma_x, const double* sigma_s,
@@ -1046,6 +1041,7 @@ int launch_assemble(const Shape& S, const Tab& tb, const Ws& ws, const double* j
   else
     hipLaunchKernelGGL(k_assemble<double>, dim3((unsigned)tb.n_elem), dim3(nt), lds, st, S, tb, ws,
                        jac, hess, sigma_s, delta_w, r_x, r_s, r_y, rhs);
+  launch_thpart(S, tb, ws, ws.rthp, nullptr, nullptr, ws.thv, st);
   hipLaunchKernelGGL(k_rhs_theta, dim3(tb.n_inst), dim3(64), 0, st, S, tb, ws, r_x, sigma_x,
                      delta_w, rhs);
   return ok_or();
@@ -1101,8 +1097,7 @@ static int solve_t(const Shape& S, const Tab& tb, const HostPlan& hp, const Ws& 
   for (int l = 1; l < tb.L; ++l)
     if (hp.st[l] > 0)
       hipLaunchKernelGGL(k_crf_step<T>, dim3(hp.st[l]), dim3(snt), clds, st, S, tb, ws, rhs, l);
-  hipLaunchKernelGGL(k_thpart, dim3(ws.nchunk, tb.n_inst), dim3(64), 0, st, S, tb, ws, ws.cB,
-                     ws.cBsep, rthp, ws.thv);
+  launch_thpart(S, tb, ws, ws.cB, ws.cBsep, rthp, ws.thv, st);
   hipLaunchKernelGGL(k_border_solve<T>, dim3(tb.n_inst), dim3(1024), border_solve_lds(S), st, S,
                      tb, ws, rhs, dx);
   for (int l = tb.L; l >= 1; --l) {
@@ -1130,6 +1125,7 @@ static int matvec_masked(const Shape& S, const Tab& tb, const Ws& ws, const doub
   hipLaunchKernelGGL(k_mv2, dim3((unsigned)tb.n_elem), dim3(nt),
                      sizeof(double) * (4 * S.b + S.ns + S.K * S.nr + 3 * S.np), st, S, tb, ws, v,
                      ws.vtmp2, out, skip);
+  launch_thpart(S, tb, ws, ws.rthp, nullptr, nullptr, ws.thv, st);
   hipLaunchKernelGGL(k_mv3, dim3(tb.n_inst), dim3(64), 0, st, S, tb, ws, v, out, skip);
   return ok_or();
 }

@@ -19,6 +19,9 @@ inline int elem_threads(const Shape& S) {
 }
 size_t sep_solve_lds(const Shape& S);      // separator-chain solve kernels
 size_t border_solve_lds(const Shape& S);   // border solve kernel
+// Theta partials of each instance over 16-element chunks (a + [i > 0] b - d, b and d optional).
+void launch_thpart(const Shape& S, const Tab& tb, const Ws& ws, const double* a, const double* b,
+                   const double* d, double* out, hipStream_t st);
 
 int launch_eval(const Shape& S, const Tab& tb, const Ws& ws, const double* x, double* obj,
                 double* g, hipStream_t st);
