@@ -29,7 +29,7 @@ PEAK_HBM_GBS = 8000.0
 # An entry holds only for the kernel source it was taken on (fingerprint of the shared headers
 # and the translation unit that instantiates that grid).
 L0_COMMON = ["level0_impl.h", "regchol.h", "elem.h", "common.h", "kernels.h"]
-L0_TRAFFIC = {20: {"tu": "k_level0_u.hip", "sha": "dca5f13368af9d11", "bytes": 113392642.0}}
+L0_TRAFFIC = {20: {"tu": "k_level0_u.hip", "sha": "0cefb2fdc47464c9", "bytes": 113392642.0}}
 
 
 def level0_traffic(tile):
