@@ -105,8 +105,8 @@ def main():
                          "copy kernel of known traffic for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(instances shard trivially across GPUs; see DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(instances are independent and shard across GPUs one process per GPU)", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "multistart":
