@@ -281,49 +281,6 @@ __global__ void k_rhs_theta(Shape S, Tab tb, Ws ws, const double* __restrict__ r
   }
 }
 
-// ---------------------------------------------------------------- small dense LDS helpers
-// Row-major n x n lower Cholesky in place (FP64 work array), all threads.
-__device__ bool chol_small(double* A, int n, double* misc) {
-  for (int c = 0; c < n; ++c) {
-    if (tid() == 0) {
-      double piv = A[c * n + c];
-      bool ok = piv > 0.0 && isfinite(piv);
-      double sq = ok ? sqrt(piv) : 1.0;
-      A[c * n + c] = sq;
-      misc[0] = ok ? 1.0 : 0.0;
-      misc[1] = 1.0 / sq;
-    }
-    __syncthreads();
-    if (misc[0] == 0.0) return false;
-    double inv = misc[1];
-    for (int r = c + 1 + tid(); r < n; r += nthr()) A[r * n + c] *= inv;
-    __syncthreads();
-    const int m = n - c - 1;
-    for (int t = tid(); t < m * m; t += nthr()) {
-      int r = c + 1 + t / m, q = c + 1 + t % m;
-      if (q <= r) A[r * n + q] -= A[r * n + c] * A[q * n + c];
-    }
-    __syncthreads();
-  }
-  // zero the strict upper triangle
-  for (int t = tid(); t < n * n; t += nthr()) {
-    int r = t / n, q = t % n;
-    if (q > r) A[t] = 0.0;
-  }
-  __syncthreads();
-  return true;
-}
-
-// B (n x m, row-major, ld m) <- L^{-1} B; one thread per column.
-__device__ void trsm_l(const double* Lm, int n, double* B, int m) {
-  for (int col = tid(); col < m; col += nthr()) {
-    for (int r = 0; r < n; ++r) {
-      double v = B[r * m + col];
-      for (int q = 0; q < r; ++q) v -= Lm[r * n + q] * B[q * m + col];
-      B[r * m + col] = v / Lm[r * n + r];
-    }
-  }
-}
 // ---------------------------------------------------------------- wave triangular solves
 // One full wave (the calling workgroup's threads 0..63) solves with a lower-triangular L of
 // order n <= 256 in place on the LDS vector x.  Column oriented: lane t keeps rows t, t+64,
@@ -392,26 +349,6 @@ struct PackedCol {
   __device__ double operator()(int r, int c) const { return M[off(c) + (r - c)]; }
 };
 
-template <typename T>
-__device__ inline void load_blk(double* dst, const T* src, int n) {
-  for (int t = tid(); t < n; t += nthr()) dst[t] = (double)src[t];
-}
-template <typename T>
-__device__ inline void store_blk(T* dst, const double* src, int n) {
-  for (int t = tid(); t < n; t += nthr()) dst[t] = (T)src[t];
-}
-
-// C (n x m) -= A^T B, A: k x n, B: k x m (row-major, from global T); lower only if sym.
-template <typename T>
-__device__ void sub_atb(double* C, int n, int m, const T* A, const T* B, int k, bool sym) {
-  for (int t = tid(); t < n * m; t += nthr()) {
-    int r = t / m, q = t % m;
-    if (sym && q > r) continue;
-    double acc = 0.0;
-    for (int p = 0; p < k; ++p) acc += (double)A[p * n + r] * (double)B[p * m + q];
-    C[t] -= acc;
-  }
-}
 
 // ---------------------------------------------------------------- cyclic reduction levels
 // The chain eliminations themselves run in the k_chain kernels (register partial Cholesky of
@@ -536,15 +473,6 @@ __global__ void __launch_bounds__(64) k_l0_fwd(Shape S, Tab tb, Ws ws, const dou
     else if (a < ns + np) ws.cB[e * np + (a - ns)] = acc;
     else ws.cP[e * ns + (a - ns - np)] = (i > 0) ? acc : 0.0;
   }
-}
-
-// Forward solve of the separator chain, mirroring the factor: rcur holds the current
-// right-hand side of surviving separators.
-__device__ inline double sep_rhs_initial(const Shape& S, const Ws& ws, const double* rhs,
-                                         int64_t xoff, int64_t es, int s, bool has_next, int a) {
-  double v = rhs[xoff + (int64_t)s * S.b + S.mI + a] - ws.cS[es * S.ns + a];
-  if (has_next) v -= ws.cP[(es + 1) * S.ns + a];
-  return v;
 }
 
 // LDS of the separator solve kernels: three ns x ns blocks, the ns x np border rows, four
