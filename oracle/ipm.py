@@ -75,6 +75,7 @@ class State:
     acc_count: int = 0
     status: int = RUNNING
     log: list = field(default_factory=list)
+    last_step: tuple = ()
 
 
 def _push(v, lo, hi, k1, k2):
@@ -227,6 +228,7 @@ def iterate(model, st: State, opt: Options, solver="ldl"):
     if dw > 0.0:
         st.delta_last = dw
     dx, ds, dy, dzL, dzU, dvL, dvU = step
+    st.last_step = step   # kept for inspection by tests
 
     # fraction to the boundary
     tl, tu, sl, su = kkt.slacks(model, st.x, st.s, opt.tau_r)
@@ -307,3 +309,27 @@ def solve(model, x0, opt: Options | None = None, solver="ldl", max_iter=None):
         if max_iter is not None and st.it >= max_iter and st.status == RUNNING:
             break
     return st
+
+
+def reduced_hessian(model, x, y):
+    """Hessian of the Lagrangian reduced to the parameter directions at (x, y).
+
+    The collocation constraints determine the states from the parameters (their Jacobian in the
+    states, J_z, is square and nonsingular), so the feasible directions are Z = [-J_z^-1 J_th; I].
+    The reduced Hessian Z^T W Z, W = Hessian of Phi + y^T g, is the second derivative of the
+    objective along the discrete trajectory z(theta) when y makes the state gradient of the
+    Lagrangian vanish (problem statement eq. 1, discretized NLP eq. 2).  Returns the p x p
+    matrix and its condition number (inf when it is not positive definite)."""
+    J = model.jacobian(x).tocsc()
+    nz = model.nz
+    Jz, Jth = J[:, :nz], J[:, nz:].toarray()
+    import scipy.sparse.linalg as spla
+    lu = spla.splu(Jz)
+    dz = -lu.solve(Jth)
+    Z = np.vstack([dz, np.eye(model.np_)])
+    W = model.hessian(x, y)
+    H = Z.T @ (W @ Z)
+    H = 0.5 * (H + H.T)
+    ev = np.linalg.eigvalsh(H)
+    kappa = float(ev[-1] / ev[0]) if ev[0] > 0 else math.inf
+    return H, kappa

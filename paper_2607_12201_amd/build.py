@@ -27,13 +27,37 @@ def _hipcc():
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False) -> str:
+def _includes(path, seen):
+    """Quoted includes of a source, followed transitively."""
+    if path in seen or not os.path.exists(path):
+        return seen
+    seen.add(path)
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if line.startswith("#include \""):
+                _includes(os.path.normpath(os.path.join(os.path.dirname(path), line.split('"')[1])), seen)
+    return seen
+
+
+def _stale(src, obj):
+    """An object is stale when it is missing or older than its source or a header it includes."""
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    return any(os.path.getmtime(d) > t for d in _includes(os.path.join(CSRC, src), set()))
+
+
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every source (incremental=True: only objects older than their inputs) and link."""
     hipcc = _hipcc()
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
 
     def compile_one(src):
         obj = os.path.join(objdir, src.replace(".hip", ".o"))
+        if incremental and not _stale(src, obj):
+            return obj
         cmd = [hipcc, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
@@ -54,4 +78,4 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose=True, incremental="--incremental" in sys.argv))

@@ -16,6 +16,7 @@ RUNNING, SOLVED, ACCEPTABLE, MAXITER, TIMEOUT, ENOTPD, ENONFINITE, RESTORATION_R
 FP64, FP32_IR = 0, 1
 PHASES = ("eval", "level0", "cr", "border", "solve", "step", "linesearch")
 MAX_LS = 48
+FILTER_CAP = 128
 
 _i32p = C.POINTER(C.c_int32)
 _f64p = C.POINTER(C.c_double)

@@ -119,7 +119,7 @@ def _logk_full(param, logk_fixed, theta):
 
 
 def _assemble(n_s, react, prod, param, logk_fixed, theta_true, theta0, N, T, z0,
-              obs_species, n_times, sigma_abs, sigma_rel, lo, hi, rng, stiff):
+              obs_species, n_times, sigma_abs, sigma_rel, lo, hi, rng, stiff, meas_tau=1.0):
     n_r = len(param)
     n_p = len(theta_true)
     h = np.full(N, T / N)
@@ -128,17 +128,19 @@ def _assemble(n_s, react, prod, param, logk_fixed, theta_true, theta0, N, T, z0,
         raise ValueError("measurement times must align with element ends")
     step = N // n_times
     meas_elem_t = np.arange(1, n_times + 1) * step - 1          # element whose end is t_m
+    # measurement time t_m = t_(e-1) + meas_tau h_e inside element e (meas_tau = 1: its end)
+    t_meas = t_bound[meas_elem_t] + meas_tau * h[meas_elem_t]
     true_traj = _simulate(n_s, react, prod, _logk_full(param, logk_fixed, theta_true), z0,
-                          t_bound, stiff)
+                          np.concatenate([[0.0], t_meas]), stiff)
     M = len(obs_species) * n_times
     meas_elem = np.empty(M, np.int32)
     meas_species = np.empty(M, np.int32)
     ztrue = np.empty(M)
     m = 0
-    for e in meas_elem_t:
+    for q, e in enumerate(meas_elem_t):
         for s in obs_species:
             meas_elem[m], meas_species[m] = e, s
-            ztrue[m] = true_traj[e + 1, s]
+            ztrue[m] = true_traj[q + 1, s]
             m += 1
     sigma = np.maximum(sigma_abs, sigma_rel * np.abs(ztrue)) if sigma_rel > 0 else np.full(M, sigma_abs)
     y = ztrue + sigma * rng.standard_normal(M)
@@ -147,7 +149,7 @@ def _assemble(n_s, react, prod, param, logk_fixed, theta_true, theta0, N, T, z0,
         n_s=n_s, n_r=n_r, n_p=n_p, N=N,
         react=react.astype(np.int32), prod=prod.astype(np.int32), param=param.astype(np.int32),
         logk_fixed=logk_fixed.astype(np.float64), h=h, z0=z0.astype(np.float64),
-        meas_elem=meas_elem, meas_species=meas_species, meas_tau=np.ones(M),
+        meas_elem=meas_elem, meas_species=meas_species, meas_tau=np.full(M, float(meas_tau)),
         meas_y=y, meas_sigma=sigma,
         theta_lo=np.full(n_p, lo), theta_hi=np.full(n_p, hi),
         theta_true=theta_true.astype(np.float64), theta0=theta0.astype(np.float64),
@@ -172,9 +174,10 @@ def ab_reversible(seed=0, N=20):
 
 
 def random_network(seed=0, n_s=20, n_r=40, N=1000, n_obs=5, n_times=50, klo=1e-2, khi=1e1,
-                   n_fixed=0, stiff=False, lo=None, hi=None):
+                   n_fixed=0, stiff=False, lo=None, hi=None, meas_tau=1.0):
     """Random mass-action network: log-uniform rates in [klo, khi], initial state U[0,1],
-    n_obs observed species at n_times equally spaced times, 5% relative noise.
+    n_obs observed species at n_times equally spaced times, 5% relative noise.  meas_tau < 1
+    places each measurement inside its element at that local time instead of at its end.
 
     Reactions n_r-n_fixed .. n_r-1 have fixed, known rates drawn from the same law."""
     rng = np.random.default_rng(seed)
@@ -190,7 +193,7 @@ def random_network(seed=0, n_s=20, n_r=40, N=1000, n_obs=5, n_times=50, klo=1e-2
     lo = np.log(klo) - np.log(100.0) if lo is None else lo
     hi = np.log(khi) + np.log(100.0) if hi is None else hi
     return _assemble(n_s, react, prod, param, logk_fixed, theta_true, theta0, N, 10.0, z0,
-                     obs, n_times, 0.01 * 0.05, 0.05, lo, hi, rng, stiff)
+                     obs, n_times, 0.01 * 0.05, 0.05, lo, hi, rng, stiff, meas_tau)
 
 
 def stiff_network(seed=0, N=10000):

@@ -30,6 +30,9 @@ CASES = {
     "single": lambda: workloads.random_network(3, n_s=3, n_r=5, N=1, n_obs=2, n_times=1),
     "two": lambda: workloads.random_network(4, n_s=3, n_r=5, N=2, n_obs=2, n_times=2),
     "net20_n1000": lambda: workloads.random_network(0),
+    # measurements inside their elements (local time 0.37), not at element ends
+    "interior_tau": lambda: workloads.random_network(7, n_s=5, n_r=9, N=12, n_obs=2, n_times=12,
+                                                     n_fixed=1, meas_tau=0.37),
 }
 
 
@@ -58,3 +61,35 @@ def oracle_kkt(m, x, s, y, zL, zU, vL, vU, mu, tau_r, dw):
 
 def rel_err(a, b):
     return float(np.max(np.abs(a - b)) / max(1e-300, np.max(np.abs(b))))
+
+
+def term_scales(m, x):
+    """Per-entry magnitude of the terms each value of g and grad Phi is summed from (eq. 2b-2d
+    and the least-squares gradient), so that entries with cancellation are judged against the
+    size of what cancelled: |z| terms of the node-0 rows; sum_j |a_jk z| + h sum_r |nu_sr rho_r| of
+    the collocation rows; sum_m (sum_j |w_mj z| + |y_m|) |w_mj| / sigma_m^2 of the gradient."""
+    z, th = m.split(x)
+    G = np.zeros((m.N, m.K + 1, m.ns))
+    G[0, 0] = np.abs(z[0, 0]) + np.abs(m.z0)
+    if m.N > 1:
+        G[1:, 0] = np.abs(z[1:, 0]) + np.einsum("j,ijs->is", np.abs(m.bw), np.abs(z[:-1]))
+    rho, _ = m.rate_parts(z[:, 1:, :], th)
+    for k in range(1, m.K + 1):
+        G[:, k] = (np.einsum("j,ijs->is", np.abs(m.a[:, k]), np.abs(z))
+                   + m.h[:, None] * (np.abs(rho[:, k - 1]) @ np.abs(m.nu.T)))
+    # the residual r_m = (sum_j w_mj z - y_m) / sigma_m cancels its prediction against y_m
+    gs = np.zeros(m.n)
+    for q in range(len(m.my)):
+        zz = z[m.me[q], :, m.ms[q]]
+        rs = (np.abs(m.momega[q]) @ np.abs(zz) + abs(m.my[q])) / m.msig[q]
+        for j in range(m.K + 1):
+            gs[m.zidx(m.me[q], j, m.ms[q])] += rs * abs(m.momega[q, j]) / m.msig[q]
+    return G.ravel(), gs
+
+
+def assert_elementwise(got, ref, scale, tol, what):
+    """|got - ref| <= tol * (|ref| + scale) entry by entry."""
+    got, ref = np.asarray(got).ravel(), np.asarray(ref).ravel()
+    bound = tol * (np.abs(ref) + np.asarray(scale).ravel())
+    bad = np.abs(got - ref) > bound
+    assert not np.any(bad), (what, int(np.sum(bad)), float(np.max(np.abs(got - ref) - bound)))

@@ -56,33 +56,45 @@ def test_init_matches_oracle(torch):
     assert info["mu"] == 0.1 and info["status"] == colloc.RUNNING
 
 
-@pytest.mark.parametrize("name,tau_r,same_path", [("ab20", 1e-8, True), ("ab20", 1e-4, True),
-                                                  ("tiny", 1e-6, True), ("ragged37", 1e-6, False)])
-def test_solve_matches_oracle(torch, name, tau_r, same_path):
-    """same_path: the iteration count must agree too, and the final parameters within 1e-6.
-    On ill-conditioned instances rounding differences of the two elimination orders can flip a
-    line-search decision; the two runs then stop at different points of the tolerance region,
-    and along sloppy parameter directions (nearly unidentifiable rates) those points differ by
-    far more than 1e-6 in theta.  There the outcome is compared: status, and the final
-    objective within 1e-8 relative, the gap two 1e-6-stationary points can have."""
+def _oracle_e0(m, P, state, tau_r):
+    """Scaled optimality error of the GPU's final iterate, evaluated by the oracle."""
+    v = {n: P.state_vec(state, n).cpu().numpy() for n in ("x", "s", "y", "vL", "vU", "zL", "zU")}
+    opt = ipm.Options(tau_r=tau_r)
+    st = ipm.State(x=v["x"], s=v["s"], y=v["y"], zL=v["zL"], zU=v["zU"], vL=v["vL"], vU=v["vU"],
+                   mu=0.0, theta_max=0.0, theta_min=0.0)
+    E, _, _ = ipm.optimality_errors(m, st, opt, m.gradient(st.x), m.jacobian(st.x), m.constraints(st.x))
+    return E(0.0)
+
+
+@pytest.mark.parametrize("name,tau_r", [("ab20", 1e-8), ("ab20", 1e-4), ("tiny", 1e-6), ("ragged37", 1e-6)])
+def test_solve_matches_oracle(torch, name, tau_r):
+    """Final-parameter parity where it is defined.  Where the oracle's reduced Hessian at its
+    optimum has condition number <= 1e6 the parameters are determined to the solve tolerance
+    and must agree within 1e-6 (and so must the iteration count).  Above that, sloppy parameter
+    directions let two 1e-6-stationary points differ by more than 1e-6 in theta; there the
+    final objective must agree within 1e-10 relative and the oracle's own optimality error of
+    the GPU's final iterate must meet the tolerance."""
     announce(f"ipm solve {name} tau_r={tau_r}")
     inst = CASES[name]()
     m = problem.Model(inst, 3)
     x0 = workloads.initial_point(inst, 3)
-    st_o = ipm.solve(m, x0, ipm.Options(tau_r=tau_r), solver="ldl" if m.n < 800 else "block")
+    opt_o = ipm.Options(tau_r=tau_r)
+    st_o = ipm.solve(m, x0, opt_o, solver="ldl" if m.n < 800 else "block")
+    _, kappa = ipm.reduced_hessian(m, st_o.x, st_o.y)
     P = colloc.Problem(inst, 3)
     state, info, calls = run_gpu(P, x0, colloc.default_opts(tau_r=tau_r), torch)
     info = info[0]
     th = P.state_vec(state, "x").cpu().numpy()[m.nz:]
     print(f"oracle status {st_o.status} it {st_o.it}; gpu status {info['status']} it {info['iter']} "
-          f"calls {calls}", flush=True)
-    assert info["status"] == st_o.status
-    if same_path:
+          f"calls {calls}; reduced-Hessian kappa {kappa:.3e}", flush=True)
+    assert info["status"] == st_o.status == ipm.SOLVED
+    if kappa <= 1e6:
         assert info["iter"] == st_o.it
         assert np.max(np.abs(th - st_o.x[m.nz:]) / np.maximum(1.0, np.abs(st_o.x[m.nz:]))) < 1e-6
     else:
         phi_o = m.objective(st_o.x)
-        assert abs(info["obj"] - phi_o) <= 1e-8 * max(1.0, abs(phi_o)), (info["obj"], phi_o)
+        assert abs(info["obj"] - phi_o) <= 1e-10 * max(1.0, abs(phi_o)), (info["obj"], phi_o)
+        assert _oracle_e0(m, P, state, tau_r) <= opt_o.tol
 
 
 def test_first_iterate_matches_oracle(torch):

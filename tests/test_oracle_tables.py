@@ -84,3 +84,21 @@ def test_lagrange_values_partition_of_unity():
         v = lagrange_values(tau, t)
         assert abs(v.sum() - 1.0) < 1e-14
     assert np.allclose(lagrange_values(tau, 1.0), [0, 0, 0, 1], atol=1e-14)
+
+
+@pytest.mark.parametrize("K", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("family", ["radau", "gauss"])
+def test_lagrange_values_interpolate_polynomials(K, family):
+    """Measurement weights l_j(t) at interior t reproduce every polynomial of degree <= K from
+    its node values (a basis built on permuted nodes, or a wrong node, fails this)."""
+    tau, _, _ = collocation_tables(K, family)
+    rng = np.random.default_rng(K)
+    for t in rng.uniform(0.0, 1.0, 7):
+        w = lagrange_values(tau, t)
+        for q in range(K + 1):
+            assert abs(w @ tau ** q - t ** q) < 1e-12
+        c = rng.standard_normal(K + 1)
+        assert abs(w @ np.polyval(c, tau) - np.polyval(c, t)) < 1e-12 * np.sum(np.abs(c)) * 100
+    # and at the nodes themselves the weights are the unit vectors
+    for j in range(K + 1):
+        assert np.max(np.abs(lagrange_values(tau, tau[j]) - np.eye(K + 1)[j])) < 1e-11
