@@ -61,5 +61,15 @@ def collocation_tables(K: int, family: str = "radau"):
 
 
 def lagrange_values(tau: np.ndarray, t: float) -> np.ndarray:
-    """l_j(t) for j = 0..K (measurement interpolation weights)."""
-    return np.array([nppoly.polyval(t, c) for c in lagrange_polys(tau)])
+    """l_j(t) = prod_(m != j) (t - tau_m) / (tau_j - tau_m) for j = 0..K (measurement
+    interpolation weights), straight from the definition of the Lagrange basis: exactly 0 or 1
+    at the nodes themselves."""
+    K1 = len(tau)
+    out = np.empty(K1, dtype=np.result_type(t, float))
+    for j in range(K1):
+        v = 1.0
+        for m in range(K1):
+            if m != j:
+                v = v * (t - tau[m]) / (tau[j] - tau[m])
+        out[j] = v
+    return out
