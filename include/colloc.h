@@ -171,6 +171,21 @@ size_t colloc_state_bytes(const colloc_problem* p);
 int colloc_eval(const colloc_problem* p, const double* x_dev, double* obj_dev, double* g_dev,
                 void* ws_dev, hipStream_t stream);
 
+/* colloc_eval without a workspace, for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation).  Same inputs and
+ * outputs as colloc_eval, bitwise the same results.  The per-element partial objective sums live
+ * in a library-owned static device array of COLLOC_NOALLOC_SCRATCH_DOUBLES doubles per GPU
+ * (4 MiB, held until the process ends), so the call handles at most
+ * COLLOC_NOALLOC_MAX_ELEMS finite elements over the batch; larger handles return COLLOC_EINVAL
+ * before anything is enqueued.  The call allocates nothing.  Every call on one GPU shares that
+ * GPU's array: calls that overlap on one GPU (different streams or threads) race and must be
+ * serialized by the caller.  Nothing in the array needs clearing: each call writes every entry
+ * it reads. */
+#define COLLOC_NOALLOC_SCRATCH_DOUBLES (1 << 19)
+#define COLLOC_NOALLOC_MAX_ELEMS (COLLOC_NOALLOC_SCRATCH_DOUBLES / 13)
+int colloc_eval_noalloc(const colloc_problem* p, const double* x_dev, double* obj_dev,
+                        double* g_dev, hipStream_t stream);
+
 /* a2 -- derivatives of every expression pattern (the paper's per-pattern parallel AD):
  *   grad[n_total]  = grad Phi
  *   jac[jac_len]   = per (element i, collocation point k=1..K, reaction r), three values

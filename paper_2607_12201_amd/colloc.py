@@ -81,7 +81,9 @@ EXPORTS = [
     "ipm_init", "ipm_step", "colloc_state_layout_get", "colloc_timing_enable",
     "colloc_timing_read", "colloc_tables", "ipm_graph_create", "ipm_graph_launch",
     "ipm_graph_destroy", "colloc_tile_options", "colloc_tile_set", "colloc_tile_get",
+    "colloc_eval_noalloc",
 ]
+NOALLOC_MAX_ELEMS = (1 << 19) // 13
 
 _lib = None
 
@@ -104,6 +106,7 @@ def load(path: str = LIB_PATH):
         "colloc_workspace_bytes": (sz, [vp, i32]),
         "colloc_state_bytes": (sz, [vp]),
         "colloc_eval": (i32, [vp, vp, vp, vp, vp, vp]),
+        "colloc_eval_noalloc": (i32, [vp, vp, vp, vp, vp]),
         "colloc_derivs": (i32, [vp, vp, vp, vp, vp, vp, vp]),
         "kkt_assemble": (i32, [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, vp, vp]),
         "kkt_factor": (i32, [vp, vp, i32, vp, vp]),
@@ -265,6 +268,10 @@ class Problem:
         g = self.vec(self.m_total)
         _check(self.lib.colloc_eval(self.h, _ptr(x), _ptr(obj), _ptr(g), _ptr(ws), _stream()), "colloc_eval")
         return obj, g
+
+    def eval_noalloc(self, x, obj, g):
+        """colloc_eval without a workspace (static library scratch); outputs are the caller's."""
+        return self.lib.colloc_eval_noalloc(self.h, _ptr(x), _ptr(obj), _ptr(g), _stream())
 
     def derivs(self, x, y):
         grad = self.vec(self.n_total)

@@ -19,6 +19,7 @@ using namespace cl;
 namespace cl {
 size_t ipm_eval_lds(const Shape& S, int nt);
 int kkt_prepare_attrs(const Shape& S);
+int static_scratch(double** out);
 }
 
 // ------------------------------------------------------------------------ collocation tables
@@ -510,6 +511,8 @@ extern "C" int colloc_upload(colloc_problem* p, void* table_dev, hipStream_t str
   t.st_s = (const int*)(b + p->o_sts);
   t.cr_items_max = p->cr_items_max;
   if (kkt_prepare_attrs(p->S) != 0 || level0_prepare_attrs(p->S) != 0) return COLLOC_EHIP;
+  double* scr = nullptr;   // this device's static scratch of colloc_eval_noalloc
+  if (static_scratch(&scr) != COLLOC_OK) return COLLOC_EHIP;
   p->uploaded = true;
   return COLLOC_OK;
 }
@@ -660,6 +663,24 @@ extern "C" int colloc_eval(const colloc_problem* p, const double* x, double* obj
                            void* ws_dev, hipStream_t stream) {
   CHECK(p && p->uploaded && aligned8(x) && aligned8(obj) && aligned8(g) && ws_dev);
   Ws w = ws_layout(p, 0, ws_dev, nullptr);
+  return launch_eval(p->S, p->tab, w, x, obj, g, stream) ? COLLOC_EHIP : COLLOC_OK;
+}
+
+extern "C" int colloc_eval_noalloc(const colloc_problem* p, const double* x, double* obj, double* g,
+                                   hipStream_t stream) {
+  CHECK(p && p->uploaded && aligned8(x) && aligned8(obj) && aligned8(g));
+  static_assert(EP_N == 13, "COLLOC_NOALLOC_MAX_ELEMS assumes 13 partial slots per element");
+  if (p->n_elem > COLLOC_NOALLOC_MAX_ELEMS) {
+    if (getenv("COLLOC_DEBUG"))
+      fprintf(stderr, "colloc_eval_noalloc: %lld elements exceed the static scratch (%d)\n",
+              (long long)p->n_elem, COLLOC_NOALLOC_MAX_ELEMS);
+    return COLLOC_EINVAL;
+  }
+  double* scr = nullptr;
+  if (static_scratch(&scr) != COLLOC_OK) return COLLOC_EHIP;
+  Ws w;
+  memset(&w, 0, sizeof(w));
+  w.epart = scr;   // the only workspace array the evaluation kernels touch
   return launch_eval(p->S, p->tab, w, x, obj, g, stream) ? COLLOC_EHIP : COLLOC_OK;
 }
 
