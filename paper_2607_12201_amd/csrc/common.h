@@ -15,6 +15,8 @@ struct Shape {
   int ns, nr, np, K, b, mI, R, Rt;
   int lsp, lrq, lpc, mmax;      // longest per-instance lists (species->reactions, reactant
                                 // slots, parameter->reactions) and most measurements per element
+  int lcf, lct;                 // longest per-instance column lists of F and Fth (tiled path)
+  int big;                      // 1: tiled matrix-core factorization (large element blocks)
   double a[CL_KMAX + 1][CL_KMAX + 1];  // a[j][k] = l_j'(tau_k)
 };
 
@@ -56,6 +58,18 @@ struct Tab {
   const int* st_ptr;          // [L]  step l (1..L-1): separators that are multiples of 2^l
   const int* st_inst;
   const int* st_s;
+  // column lists of the point Jacobians (tiled assembly): F_k[s][u] = sum over the entries o of
+  // column u of [cf_s[o] == s] cf_nu[o] d rho_(cf_r[o]) / d slot cf_t[o]; Fth_k[s][c] likewise
+  // with d rho_(ct_r[o]) / d theta.  Absolute offsets per instance.
+  const int* cf_ptr;          // [n_inst][ns + 1]
+  const int* cf_s;
+  const int* cf_r;
+  const int* cf_t;
+  const double* cf_nu;
+  const int* ct_ptr;          // [n_inst][np + 1]
+  const int* ct_s;
+  const int* ct_r;
+  const double* ct_nu;
   int cr_items_max;           // largest level
 };
 
@@ -110,6 +124,12 @@ struct Ws {
   int* fbflag;                // [n_inst] FP64 fallback mask (0 = re-factor in FP64)
   int* fbneed;                // [n_inst] 1 = the instance re-factors in FP64 this step
   double* irpart;             // [n_elem][2] refinement partial maxima |d|, |dx|
+  // tiled path (Shape::big)
+  void* ebuf;                 // [n_elem][Rp x Rp] element matrices / factors
+  void* sbuf;                 // [n_elem][Lp x Lp] separator local matrices / factors
+  double* bbuf;               // [n_inst][Bp x Bp] border matrices / factors (FP64)
+  double* evec;               // [n_elem][Rp] element forward vectors
+  double* svec;               // [n_elem][Lp] separator forward vectors
 };
 
 // Element partial-sum slots (colloc_eval and the interior-point reductions).

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/colloc.h"
+#include "big.h"
 #include "ipm.h"
 #include "kernels.h"
 
@@ -20,6 +21,8 @@ namespace cl {
 size_t ipm_eval_lds(const Shape& S, int nt);
 int kkt_prepare_attrs(const Shape& S);
 int static_scratch(double** out);
+int ipm_prepare_attrs(const Shape& S);
+size_t ipm_trial_lds(const Shape& S, int max_ls);
 }
 
 // ------------------------------------------------------------------------ collocation tables
@@ -126,7 +129,8 @@ struct colloc_problem {
   // offsets of each table in the image
   size_t o_N, o_x, o_g, o_e0, o_ei, o_el, o_eh, o_mptr, o_msp, o_mw, o_mys, o_react, o_param,
       o_logk, o_spp, o_spr, o_spnu, o_rxs, o_rxnu, o_z0, o_lo, o_hi, o_crp, o_cri, o_crj, o_stp,
-      o_sti, o_sts, o_rqp, o_rqr, o_rqt, o_pcp, o_pcr;
+      o_sti, o_sts, o_rqp, o_rqr, o_rqt, o_pcp, o_pcr, o_cfp, o_cfs, o_cfr, o_cft, o_cfnu, o_ctp,
+      o_cts, o_ctr, o_ctnu;
   int cr_items_max;
   Tab tab;
   bool uploaded;
@@ -219,24 +223,39 @@ extern "C" int colloc_create(const colloc_instance_desc* inst, int32_t n_inst, i
   double tau[CL_KMAX + 1];
   radau_nodes(K, tau);
   diff_weights(K, tau, S.a);
-  // LDS budgets of the kernels (bytes)
-  int nt = elem_threads(S);
-  size_t need = std::max<size_t>(level0_lds_bytes(S, 0), ipm_eval_lds(S, nt));
-  need = std::max<size_t>(need, level0r_lds_bytes(S));
-  need = std::max<size_t>(need, std::max(chain_lds_bytes(S, 1), chain_lds_bytes(S, 2)));
-  if (!level0r_supported(S)) {
-    delete p;
-    return COLLOC_EUNSUPPORTED;
+  // Factorization path: register-resident element blocks where they fit, otherwise (or when
+  // COLLOC_FACTOR_PATH=tiled asks for it) the tiled matrix-core path.
+  {
+    const char* fp = getenv("COLLOC_FACTOR_PATH");
+    const bool force_tiled = fp && strcmp(fp, "tiled") == 0;
+    const bool force_reg = fp && strcmp(fp, "register") == 0;
+    S.big = (force_tiled || !level0r_supported(S)) ? 1 : 0;
+    if (force_reg && S.big) {
+      delete p;
+      return COLLOC_EUNSUPPORTED;
+    }
   }
-  size_t need_b = sizeof(double) * std::max<size_t>(
-      (size_t)2 * ns * ns + 2 * (size_t)ns * np + (size_t)np * np + 8,
-      (size_t)7 * ns * ns + 3 * (size_t)ns * np + 8);
-  need_b = std::max<size_t>(need_b, sizeof(double) * ((size_t)ns * ns + ns + np + (size_t)np * np + 1024));
-  need_b = std::max<size_t>(need_b, sep_solve_lds(S));
-  need_b = std::max<size_t>(need_b, border_solve_lds(S));
-  // line-search trials: vectors, rate constants of every candidate, partial sums (no attribute)
-  const size_t need_t = sizeof(double) * (4 * (size_t)S.b + 2 * ns + 2 * np + (size_t)CL_MAX_LS * nr + 768);
-  if (need > lds_limit() || need_b > lds_limit() || need_t > 64 * 1024 || nr * K > 65536) {
+  // LDS budgets of the kernels (bytes); the tiled path's element assembly is checked once the
+  // column lists are known
+  int nt = elem_threads(S);
+  size_t need = ipm_eval_lds(S, nt);
+  size_t need_b = 0;
+  if (!S.big) {
+    need = std::max<size_t>(need, level0_lds_bytes(S, 0));
+    need = std::max<size_t>(need, level0r_lds_bytes(S));
+    need = std::max<size_t>(need, std::max(chain_lds_bytes(S, 1), chain_lds_bytes(S, 2)));
+    need_b = sizeof(double) * std::max<size_t>(
+        (size_t)2 * ns * ns + 2 * (size_t)ns * np + (size_t)np * np + 8,
+        (size_t)7 * ns * ns + 3 * (size_t)ns * np + 8);
+    need_b = std::max<size_t>(need_b, sizeof(double) * ((size_t)ns * ns + ns + np + (size_t)np * np + 1024));
+    need_b = std::max<size_t>(need_b, sep_solve_lds(S));
+    need_b = std::max<size_t>(need_b, border_solve_lds(S));
+  } else {
+    need_b = big_solve_lds(S);
+  }
+  // line-search trials: vectors, rate constants of every candidate, partial sums
+  const size_t need_t = ipm_trial_lds(S, CL_MAX_LS);
+  if (need > lds_limit() || need_b > lds_limit() || need_t > lds_limit() || nr * K > 65536) {
     delete p;
     return COLLOC_EUNSUPPORTED;
   }
@@ -350,7 +369,41 @@ extern "C" int colloc_create(const colloc_instance_desc* inst, int32_t n_inst, i
     S.lpc = std::max(S.lpc, pcp[(size_t)q * (np + 1) + np] - pcp[(size_t)q * (np + 1)]);
   }
   for (int64_t e = 0; e < eo; ++e) S.mmax = std::max(S.mmax, mptr[e + 1] - mptr[e]);
-  if (level0r_lds_bytes(S) > lds_limit()) {
+  // column lists of F and Fth (tiled assembly): for reactant species u, every (reaction, slot)
+  // with u in the slot and every species s the reaction changes; for parameter c, every reaction
+  // of c and every species it changes
+  std::vector<int> cfp((size_t)n_inst * (ns + 1)), cfs, cfr, cft, ctp((size_t)n_inst * (np + 1)), cts, ctr;
+  std::vector<double> cfnu, ctnu;
+  for (int q = 0; q < n_inst; ++q) {
+    const int* rs = rxs.data() + (size_t)q * nr * 4;
+    const double* rn = rxnu.data() + (size_t)q * nr * 4;
+    for (int u = 0; u < ns; ++u) {
+      cfp[(size_t)q * (ns + 1) + u] = (int)cfs.size();
+      for (int o = rqp[(size_t)q * (ns + 1) + u]; o < rqp[(size_t)q * (ns + 1) + u + 1]; ++o)
+        for (int k = 0; k < 4; ++k)
+          if (rs[rqr[o] * 4 + k] >= 0) {
+            cfs.push_back(rs[rqr[o] * 4 + k]);
+            cfr.push_back(rqr[o]);
+            cft.push_back(rqt[o]);
+            cfnu.push_back(rn[rqr[o] * 4 + k]);
+          }
+    }
+    cfp[(size_t)q * (ns + 1) + ns] = (int)cfs.size();
+    for (int c = 0; c < np; ++c) {
+      ctp[(size_t)q * (np + 1) + c] = (int)cts.size();
+      for (int o = pcp[(size_t)q * (np + 1) + c]; o < pcp[(size_t)q * (np + 1) + c + 1]; ++o)
+        for (int k = 0; k < 4; ++k)
+          if (rs[pcr[o] * 4 + k] >= 0) {
+            cts.push_back(rs[pcr[o] * 4 + k]);
+            ctr.push_back(pcr[o]);
+            ctnu.push_back(rn[pcr[o] * 4 + k]);
+          }
+    }
+    ctp[(size_t)q * (np + 1) + np] = (int)cts.size();
+    S.lcf = std::max(S.lcf, cfp[(size_t)q * (ns + 1) + ns] - cfp[(size_t)q * (ns + 1)]);
+    S.lct = std::max(S.lct, ctp[(size_t)q * (np + 1) + np] - ctp[(size_t)q * (np + 1)]);
+  }
+  if ((!S.big && level0r_lds_bytes(S) > lds_limit()) || (S.big && big_asm_lds(S) > lds_limit())) {
     delete p;
     return COLLOC_EUNSUPPORTED;
   }
@@ -422,6 +475,15 @@ extern "C" int colloc_create(const colloc_instance_desc* inst, int32_t n_inst, i
   p->o_stp = im.add(stp.data(), sizeof(int) * stp.size());
   p->o_sti = im.add(sti.data(), sizeof(int) * sti.size());
   p->o_sts = im.add(sts.data(), sizeof(int) * sts.size());
+  p->o_cfp = im.add(cfp.data(), sizeof(int) * cfp.size());
+  p->o_cfs = im.add(cfs.data(), sizeof(int) * cfs.size());
+  p->o_cfr = im.add(cfr.data(), sizeof(int) * cfr.size());
+  p->o_cft = im.add(cft.data(), sizeof(int) * cft.size());
+  p->o_cfnu = im.add(cfnu.data(), sizeof(double) * cfnu.size());
+  p->o_ctp = im.add(ctp.data(), sizeof(int) * ctp.size());
+  p->o_cts = im.add(cts.data(), sizeof(int) * cts.size());
+  p->o_ctr = im.add(ctr.data(), sizeof(int) * ctr.size());
+  p->o_ctnu = im.add(ctnu.data(), sizeof(double) * ctnu.size());
   im.bytes.resize((im.bytes.size() + 255) & ~(size_t)255);
   p->uploaded = false;
   p->timing = false;
@@ -509,8 +571,22 @@ extern "C" int colloc_upload(colloc_problem* p, void* table_dev, hipStream_t str
   t.st_ptr = (const int*)(b + p->o_stp);
   t.st_inst = (const int*)(b + p->o_sti);
   t.st_s = (const int*)(b + p->o_sts);
+  t.cf_ptr = (const int*)(b + p->o_cfp);
+  t.cf_s = (const int*)(b + p->o_cfs);
+  t.cf_r = (const int*)(b + p->o_cfr);
+  t.cf_t = (const int*)(b + p->o_cft);
+  t.cf_nu = (const double*)(b + p->o_cfnu);
+  t.ct_ptr = (const int*)(b + p->o_ctp);
+  t.ct_s = (const int*)(b + p->o_cts);
+  t.ct_r = (const int*)(b + p->o_ctr);
+  t.ct_nu = (const double*)(b + p->o_ctnu);
   t.cr_items_max = p->cr_items_max;
-  if (kkt_prepare_attrs(p->S) != 0 || level0_prepare_attrs(p->S) != 0) return COLLOC_EHIP;
+  if (ipm_prepare_attrs(p->S) != 0) return COLLOC_EHIP;
+  if (p->S.big) {
+    if (big_prepare_attrs(p->S) != 0) return COLLOC_EHIP;
+  } else if (kkt_prepare_attrs(p->S) != 0 || level0_prepare_attrs(p->S) != 0) {
+    return COLLOC_EHIP;
+  }
   double* scr = nullptr;   // this device's static scratch of colloc_eval_noalloc
   if (static_scratch(&scr) != COLLOC_OK) return COLLOC_EHIP;
   p->uploaded = true;
@@ -557,37 +633,47 @@ static Ws ws_layout(const colloc_problem* p, int prec, void* base, size_t* bytes
   w.irpart = c.take<double>(E * 2);
   w.rthp = c.take<double>(E * S.np);
   w.dcont = c.take<double>(E * S.ns);
+  const bool big = S.big != 0;
+  const size_t Er = big ? 0 : E;   // register-path block arrays (empty on the tiled path)
   w.ath = c.take<double>(E * S.np * S.np);
-  w.thcr = c.take<double>(E * S.np * S.np);
+  w.thcr = c.take<double>(Er * S.np * S.np);
   w.S = c.take<double>(I * S.np * S.np);
   w.nchunk = p->nchunk;
   w.thred = c.take<double>(I * p->nchunk * S.np * S.np);
   w.thv = c.take<double>(I * p->nchunk * S.np);
-  w.yI = c.take<double>(E * S.mI);
-  w.cS = c.take<double>(E * S.ns);
-  w.cP = c.take<double>(E * S.ns);
-  w.cB = c.take<double>(E * S.np);
-  w.ysep = c.take<double>(E * S.ns);
+  w.yI = c.take<double>(Er * S.mI);
+  w.cS = c.take<double>(Er * S.ns);
+  w.cP = c.take<double>(Er * S.ns);
+  w.cB = c.take<double>(Er * S.np);
+  w.ysep = c.take<double>(Er * S.ns);
   w.xsep = c.take<double>(E * S.ns);
   w.rcur = c.take<double>(E * S.ns);
-  w.cBsep = c.take<double>(E * S.np);
+  w.cBsep = c.take<double>(Er * S.np);
   w.xth = c.take<double>(I * S.np);
+  if (big) {   // tiled path: FP64 vectors and border, then the blocks in the factor precision
+    const BigGeom G = big_geom(S);
+    w.evec = c.take<double>(E * G.Rp);
+    w.svec = c.take<double>(E * G.Lp);
+    w.bbuf = c.take<double>(I * G.Bp * G.Bp);
+    w.ebuf = c.take<char>(E * G.Rp * G.Rp, sz);
+    w.sbuf = c.take<char>(E * G.Lp * G.Lp, sz);
+  }
   // block data in the factor precision
-  w.panel = c.take<char>(E * S.R * S.mI, sz);
-  w.dss = c.take<char>(E * S.ns * S.ns, sz);
-  w.bs = c.take<char>(E * S.ns * S.np, sz);
-  w.tprev = c.take<char>(E * S.ns * S.ns, sz);
-  w.e1 = c.take<char>(E * S.ns * S.ns, sz);
-  w.gprev = c.take<char>(E * S.ns * S.np, sz);
-  w.lsep = c.take<char>(E * S.ns * S.ns, sz);
-  w.ul = c.take<char>(E * S.ns * S.ns, sz);
-  w.ur = c.take<char>(E * S.ns * S.ns, sz);
-  w.ub = c.take<char>(E * S.ns * S.np, sz);
-  w.cTl = c.take<char>(E * S.ns * S.ns, sz);
-  w.cTr = c.take<char>(E * S.ns * S.ns, sz);
-  w.cE = c.take<char>(E * S.ns * S.ns, sz);
-  w.cGl = c.take<char>(E * S.ns * S.np, sz);
-  w.cGr = c.take<char>(E * S.ns * S.np, sz);
+  w.panel = c.take<char>(Er * S.R * S.mI, sz);
+  w.dss = c.take<char>(Er * S.ns * S.ns, sz);
+  w.bs = c.take<char>(Er * S.ns * S.np, sz);
+  w.tprev = c.take<char>(Er * S.ns * S.ns, sz);
+  w.e1 = c.take<char>(Er * S.ns * S.ns, sz);
+  w.gprev = c.take<char>(Er * S.ns * S.np, sz);
+  w.lsep = c.take<char>(Er * S.ns * S.ns, sz);
+  w.ul = c.take<char>(Er * S.ns * S.ns, sz);
+  w.ur = c.take<char>(Er * S.ns * S.ns, sz);
+  w.ub = c.take<char>(Er * S.ns * S.np, sz);
+  w.cTl = c.take<char>(Er * S.ns * S.ns, sz);
+  w.cTr = c.take<char>(Er * S.ns * S.ns, sz);
+  w.cE = c.take<char>(Er * S.ns * S.ns, sz);
+  w.cGl = c.take<char>(Er * S.ns * S.np, sz);
+  w.cGr = c.take<char>(Er * S.ns * S.np, sz);
   if (bytes) *bytes = (c.off + 255) & ~(size_t)255;
   return w;
 }
@@ -855,6 +941,10 @@ extern "C" int ipm_graph_destroy(colloc_graph* g) {
 
 extern "C" int colloc_tile_options(const colloc_problem* p, int32_t which, int32_t* ts, int32_t cap) {
   CHECK(p && which >= 0 && which <= 2 && cap >= 0 && (ts || cap == 0));
+  if (p->S.big) {   // the tiled path has one fixed tiling
+    if (cap > 0) ts[0] = 0;
+    return 1;
+  }
   int tmp[8];
   const int n = tile_options(p->S, which, tmp, 8);
   for (int i = 0; i < n && i < cap; ++i) ts[i] = tmp[i];
@@ -862,7 +952,7 @@ extern "C" int colloc_tile_options(const colloc_problem* p, int32_t which, int32
 }
 
 extern "C" int colloc_tile_set(colloc_problem* p, int32_t which, int32_t ts) {
-  CHECK(p && which >= 0 && which <= 2 && tile_valid(p->S, which, ts));
+  CHECK(p && which >= 0 && which <= 2 && (p->S.big ? ts == 0 : tile_valid(p->S, which, ts)));
   p->hp.ts[which] = ts;
   return COLLOC_OK;
 }

@@ -1,0 +1,1018 @@
+// Tiled (matrix-core) factorization and solve of the condensed KKT matrix for element blocks too
+// large for the register-resident kernels.  Same elimination order as the register path (every
+// element's interior collocation nodes, then cyclic reduction of the element-end separators,
+// then the border [separator 0 | theta]), with every dense block in global memory:
+//
+//   assembly   k_big_asm       one workgroup per element writes the lower triangle of its
+//                              matrix over [z | theta | P] (eq. 2b-2d through J^T Ds J + W) from
+//                              the per-pattern derivative values, the theta-theta block in FP64
+//   level 0    k_pchol_panel   left-looking partial Cholesky of the interior columns, 32-column
+//                              panels, updates as 16x16x4 matrix-core products
+//              k_pchol_syrk    trailing Schur complement (all rows below the interior block)
+//                              as matrix-core tiles, the tiles of one element on one XCD
+//   chain      k_sep_init / k_sep_step gather each separator's local matrix; the same two
+//                              kernels eliminate the separators of every cyclic-reduction level
+//   border     k_big_theta     theta-theta Schur complement in FP64 on matrix cores, split over
+//                              16-element chunks (fixed order); k_border_build sums the chunks
+//                              into the border matrix, k_pchol_panel factors it
+//   solve      blocked forward/backward substitution through the same levels (FP64 vectors)
+#include <stdio.h>
+#include <stdlib.h>
+
+#include <algorithm>
+
+#include "big.h"
+#include "elem.h"
+#include "kernels.h"
+
+namespace cl {
+
+// ---------------------------------------------------------------- item addressing
+// mode 0: element e (matrix e of ebuf), mode 1: separator eliminated at cyclic-reduction level
+// `level` (matrix = its global index in sbuf), mode 2: instance border (matrix = instance).
+struct PArgs {
+  void* base;
+  int64_t stride;   // elements between matrices
+  int ld, n, m, count, mode, level;
+  int zero;         // syrk: the trailing block starts at zero (not read)
+  int skip0, skip1; // syrk: tiles inside [skip0, skip1)^2 are not computed
+  int ntile;        // syrk: lower tiles per item
+};
+
+__device__ inline void pitem(const Tab& tb, const PArgs& a, int k, int64_t& mat, int& inst) {
+  if (a.mode == 0) {
+    mat = k;
+    inst = tb.elem_inst[k];
+  } else if (a.mode == 1) {
+    const int it = tb.cr_ptr[a.level - 1] + k;
+    inst = tb.cr_inst[it];
+    mat = tb.inst_e0[inst] + tb.cr_j[it];
+  } else {
+    mat = k;
+    inst = k;
+  }
+}
+
+// ---------------------------------------------------------------- assembly
+// LDS layout of k_big_asm (doubles, then ints).
+struct AsmLds {
+  double *D;            // (K + 1) x ns row weights Ds of the element (node-major)
+  double *vF, *vT;      // K x lcf, K x lct list values of the F and Fth columns per point
+  double *hv;           // K nr 4 weighted second-derivative values
+  double *mw;           // element measurements' weights (mmax x (K + 1))
+  int *cfp, *cfs, *ctp, *cts, *rqp, *rqr, *rqt, *pcp, *pcr, *rea, *par, *msp;
+  int nmeas;
+};
+
+size_t big_asm_lds(const Shape& S) {
+  const size_t nd = (size_t)(S.K + 1) * S.ns + (size_t)S.K * (S.lcf + S.lct) + 4 * (size_t)S.K * S.nr +
+                    (size_t)S.mmax * (S.K + 1) + 8;
+  const size_t ni = (S.ns + 1) + (size_t)S.lcf + (S.np + 1) + S.lct + (S.ns + 1) + 2 * (size_t)S.lrq +
+                    (S.np + 1) + S.lpc + 3 * (size_t)S.nr + S.mmax + 8;
+  return sizeof(double) * nd + sizeof(int) * ni;
+}
+
+// F_k[s][u] summed over the column list of u.
+__device__ inline double a_F(const AsmLds& L, int lcf, int k, int s, int u) {
+  double v = 0.0;
+  const double* vf = L.vF + (k - 1) * lcf;
+  for (int o = L.cfp[u]; o < L.cfp[u + 1]; ++o) v += (L.cfs[o] == s) ? vf[o] : 0.0;
+  return v;
+}
+__device__ inline double a_T(const AsmLds& L, int lct, int k, int s, int c) {
+  double v = 0.0;
+  const double* vt = L.vT + (k - 1) * lct;
+  for (int o = L.ctp[c]; o < L.ctp[c + 1]; ++o) v += (L.cts[o] == s) ? vt[o] : 0.0;
+  return v;
+}
+// sum_s d_k[s] X[s][p] Y[s][q] for two column lists
+__device__ inline double a_dot(const int* p1, const int* s1, const double* v1, int u1, const int* p2,
+                               const int* s2, const double* v2, int u2, const double* d) {
+  double acc = 0.0;
+  for (int o1 = p1[u1]; o1 < p1[u1 + 1]; ++o1) {
+    const int s = s1[o1];
+    const double x = v1[o1] * d[s];
+    for (int o2 = p2[u2]; o2 < p2[u2 + 1]; ++o2) acc += (s2[o2] == s) ? x * v2[o2] : 0.0;
+  }
+  return acc;
+}
+
+// Entry (r, c), r >= c, of element i's matrix over [z (b) | theta (np) | P (ns)]: node-0 rows
+// (initial condition / continuity, eq. 2c-2d), the measurement Hessian and dw on z, and for every
+// collocation point k the product of its rows a_jk e_(j,s) - h F_k on node k - h Fth_k on theta,
+// weighted by Ds, plus the reaction second derivatives (W).  theta-theta entries exclude Sx + dw
+// (added once per instance at the border).
+__device__ inline double big_entry(const Shape& S, const AsmLds& L, int i, double h, double dw, int r, int c) {
+  const int ns = S.ns, np = S.np, b = S.b, K = S.K, nr = S.nr;
+  const double* d0 = L.D;
+  if (r < b) {
+    const int j1 = r / ns, s1 = r - j1 * ns, j2 = c / ns, s2 = c - j2 * ns;
+    double v = (r == c) ? dw : 0.0;
+    if (s1 == s2) {
+      if (j1 == 0 && j2 == 0) v += d0[s1];
+      for (int q = 0; q < L.nmeas; ++q)
+        if (L.msp[q] == s1) v += L.mw[q * (K + 1) + j1] * L.mw[q * (K + 1) + j2];
+      for (int k = 1; k <= K; ++k) v += L.D[k * ns + s1] * S.a[j1][k] * S.a[j2][k];
+    }
+    if (j2 >= 1) v -= h * S.a[j1][j2] * L.D[j2 * ns + s1] * a_F(L, S.lcf, j2, s1, s2);
+    if (j1 >= 1) v -= h * S.a[j2][j1] * L.D[j1 * ns + s2] * a_F(L, S.lcf, j1, s2, s1);
+    if (j1 == j2 && j1 >= 1) {
+      const int k = j1;
+      v += h * h * a_dot(L.cfp, L.cfs, L.vF + (k - 1) * S.lcf, s1, L.cfp, L.cfs, L.vF + (k - 1) * S.lcf, s2,
+                         L.D + k * ns);
+      double wz = 0.0;   // reactions with s1 in a slot and s2 in the other
+      for (int o = L.rqp[s1]; o < L.rqp[s1 + 1]; ++o) {
+        const int rr = L.rqr[o], sl = L.rqt[o];
+        wz += (L.rea[2 * rr + 1 - sl] == s2) ? L.hv[((k - 1) * nr + rr) * 4] : 0.0;
+      }
+      v += wz;
+    }
+    return v;
+  }
+  if (r < b + np) {
+    const int th = r - b;
+    if (c < b) {
+      const int j = c / ns, s = c - j * ns;
+      double v = 0.0;
+      for (int k = 1; k <= K; ++k) v -= h * S.a[j][k] * L.D[k * ns + s] * a_T(L, S.lct, k, s, th);
+      if (j >= 1) {
+        const int k = j;
+        v += h * h * a_dot(L.cfp, L.cfs, L.vF + (k - 1) * S.lcf, s, L.ctp, L.cts, L.vT + (k - 1) * S.lct, th,
+                           L.D + k * ns);
+        double wt = 0.0;   // reactions with s in a slot and rate parameter th
+        for (int o = L.rqp[s]; o < L.rqp[s + 1]; ++o) {
+          const int rr = L.rqr[o], sl = L.rqt[o];
+          wt += (L.par[rr] == th) ? L.hv[((k - 1) * nr + rr) * 4 + 1 + sl] : 0.0;
+        }
+        v += wt;
+      }
+      return v;
+    }
+    const int th2 = c - b;
+    double v = 0.0;
+    for (int k = 1; k <= K; ++k) {
+      v += h * h * a_dot(L.ctp, L.cts, L.vT + (k - 1) * S.lct, th, L.ctp, L.cts, L.vT + (k - 1) * S.lct, th2,
+                         L.D + k * ns);
+      if (th == th2)
+        for (int o = L.pcp[th]; o < L.pcp[th + 1]; ++o) v += L.hv[((k - 1) * nr + L.pcr[o]) * 4 + 3];
+    }
+    return v;
+  }
+  const int p = r - b - np;   // P row: the previous separator, coupled through eq. 2c
+  if (i == 0) return 0.0;
+  if (c < b) return (c == p) ? -d0[p] : 0.0;
+  if (c < b + np) return 0.0;
+  return (c == r) ? d0[p] : 0.0;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_big_asm(Shape S, Tab tb, Ws ws) {
+  extern __shared__ double lds[];
+  const int64_t e = blockIdx.x;
+  const int inst = tb.elem_inst[e], i = tb.elem_loc[e];
+  if (block_flag(&ws.flag[inst])) return;
+  const int ns = S.ns, np = S.np, nr = S.nr, K = S.K, b = S.b, R = S.R;
+  const BigGeom G = big_geom(S);
+  const double h = tb.elem_h[e], dw = ws.dw[inst];
+  AsmLds L;
+  L.D = lds;
+  L.vF = L.D + (K + 1) * ns;
+  L.vT = L.vF + K * S.lcf;
+  L.hv = L.vT + K * S.lct;
+  L.mw = L.hv + 4 * K * nr;
+  int* ip = (int*)(L.mw + S.mmax * (K + 1) + 8);
+  L.cfp = ip; ip += ns + 1;
+  L.cfs = ip; ip += S.lcf;
+  L.ctp = ip; ip += np + 1;
+  L.cts = ip; ip += S.lct;
+  L.rqp = ip; ip += ns + 1;
+  L.rqr = ip; ip += S.lrq;
+  L.rqt = ip; ip += S.lrq;
+  L.pcp = ip; ip += np + 1;
+  L.pcr = ip; ip += S.lpc;
+  L.rea = ip; ip += 2 * nr;
+  L.par = ip; ip += nr;
+  L.msp = ip;
+  // instance tables (relative list offsets), element values
+  const int cf0 = tb.cf_ptr[inst * (ns + 1)], ct0 = tb.ct_ptr[inst * (np + 1)];
+  const int rq0 = tb.rq_ptr[inst * (ns + 1)], pc0 = tb.pc_ptr[inst * (np + 1)];
+  const int ncf = tb.cf_ptr[inst * (ns + 1) + ns] - cf0, nct = tb.ct_ptr[inst * (np + 1) + np] - ct0;
+  const int nrq = tb.rq_ptr[inst * (ns + 1) + ns] - rq0, npc = tb.pc_ptr[inst * (np + 1) + np] - pc0;
+  const int m0 = tb.elem_mptr[e], nm = tb.elem_mptr[e + 1] - m0;
+  const int64_t gi = tb.inst_g[inst] + (int64_t)i * b;
+  const int64_t jl = (int64_t)K * nr;
+  const double* jac = ws.jac + e * jl * 3;
+  const double* hes = ws.hess + e * jl * 4;
+  for (int t = tid(); t <= ns; t += nthr()) {
+    L.cfp[t] = tb.cf_ptr[inst * (ns + 1) + t] - cf0;
+    L.rqp[t] = tb.rq_ptr[inst * (ns + 1) + t] - rq0;
+  }
+  for (int t = tid(); t <= np; t += nthr()) {
+    L.ctp[t] = tb.ct_ptr[inst * (np + 1) + t] - ct0;
+    L.pcp[t] = tb.pc_ptr[inst * (np + 1) + t] - pc0;
+  }
+  for (int t = tid(); t < ncf; t += nthr()) L.cfs[t] = tb.cf_s[cf0 + t];
+  for (int t = tid(); t < nct; t += nthr()) L.cts[t] = tb.ct_s[ct0 + t];
+  for (int t = tid(); t < nrq; t += nthr()) {
+    L.rqr[t] = tb.rq_r[rq0 + t];
+    L.rqt[t] = tb.rq_t[rq0 + t];
+  }
+  for (int t = tid(); t < npc; t += nthr()) L.pcr[t] = tb.pc_r[pc0 + t];
+  for (int t = tid(); t < 2 * nr; t += nthr()) L.rea[t] = tb.react[inst * nr * 2 + t];
+  for (int t = tid(); t < nr; t += nthr()) L.par[t] = tb.param[inst * nr + t];
+  for (int t = tid(); t < nm; t += nthr()) L.msp[t] = tb.meas_sp[m0 + t];
+  for (int t = tid(); t < nm * (K + 1); t += nthr()) L.mw[t] = tb.meas_w[(int64_t)m0 * (K + 1) + t];
+  for (int t = tid(); t < b; t += nthr()) L.D[t] = ws.Ds[gi + t];
+  for (int t = tid(); t < 4 * jl; t += nthr()) L.hv[t] = hes[t];
+  for (int t = tid(); t < K * ncf; t += nthr()) {
+    const int k = t / ncf, o = t - k * ncf;
+    L.vF[k * S.lcf + o] = tb.cf_nu[cf0 + o] * jac[(k * nr + tb.cf_r[cf0 + o]) * 3 + tb.cf_t[cf0 + o]];
+  }
+  for (int t = tid(); t < K * nct; t += nthr()) {
+    const int k = t / nct, o = t - k * nct;
+    L.vT[k * S.lct + o] = tb.ct_nu[ct0 + o] * jac[(k * nr + tb.ct_r[ct0 + o]) * 3 + 2];
+  }
+  L.nmeas = nm;
+  __syncthreads();
+  T* A = (T*)ws.ebuf + e * (int64_t)G.Rp * G.Rp;
+  double* ath = ws.ath + e * (int64_t)np * np;
+  // column by column, consecutive threads on consecutive rows (coalesced stores)
+  for (int c = 0; c < R; ++c) {
+    for (int r = c + tid(); r < R; r += nthr()) {
+      const bool tt = r >= b && r < b + np && c >= b;   // theta-theta: FP64 side array
+      const double v = big_entry(S, L, i, h, dw, r, c);
+      if (tt) {
+        ath[(r - b) * np + (c - b)] = v;
+        A[r + (int64_t)c * G.Rp] = (T)0;
+      } else {
+        A[r + (int64_t)c * G.Rp] = (T)v;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- partial Cholesky
+// Left-looking partial Cholesky of the first m columns of an n x n SPD matrix (lower triangle,
+// column-major, leading dimension ld), one workgroup of four waves per matrix.  Columns are
+// eliminated in panels of 32: the panel's rows are brought up to date with all earlier panels in
+// chunks of 128 rows (C = A - L_rows L_panel^T as 16x16x4 matrix-core products, operands staged
+// through LDS 16 columns at a time), then the panel's 32 x 32 diagonal block is factored by one
+// wave and every row below it solved against that factor (FP64 arithmetic), and the chunk is
+// stored back.  A non-positive or non-finite pivot sets the instance's flag.
+template <typename T>
+__global__ void __launch_bounds__(256) k_pchol_panel(Tab tb, Ws ws, PArgs a) {
+  constexpr int NB = 32, CH = 128, KC = 16, PC = NB + 1;
+  __shared__ T sA[KC * CH];
+  __shared__ T sB[KC * NB];
+  __shared__ double sC[CH * PC];
+  __shared__ double sL[NB * PC];
+  __shared__ int sflag;
+  typedef typename Mma<T>::acc acc_t;
+  if ((int)blockIdx.x >= a.count) return;
+  int64_t mat;
+  int inst;
+  pitem(tb, a, blockIdx.x, mat, inst);
+  if (block_flag(&ws.flag[inst])) return;
+  T* A = (T*)a.base + mat * a.stride;
+  const int n = a.n, m = a.m, ld = a.ld;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  for (int k0 = 0; k0 < m; k0 += NB) {
+    const int wd = min(NB, m - k0);
+    for (int r0 = k0; r0 < n; r0 += CH) {
+      acc_t c00 = {0, 0, 0, 0}, c01 = {0, 0, 0, 0}, c10 = {0, 0, 0, 0}, c11 = {0, 0, 0, 0};
+      for (int kc = 0; kc < k0; kc += KC) {
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < (KC * CH) / 256; ++q) {
+          const int idx = t + 256 * q, ii = idx & (CH - 1), kk = idx / CH, r = r0 + ii;
+          sA[kk * CH + ii] = r < n ? A[r + (int64_t)(kc + kk) * ld] : (T)0;
+        }
+#pragma unroll
+        for (int q = 0; q < (KC * NB) / 256; ++q) {
+          const int idx = t + 256 * q, j = idx & (NB - 1), kk = idx / NB;
+          sB[kk * NB + j] = j < wd ? A[(k0 + j) + (int64_t)(kc + kk) * ld] : (T)0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < KC / 4; ++s) {
+          const int kk = 4 * s + (lane >> 4), li = lane & 15;
+          const T a0 = sA[kk * CH + 32 * w + li], a1 = sA[kk * CH + 32 * w + 16 + li];
+          const T b0 = sB[kk * NB + li], b1 = sB[kk * NB + 16 + li];
+          c00 = Mma<T>::mma(a0, b0, c00);
+          c01 = Mma<T>::mma(a0, b1, c01);
+          c10 = Mma<T>::mma(a1, b0, c10);
+          c11 = Mma<T>::mma(a1, b1, c11);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int rr = 32 * w + Mma<T>::row(lane, v), cc = lane & 15;
+        sC[rr * PC + cc] = (double)c00[v];
+        sC[rr * PC + 16 + cc] = (double)c01[v];
+        sC[(rr + 16) * PC + cc] = (double)c10[v];
+        sC[(rr + 16) * PC + 16 + cc] = (double)c11[v];
+      }
+      __syncthreads();
+      for (int idx = t; idx < CH * NB; idx += 256) {
+        const int ii = idx & (CH - 1), j = idx / CH, r = r0 + ii;
+        if (r < n && j < wd && r >= k0 + j) sC[ii * PC + j] = (double)A[r + (int64_t)(k0 + j) * ld] - sC[ii * PC + j];
+      }
+      __syncthreads();
+      int i0 = 0;
+      if (r0 == k0) {   // the chunk holds the panel's diagonal block: factor it (wave 0)
+        if (w == 0) {
+          bool good = true;
+          for (int j = 0; j < wd; ++j) {
+            const double piv = sC[j * PC + j];
+            good = good && piv > 0.0 && isfinite(piv);
+            const double ljj = good ? sqrt(piv) : 1.0;
+            __builtin_amdgcn_wave_barrier();
+            if (lane == j) sC[j * PC + j] = ljj;
+            if (lane > j && lane < wd) sC[lane * PC + j] /= ljj;
+            __builtin_amdgcn_wave_barrier();
+            if (lane > j && lane < wd) {
+              const double lij = sC[lane * PC + j];
+              for (int jj = j + 1; jj <= lane; ++jj) sC[lane * PC + jj] -= lij * sC[jj * PC + j];
+            }
+            __builtin_amdgcn_wave_barrier();
+          }
+          if (lane == 0) sflag = good ? 1 : 0;
+        }
+        __syncthreads();
+        if (!sflag) {
+          if (t == 0) atomicOr(&ws.flag[inst], 1);
+          return;
+        }
+        for (int idx = t; idx < NB * NB; idx += 256) {
+          const int ii = idx / NB, j = idx - ii * NB;
+          sL[ii * PC + j] = (ii < wd && j <= ii) ? sC[ii * PC + j] : 0.0;
+        }
+        __syncthreads();
+        i0 = wd;
+      }
+      // rows below the diagonal block: x = c L^{-T}, one thread per row
+      for (int ii = i0 + t; ii < CH && r0 + ii < n; ii += 256) {
+        double* x = sC + ii * PC;
+        for (int j = 0; j < wd; ++j) {
+          double s = x[j];
+          for (int p = 0; p < j; ++p) s -= x[p] * sL[j * PC + p];
+          x[j] = s / sL[j * PC + j];
+        }
+      }
+      __syncthreads();
+      for (int idx = t; idx < CH * NB; idx += 256) {
+        const int ii = idx & (CH - 1), j = idx / CH, r = r0 + ii;
+        if (r < n && j < wd && r >= k0 + j) A[r + (int64_t)(k0 + j) * ld] = (T)sC[ii * PC + j];
+      }
+    }
+  }
+}
+
+// Trailing update C = C - X X^T (or -X X^T when the block starts at zero) of the rows and columns
+// [m, n), X = L[m:n, 0:m], lower 64 x 64 tiles.  Tiles of one matrix go to one XCD (block id mod 8)
+// in consecutive dispatch order, so the matrix's X rows are read from HBM into that XCD's L2 once
+// and shared by its tiles.  Tiles inside [skip0, skip1)^2 are not computed.
+template <typename T>
+__global__ void __launch_bounds__(256) k_pchol_syrk(Tab tb, Ws ws, PArgs a) {
+  constexpr int TM = 64, KC = 16;
+  __shared__ T sA[KC * TM];
+  __shared__ T sB[KC * TM];
+  typedef typename Mma<T>::acc acc_t;
+  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  const int item = (slot / a.ntile) * 8 + xcd, tile = slot % a.ntile;
+  if (item >= a.count) return;
+  int64_t mat;
+  int inst;
+  pitem(tb, a, item, mat, inst);
+  if (block_flag(&ws.flag[inst])) return;
+  int ti = (int)((sqrtf(8.0f * (float)tile + 1.0f) - 1.0f) * 0.5f);
+  while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
+  while (ti * (ti + 1) / 2 > tile) --ti;
+  const int tj = tile - ti * (ti + 1) / 2;
+  const int n = a.n, m = a.m, ld = a.ld;
+  const int R0 = m + TM * ti, C0 = m + TM * tj;
+  if (R0 >= a.skip0 && R0 + TM <= a.skip1 && C0 >= a.skip0 && C0 + TM <= a.skip1) return;
+  T* A = (T*)a.base + mat * a.stride;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, wr = w >> 1, wc = w & 1;
+  acc_t c00 = {0, 0, 0, 0}, c01 = {0, 0, 0, 0}, c10 = {0, 0, 0, 0}, c11 = {0, 0, 0, 0};
+  for (int kc = 0; kc < m; kc += KC) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < (KC * TM) / 256; ++q) {
+      const int idx = t + 256 * q, ii = idx & (TM - 1), kk = idx / TM, k = kc + kk;
+      const int r = R0 + ii, c = C0 + ii;
+      sA[kk * TM + ii] = (r < n && k < m) ? A[r + (int64_t)k * ld] : (T)0;
+      sB[kk * TM + ii] = (c < n && k < m) ? A[c + (int64_t)k * ld] : (T)0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < KC / 4; ++s) {
+      const int kk = 4 * s + (lane >> 4), li = lane & 15;
+      const T a0 = sA[kk * TM + 32 * wr + li], a1 = sA[kk * TM + 32 * wr + 16 + li];
+      const T b0 = sB[kk * TM + 32 * wc + li], b1 = sB[kk * TM + 32 * wc + 16 + li];
+      c00 = Mma<T>::mma(a0, b0, c00);
+      c01 = Mma<T>::mma(a0, b1, c01);
+      c10 = Mma<T>::mma(a1, b0, c10);
+      c11 = Mma<T>::mma(a1, b1, c11);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int rb = R0 + 32 * wr + Mma<T>::row(lane, v), cb = C0 + 32 * wc + (lane & 15);
+    const T vals[4] = {c00[v], c01[v], c10[v], c11[v]};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = rb + 16 * (q >> 1), c = cb + 16 * (q & 1);
+      if (r < n && c < n && r >= c) {
+        T* p = A + r + (int64_t)c * ld;
+        *p = a.zero ? -vals[q] : *p - vals[q];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- cyclic reduction gathers
+// Separator s's local matrix (sbuf, ld Lp): rows [0, ns) its block T_s, [ns, 2 ns) the coupling to
+// its left neighbour E_L(a, q) = K(left_a, s_q), [2 ns, 3 ns) to its right neighbour, [3 ns, Lr) the
+// theta border G_s; columns [0, ns).  After elimination the trailing block (rows and columns from
+// ns) holds -X X^T: C_LL, C_RL (the new coupling between the neighbours), C_RR, C_thL, C_thR.
+template <typename T>
+__device__ inline T& sep_at(const Ws& ws, const BigGeom& G, int64_t es, int r, int c) {
+  return ((T*)ws.sbuf)[es * (int64_t)G.Lp * G.Lp + r + (int64_t)c * G.Lp];
+}
+template <typename T>
+__device__ inline T elem_at(const Ws& ws, const BigGeom& G, int64_t e, int r, int c) {
+  return ((const T*)ws.ebuf)[e * (int64_t)G.Rp * G.Rp + r + (int64_t)c * G.Rp];
+}
+
+// After level 0: every separator's T_s and G_s from the Schur complements of element s (its S
+// block) and element s + 1 (its P block); the couplings of the separators eliminated at level 1.
+template <typename T>
+__global__ void __launch_bounds__(256) k_sep_init(Shape S, Tab tb, Ws ws) {
+  const int64_t es = blockIdx.x;
+  const int inst = tb.elem_inst[es], s = tb.elem_loc[es];
+  if (block_flag(&ws.flag[inst])) return;
+  const int ns = S.ns, np = S.np, b = S.b, mI = S.mI, N = tb.inst_N[inst];
+  const BigGeom G = big_geom(S);
+  const bool nxt = s + 1 < N, elim1 = (s & 1) != 0;
+  const int P0 = b + np;   // first P row of an element
+  for (int idx = tid(); idx < ns * ns; idx += nthr()) {
+    const int q = idx / ns, a = idx - q * ns;   // column q, row a
+    if (a >= q) {
+      double v = (double)elem_at<T>(ws, G, es, mI + a, mI + q);
+      if (nxt) v += (double)elem_at<T>(ws, G, es + 1, P0 + a, P0 + q);
+      sep_at<T>(ws, G, es, a, q) = (T)v;
+    }
+    if (elim1) {
+      sep_at<T>(ws, G, es, ns + a, q) = elem_at<T>(ws, G, es, P0 + a, mI + q);
+      sep_at<T>(ws, G, es, 2 * ns + a, q) = nxt ? elem_at<T>(ws, G, es + 1, P0 + q, mI + a) : (T)0;
+    }
+  }
+  for (int idx = tid(); idx < np * ns; idx += nthr()) {
+    const int q = idx / np, c = idx - q * np;
+    double v = (double)elem_at<T>(ws, G, es, b + c, mI + q);
+    if (nxt) v += (double)elem_at<T>(ws, G, es + 1, P0 + q, b + c);
+    sep_at<T>(ws, G, es, 3 * ns + c, q) = (T)v;
+  }
+}
+
+// Step l (1..L-1): separators t that are multiples of 2^l add the contributions of the
+// separators eliminated at level l on either side (u1 = t - 2^(l-1): t is its right neighbour;
+// u2 = t + 2^(l-1): t is its left neighbour), in that order; those eliminated at level l+1 also
+// take their new couplings.
+template <typename T>
+__global__ void __launch_bounds__(256) k_sep_step(Shape S, Tab tb, Ws ws, int level) {
+  const int it = tb.st_ptr[level - 1] + blockIdx.x;
+  if (it >= tb.st_ptr[level]) return;
+  const int inst = tb.st_inst[it], t = tb.st_s[it];
+  if (block_flag(&ws.flag[inst])) return;
+  const int ns = S.ns, np = S.np, N = tb.inst_N[inst];
+  const BigGeom G = big_geom(S);
+  const int64_t e0 = tb.inst_e0[inst], et = e0 + t;
+  const int half = 1 << (level - 1);
+  const bool h1 = t > 0, h2 = t + half < N;
+  const int64_t u1 = e0 + t - half, u2 = e0 + t + half;
+  const bool elim = ((t >> level) & 1) != 0;
+  const bool right = elim && h2 && t + 2 * half < N;
+  for (int idx = tid(); idx < ns * ns; idx += nthr()) {
+    const int q = idx / ns, a = idx - q * ns;
+    if (a >= q) {
+      double v = (double)sep_at<T>(ws, G, et, a, q);
+      if (h1) v += (double)sep_at<T>(ws, G, u1, 2 * ns + a, 2 * ns + q);
+      if (h2) v += (double)sep_at<T>(ws, G, u2, ns + a, ns + q);
+      sep_at<T>(ws, G, et, a, q) = (T)v;
+    }
+    if (elim) {
+      sep_at<T>(ws, G, et, ns + a, q) = sep_at<T>(ws, G, u1, 2 * ns + q, ns + a);
+      sep_at<T>(ws, G, et, 2 * ns + a, q) = right ? sep_at<T>(ws, G, u2, 2 * ns + a, ns + q) : (T)0;
+    }
+  }
+  for (int idx = tid(); idx < np * ns; idx += nthr()) {
+    const int q = idx / np, c = idx - q * np;
+    double v = (double)sep_at<T>(ws, G, et, 3 * ns + c, q);
+    if (h1) v += (double)sep_at<T>(ws, G, u1, 3 * ns + c, 2 * ns + q);
+    if (h2) v += (double)sep_at<T>(ws, G, u2, 3 * ns + c, ns + q);
+    sep_at<T>(ws, G, et, 3 * ns + c, q) = (T)v;
+  }
+}
+
+// ---------------------------------------------------------------- border
+// theta-theta partials of one 16-element chunk and one 64 x 64 lower tile of the parameter
+// block, in FP64 on matrix cores: sum of the elements' assembled theta blocks minus the products of
+// their transformed theta rows (elements: mI columns each; separators 1.. of the chunk: ns
+// columns each).  grid (chunk, tile, instance).
+template <typename T>
+__global__ void __launch_bounds__(256) k_big_theta(Shape S, Tab tb, Ws ws) {
+  constexpr int TM = 64, KC = 16;
+  __shared__ double sA[KC * TM];
+  __shared__ double sB[KC * TM];
+  const int inst = blockIdx.z, chunk = blockIdx.x, tile = blockIdx.y;
+  if (block_flag(&ws.flag[inst])) return;
+  const int np = S.np, ns = S.ns, b = S.b, mI = S.mI, N = tb.inst_N[inst];
+  const BigGeom G = big_geom(S);
+  const int i0 = chunk * CL_THCHUNK, i1 = min(N, i0 + CL_THCHUNK);
+  if (i0 >= N) return;
+  int ti = (int)((sqrtf(8.0f * (float)tile + 1.0f) - 1.0f) * 0.5f);
+  while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
+  while (ti * (ti + 1) / 2 > tile) --ti;
+  const int tj = tile - ti * (ti + 1) / 2;
+  const int R0 = TM * ti, C0 = TM * tj;
+  const int64_t e0 = tb.inst_e0[inst];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, wr = w >> 1, wc = w & 1;
+  dvec4 c00 = {0, 0, 0, 0}, c01 = {0, 0, 0, 0}, c10 = {0, 0, 0, 0}, c11 = {0, 0, 0, 0};
+  for (int ii = i0; ii < i1; ++ii) {
+    for (int src = 0; src < 2; ++src) {   // the element's theta rows, then separator ii's
+      if (src == 1 && ii == 0) continue;
+      const T* X = src == 0 ? (const T*)ws.ebuf + (e0 + ii) * (int64_t)G.Rp * G.Rp + b
+                            : (const T*)ws.sbuf + (e0 + ii) * (int64_t)G.Lp * G.Lp + 3 * ns;
+      const int ldx = src == 0 ? G.Rp : G.Lp, kn = src == 0 ? mI : ns;
+      for (int kc = 0; kc < kn; kc += KC) {
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < (KC * TM) / 256; ++q) {
+          const int idx = t + 256 * q, r = idx & (TM - 1), kk = idx / TM, k = kc + kk;
+          sA[kk * TM + r] = (R0 + r < np && k < kn) ? (double)X[R0 + r + (int64_t)k * ldx] : 0.0;
+          sB[kk * TM + r] = (C0 + r < np && k < kn) ? (double)X[C0 + r + (int64_t)k * ldx] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < KC / 4; ++s) {
+          const int kk = 4 * s + (lane >> 4), li = lane & 15;
+          const double a0 = sA[kk * TM + 32 * wr + li], a1 = sA[kk * TM + 32 * wr + 16 + li];
+          const double b0 = sB[kk * TM + 32 * wc + li], b1 = sB[kk * TM + 32 * wc + 16 + li];
+          c00 = Mma<double>::mma(a0, b0, c00);
+          c01 = Mma<double>::mma(a0, b1, c01);
+          c10 = Mma<double>::mma(a1, b0, c10);
+          c11 = Mma<double>::mma(a1, b1, c11);
+        }
+      }
+    }
+  }
+  double* out = ws.thred + ((int64_t)inst * ws.nchunk + chunk) * np * np;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int rb = R0 + 32 * wr + Mma<double>::row(lane, v), cb = C0 + 32 * wc + (lane & 15);
+    const double vals[4] = {c00[v], c01[v], c10[v], c11[v]};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = rb + 16 * (q >> 1), c = cb + 16 * (q & 1);
+      if (r < np && c < np && r >= c) {
+        double acc = 0.0;   // the chunk's assembled blocks, element order
+        for (int ii = i0; ii < i1; ++ii) acc += ws.ath[(e0 + ii) * (int64_t)np * np + r * np + c];
+        out[r * np + c] = acc - vals[q];
+      }
+    }
+  }
+}
+
+// Border matrix of each instance (FP64, ld Bp): [T_0 | G_0^T; G_0 | S_thth], where separator 0
+// takes the contributions of the separator eliminated at the last level and S_thth = sum of the
+// chunk partials + Sx + dw.
+template <typename T>
+__global__ void __launch_bounds__(256) k_border_build(Shape S, Tab tb, Ws ws) {
+  const int inst = blockIdx.x;
+  if (block_flag(&ws.flag[inst])) return;
+  const int ns = S.ns, np = S.np, N = tb.inst_N[inst], L = tb.L;
+  const BigGeom G = big_geom(S);
+  const int64_t e0 = tb.inst_e0[inst];
+  const int u = L >= 1 ? (1 << (L - 1)) : N;
+  const bool hu = u < N;
+  double* B = ws.bbuf + (int64_t)inst * G.Bp * G.Bp;
+  for (int idx = tid(); idx < ns * ns; idx += nthr()) {
+    const int q = idx / ns, a = idx - q * ns;
+    if (a < q) continue;
+    double v = (double)sep_at<T>(ws, G, e0, a, q);
+    if (hu) v += (double)sep_at<T>(ws, G, e0 + u, ns + a, ns + q);
+    B[a + (int64_t)q * G.Bp] = v;
+  }
+  for (int idx = tid(); idx < np * ns; idx += nthr()) {
+    const int q = idx / np, c = idx - q * np;
+    double v = (double)sep_at<T>(ws, G, e0, 3 * ns + c, q);
+    if (hu) v += (double)sep_at<T>(ws, G, e0 + u, 3 * ns + c, ns + q);
+    B[ns + c + (int64_t)q * G.Bp] = v;
+  }
+  const int nch = (int)cl_ceil_div(N, CL_THCHUNK);
+  for (int idx = tid(); idx < np * np; idx += nthr()) {
+    const int r = idx / np, c = idx - r * np;
+    if (c > r) continue;
+    const double* src = ws.thred + (int64_t)inst * ws.nchunk * np * np + idx;
+    double acc = 0.0;
+    for (int ch = 0; ch < nch; ++ch) acc += src[(int64_t)ch * np * np];
+    if (r == c) acc += ws.sxdw[inst * np + r];
+    B[ns + r + (int64_t)(ns + c) * G.Bp] = acc;
+  }
+}
+
+// ---------------------------------------------------------------- solves
+// Workgroup-cooperative substitutions with an n x n column-major factor whose first m columns are
+// eliminated: v (LDS, n doubles).  fwd: v[0:m] <- L11^-1 v[0:m], v[m:n] <- v[m:n] - L21 v[0:m].
+// bwd: v[0:m] <- L11^-T (v[0:m] - L21^T v[m:n]).  Diagonal blocks of 64 are staged in LDS and
+// solved by wave 0 with the right-hand side in registers; the other rows or columns are updated
+// by all threads with four independent partial sums.  blk: 64 x 65 doubles of LDS.
+template <typename T>
+__device__ inline void stage_diag(const T* L, int ld, int c0, int bw, double* blk) {
+  for (int idx = tid(); idx < 64 * 64; idx += nthr()) {
+    const int c = idx >> 6, r = idx & 63;
+    blk[r * 65 + c] = (r < bw && c < bw && r >= c) ? (double)L[(c0 + r) + (int64_t)(c0 + c) * ld] : 0.0;
+  }
+}
+
+template <typename T>
+__device__ void blocked_fwd(const T* L, int ld, int m, int n, double* v, double* blk) {
+  for (int c0 = 0; c0 < m; c0 += 64) {
+    const int bw = min(64, m - c0);
+    __syncthreads();
+    stage_diag(L, ld, c0, bw, blk);
+    __syncthreads();
+    if (tid() < 64) {
+      const int lane = tid();
+      double x = lane < bw ? v[c0 + lane] : 0.0;
+      for (int j = 0; j < bw; ++j) {
+        const double xj = __shfl(x, j) / blk[j * 65 + j];
+        if (lane == j) x = xj;
+        if (lane > j && lane < bw) x -= blk[lane * 65 + j] * xj;
+      }
+      if (lane < bw) v[c0 + lane] = x;
+    }
+    __syncthreads();
+    for (int r = c0 + bw + tid(); r < n; r += nthr()) {
+      const T* row = L + r + (int64_t)c0 * ld;
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      int c = 0;
+      for (; c + 4 <= bw; c += 4) {
+        s0 += (double)row[(int64_t)c * ld] * v[c0 + c];
+        s1 += (double)row[(int64_t)(c + 1) * ld] * v[c0 + c + 1];
+        s2 += (double)row[(int64_t)(c + 2) * ld] * v[c0 + c + 2];
+        s3 += (double)row[(int64_t)(c + 3) * ld] * v[c0 + c + 3];
+      }
+      for (; c < bw; ++c) s0 += (double)row[(int64_t)c * ld] * v[c0 + c];
+      v[r] -= (s0 + s1) + (s2 + s3);
+    }
+  }
+  __syncthreads();
+}
+
+// sum over rows r in [r0, r1) of L[r, c] v[r] for columns c in [c0, c0 + cw), subtracted from
+// v[c]: four threads per column (rows interleaved by 4), partial sums combined in a fixed order.
+template <typename T>
+__device__ inline void col_update(const T* L, int ld, int c0, int cw, int r0, int r1, double* v, double* red) {
+  for (int cb = 0; cb < cw; cb += 64) {
+    const int c = cb + (tid() >> 2), part = tid() & 3;
+    double s = 0.0;
+    if (c < cw) {
+      const T* col = L + (int64_t)(c0 + c) * ld;
+      for (int r = r0 + part; r < r1; r += 4) s += (double)col[r] * v[r];
+    }
+    red[tid()] = s;
+    __syncthreads();
+    if (part == 0 && c < cw) v[c0 + c] -= (red[tid()] + red[tid() + 1]) + (red[tid() + 2] + red[tid() + 3]);
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__device__ void blocked_bwd(const T* L, int ld, int m, int n, double* v, double* blk, double* red) {
+  __syncthreads();
+  col_update(L, ld, 0, m, m, n, v, red);
+  for (int c0 = ((m - 1) / 64) * 64; c0 >= 0; c0 -= 64) {
+    const int bw = min(64, m - c0);
+    col_update(L, ld, c0, bw, c0 + bw, m, v, red);
+    stage_diag(L, ld, c0, bw, blk);
+    __syncthreads();
+    if (tid() < 64) {
+      const int lane = tid();
+      double x = lane < bw ? v[c0 + lane] : 0.0;
+      for (int j = bw - 1; j >= 0; --j) {
+        const double xj = __shfl(x, j) / blk[j * 65 + j];
+        if (lane == j) x = xj;
+        if (lane < j) x -= blk[j * 65 + lane] * xj;
+      }
+      if (lane < bw) v[c0 + lane] = x;
+    }
+    __syncthreads();
+  }
+}
+
+// Element forward: v = [r_I | 0] -> [y_I | -X y_I] kept in evec (theta and P parts included).
+template <typename T>
+__global__ void __launch_bounds__(256) k_big_fwd(Shape S, Tab tb, Ws ws, const double* __restrict__ rhs) {
+  extern __shared__ double lds[];
+  const int64_t e = blockIdx.x;
+  const int inst = tb.elem_inst[e], i = tb.elem_loc[e];
+  if (block_flag(&ws.flag[inst])) return;
+  const BigGeom G = big_geom(S);
+  const int R = S.R, mI = S.mI;
+  double* v = lds;
+  double* blk = v + G.Rp;
+  const double* r = rhs + tb.inst_x[inst] + (int64_t)i * S.b;
+  for (int q = tid(); q < R; q += nthr()) v[q] = q < mI ? r[q] : 0.0;
+  blocked_fwd((const T*)ws.ebuf + e * (int64_t)G.Rp * G.Rp, G.Rp, mI, R, v, blk);
+  for (int q = tid(); q < R; q += nthr()) ws.evec[e * (int64_t)G.Rp + q] = v[q];
+}
+
+// Separator right-hand sides after level 0: r_s = rhs(node K of element s) - X_S y (element s)
+// - X_P y (element s + 1).
+__global__ void k_big_seprhs(Shape S, Tab tb, Ws ws, const double* __restrict__ rhs) {
+  const int64_t es = blockIdx.x;
+  const int inst = tb.elem_inst[es], s = tb.elem_loc[es];
+  if (block_flag(&ws.flag[inst])) return;
+  const BigGeom G = big_geom(S);
+  const int ns = S.ns, N = tb.inst_N[inst], P0 = S.b + S.np;
+  for (int a = tid(); a < ns; a += nthr()) {
+    double v = rhs[tb.inst_x[inst] + (int64_t)s * S.b + S.mI + a] + ws.evec[es * (int64_t)G.Rp + S.mI + a];
+    if (s + 1 < N) v += ws.evec[(es + 1) * (int64_t)G.Rp + P0 + a];
+    ws.rcur[es * ns + a] = v;
+  }
+}
+
+// Cyclic-reduction forward of the separators eliminated at `level`: y = L_s^-1 r_s and their
+// contributions -X y to the neighbours and theta (svec).
+template <typename T>
+__global__ void __launch_bounds__(256) k_big_crf(Shape S, Tab tb, Ws ws, int level) {
+  extern __shared__ double lds[];
+  const int it = tb.cr_ptr[level - 1] + blockIdx.x;
+  if (it >= tb.cr_ptr[level]) return;
+  const int inst = tb.cr_inst[it];
+  if (block_flag(&ws.flag[inst])) return;
+  const BigGeom G = big_geom(S);
+  const int ns = S.ns;
+  const int64_t es = tb.inst_e0[inst] + tb.cr_j[it];
+  double* v = lds;
+  double* blk = v + G.Lp;
+  for (int q = tid(); q < G.Lr; q += nthr()) v[q] = q < ns ? ws.rcur[es * ns + q] : 0.0;
+  blocked_fwd((const T*)ws.sbuf + es * (int64_t)G.Lp * G.Lp, G.Lp, ns, G.Lr, v, blk);
+  for (int q = tid(); q < G.Lr; q += nthr()) ws.svec[es * (int64_t)G.Lp + q] = v[q];
+}
+
+// Right-hand sides of the separators that are multiples of 2^l after level l: add the
+// contributions of the separators eliminated at level l on either side.
+__global__ void k_big_crs(Shape S, Tab tb, Ws ws, int level) {
+  const int it = tb.st_ptr[level - 1] + blockIdx.x;
+  if (it >= tb.st_ptr[level]) return;
+  const int inst = tb.st_inst[it], t = tb.st_s[it];
+  if (block_flag(&ws.flag[inst])) return;
+  const BigGeom G = big_geom(S);
+  const int ns = S.ns, N = tb.inst_N[inst], half = 1 << (level - 1);
+  const int64_t e0 = tb.inst_e0[inst], et = e0 + t;
+  for (int a = tid(); a < ns; a += nthr()) {
+    double v = ws.rcur[et * ns + a];
+    if (t > 0) v += ws.svec[(et - half) * (int64_t)G.Lp + 2 * ns + a];
+    if (t + half < N) v += ws.svec[(et + half) * (int64_t)G.Lp + ns + a];
+    ws.rcur[et * ns + a] = v;
+  }
+}
+
+// theta right-hand-side partials over 16-element chunks (fixed order): the elements'
+// contributions, the eliminated separators' contributions and the optional per-element partials.
+__global__ void k_big_thv(Shape S, Tab tb, Ws ws, const double* __restrict__ rthp) {
+  const int inst = blockIdx.y, chunk = blockIdx.x;
+  if (block_flag(&ws.flag[inst])) return;
+  const BigGeom G = big_geom(S);
+  const int np = S.np, ns = S.ns, N = tb.inst_N[inst];
+  const int i0 = chunk * CL_THCHUNK, i1 = min(N, i0 + CL_THCHUNK);
+  const int64_t e0 = tb.inst_e0[inst];
+  for (int c = tid(); c < np; c += nthr()) {
+    double acc = 0.0;
+    for (int ii = i0; ii < i1; ++ii) {
+      acc += ws.evec[(e0 + ii) * (int64_t)G.Rp + S.b + c];
+      if (rthp) acc += rthp[(e0 + ii) * np + c];
+      if (ii > 0) acc += ws.svec[(e0 + ii) * (int64_t)G.Lp + 3 * ns + c];
+    }
+    ws.thv[((int64_t)inst * ws.nchunk + chunk) * np + c] = acc;
+  }
+}
+
+// Border solve: [separator 0 | theta] with the border factor; x_theta into dx, x_0 into xsep.
+__global__ void __launch_bounds__(256) k_big_border_solve(Shape S, Tab tb, Ws ws, const double* __restrict__ rhs,
+                                                          double* __restrict__ dx) {
+  extern __shared__ double lds[];
+  const int inst = blockIdx.x;
+  if (block_flag(&ws.flag[inst])) return;
+  const BigGeom G = big_geom(S);
+  const int ns = S.ns, np = S.np, N = tb.inst_N[inst], L = tb.L;
+  const int64_t e0 = tb.inst_e0[inst], xt = tb.inst_x[inst] + (int64_t)N * S.b;
+  const int u = L >= 1 ? (1 << (L - 1)) : N;
+  double* v = lds;
+  double* blk = v + G.Bp;
+  double* red = blk + 64 * 65;
+  const int nch = (int)cl_ceil_div(N, CL_THCHUNK);
+  for (int q = tid(); q < G.Br; q += nthr()) {
+    double x;
+    if (q < ns) {
+      x = ws.rcur[e0 * ns + q];
+      if (u < N) x += ws.svec[(e0 + u) * (int64_t)G.Lp + ns + q];
+    } else {
+      const int c = q - ns;
+      x = rhs[xt + c];
+      for (int ch = 0; ch < nch; ++ch) x += ws.thv[((int64_t)inst * ws.nchunk + ch) * np + c];
+    }
+    v[q] = x;
+  }
+  const double* B = ws.bbuf + (int64_t)inst * G.Bp * G.Bp;
+  blocked_fwd(B, G.Bp, G.Br, G.Br, v, blk);
+  blocked_bwd(B, G.Bp, G.Br, G.Br, v, blk, red);
+  for (int q = tid(); q < G.Br; q += nthr()) {
+    if (q < ns) ws.xsep[e0 * ns + q] = v[q];
+    else dx[xt + q - ns] = v[q];
+  }
+}
+
+// Cyclic-reduction backward of level l: x_s = L_s^-T (y_s - X^T [x_left; x_right; x_theta]).
+template <typename T>
+__global__ void __launch_bounds__(256) k_big_crb(Shape S, Tab tb, Ws ws, int level, const double* __restrict__ dx) {
+  extern __shared__ double lds[];
+  const int it = tb.cr_ptr[level - 1] + blockIdx.x;
+  if (it >= tb.cr_ptr[level]) return;
+  const int inst = tb.cr_inst[it], s = tb.cr_j[it];
+  if (block_flag(&ws.flag[inst])) return;
+  const BigGeom G = big_geom(S);
+  const int ns = S.ns, np = S.np, N = tb.inst_N[inst], half = 1 << (level - 1);
+  const int64_t e0 = tb.inst_e0[inst], es = e0 + s;
+  const int64_t xt = tb.inst_x[inst] + (int64_t)N * S.b;
+  double* v = lds;
+  double* blk = v + G.Lp;
+  double* red = blk + 64 * 65;
+  for (int q = tid(); q < G.Lr; q += nthr()) {
+    double x;
+    if (q < ns) x = ws.svec[es * (int64_t)G.Lp + q];
+    else if (q < 2 * ns) x = ws.xsep[(es - half) * ns + q - ns];
+    else if (q < 3 * ns) x = (s + half < N) ? ws.xsep[(es + half) * ns + q - 2 * ns] : 0.0;
+    else x = dx[xt + q - 3 * ns];
+    v[q] = x;
+  }
+  blocked_bwd((const T*)ws.sbuf + es * (int64_t)G.Lp * G.Lp, G.Lp, ns, G.Lr, v, blk, red);
+  for (int q = tid(); q < ns; q += nthr()) ws.xsep[es * ns + q] = v[q];
+}
+
+// Element backward: x_I = L_II^-T (y_I - X^T [x_S; x_theta; x_P]); dx of the element's nodes.
+template <typename T>
+__global__ void __launch_bounds__(256) k_big_bwd(Shape S, Tab tb, Ws ws, double* __restrict__ dx) {
+  extern __shared__ double lds[];
+  const int64_t e = blockIdx.x;
+  const int inst = tb.elem_inst[e], i = tb.elem_loc[e];
+  if (block_flag(&ws.flag[inst])) return;
+  const BigGeom G = big_geom(S);
+  const int ns = S.ns, np = S.np, b = S.b, mI = S.mI, R = S.R, N = tb.inst_N[inst];
+  const int64_t xo = tb.inst_x[inst], xt = xo + (int64_t)N * b;
+  double* v = lds;
+  double* blk = v + G.Rp;
+  double* red = blk + 64 * 65;
+  for (int q = tid(); q < R; q += nthr()) {
+    double x;
+    if (q < mI) x = ws.evec[e * (int64_t)G.Rp + q];
+    else if (q < b) x = ws.xsep[e * ns + q - mI];
+    else if (q < b + np) x = dx[xt + q - b];
+    else x = i > 0 ? ws.xsep[(e - 1) * ns + q - b - np] : 0.0;
+    v[q] = x;
+  }
+  blocked_bwd((const T*)ws.ebuf + e * (int64_t)G.Rp * G.Rp, G.Rp, mI, R, v, blk, red);
+  double* out = dx + xo + (int64_t)i * b;
+  for (int q = tid(); q < b; q += nthr()) out[q] = v[q];
+}
+
+// ---------------------------------------------------------------- launches
+static inline int ok_or() { return hipGetLastError() == hipSuccess ? 0 : -3; }
+
+static PArgs pargs(void* base, int64_t stride, int ld, int n, int m, int count, int mode, int level) {
+  PArgs a;
+  a.base = base;
+  a.stride = stride;
+  a.ld = ld;
+  a.n = n;
+  a.m = m;
+  a.count = count;
+  a.mode = mode;
+  a.level = level;
+  a.zero = 0;
+  a.skip0 = a.skip1 = 0;
+  const int nt = (int)cl_ceil_div(n - m, 64);
+  a.ntile = nt * (nt + 1) / 2;
+  return a;
+}
+
+template <typename T>
+static void syrk(const Tab& tb, const Ws& ws, PArgs a, hipStream_t st) {
+  if (a.count == 0 || a.ntile == 0) return;
+  const unsigned grid = (unsigned)(cl_ceil_div(a.count, 8) * 8 * a.ntile);
+  hipLaunchKernelGGL(k_pchol_syrk<T>, dim3(grid), dim3(256), 0, st, tb, ws, a);
+}
+
+template <typename T>
+static int big_factor_t(const Shape& S, const Tab& tb, const HostPlan& hp, const Ws& ws, phase_cb cb,
+                        void* ctx, hipStream_t st) {
+  const BigGeom G = big_geom(S);
+  const int E = (int)tb.n_elem;
+  const int64_t esz = (int64_t)G.Rp * G.Rp, ssz = (int64_t)G.Lp * G.Lp;
+  if (cb) cb(ctx, 1, 1, st);
+  hipLaunchKernelGGL(k_big_asm<T>, dim3(E), dim3(256), big_asm_lds(S), st, S, tb, ws);
+  PArgs ea = pargs(ws.ebuf, esz, G.Rp, S.R, S.mI, E, 0, 0);
+  hipLaunchKernelGGL(k_pchol_panel<T>, dim3(E), dim3(256), 0, st, tb, ws, ea);
+  // the theta-theta block is formed by k_big_theta; its tiles here are skipped
+  ea.skip0 = S.b;
+  ea.skip1 = S.b + S.np;
+  syrk<T>(tb, ws, ea, st);
+  if (cb) cb(ctx, 1, 0, st);
+  if (cb) cb(ctx, 2, 1, st);
+  hipLaunchKernelGGL(k_sep_init<T>, dim3(E), dim3(256), 0, st, S, tb, ws);
+  for (int l = 1; l <= tb.L; ++l) {
+    if (l > 1 && hp.st[l - 1] > 0)
+      hipLaunchKernelGGL(k_sep_step<T>, dim3(hp.st[l - 1]), dim3(256), 0, st, S, tb, ws, l - 1);
+    const int cnt = hp.lvl[l];
+    if (cnt == 0) continue;
+    PArgs ca = pargs(ws.sbuf, ssz, G.Lp, G.Lr, S.ns, cnt, 1, l);
+    hipLaunchKernelGGL(k_pchol_panel<T>, dim3(cnt), dim3(256), 0, st, tb, ws, ca);
+    ca.zero = 1;
+    ca.skip0 = 3 * S.ns;
+    ca.skip1 = G.Lr;
+    syrk<T>(tb, ws, ca, st);
+  }
+  if (cb) cb(ctx, 2, 0, st);
+  if (cb) cb(ctx, 3, 1, st);
+  const int nt = (int)cl_ceil_div(S.np, 64);
+  if (nt > 0)
+    hipLaunchKernelGGL(k_big_theta<T>, dim3(ws.nchunk, nt * (nt + 1) / 2, tb.n_inst), dim3(256), 0, st, S, tb, ws);
+  hipLaunchKernelGGL(k_border_build<T>, dim3(tb.n_inst), dim3(256), 0, st, S, tb, ws);
+  PArgs ba = pargs(ws.bbuf, (int64_t)G.Bp * G.Bp, G.Bp, G.Br, G.Br, tb.n_inst, 2, 0);
+  hipLaunchKernelGGL(k_pchol_panel<double>, dim3(tb.n_inst), dim3(256), 0, st, tb, ws, ba);
+  if (cb) cb(ctx, 3, 0, st);
+  return ok_or();
+}
+
+int launch_factor_big(const Shape& S, const Tab& tb, const HostPlan& hp, const Ws& ws, int prec,
+                      phase_cb cb, void* ctx, hipStream_t st) {
+  return prec ? big_factor_t<float>(S, tb, hp, ws, cb, ctx, st) : big_factor_t<double>(S, tb, hp, ws, cb, ctx, st);
+}
+
+size_t big_solve_lds(const Shape& S) {
+  const BigGeom G = big_geom(S);
+  const int nv = std::max(G.Rp, std::max(G.Lp, G.Bp));
+  return sizeof(double) * ((size_t)nv + 64 * 65 + 256);
+}
+
+template <typename T>
+static int big_solve_t(const Shape& S, const Tab& tb, const HostPlan& hp, const Ws& ws, const double* rhs,
+                       const double* rthp, double* dx, phase_cb cb, void* ctx, hipStream_t st) {
+  const size_t lds = big_solve_lds(S);
+  const int E = (int)tb.n_elem;
+  if (cb) cb(ctx, 4, 1, st);
+  hipLaunchKernelGGL(k_big_fwd<T>, dim3(E), dim3(256), lds, st, S, tb, ws, rhs);
+  hipLaunchKernelGGL(k_big_seprhs, dim3(E), dim3(64), 0, st, S, tb, ws, rhs);
+  for (int l = 1; l <= tb.L; ++l) {
+    if (l > 1 && hp.st[l - 1] > 0)
+      hipLaunchKernelGGL(k_big_crs, dim3(hp.st[l - 1]), dim3(64), 0, st, S, tb, ws, l - 1);
+    if (hp.lvl[l] > 0) hipLaunchKernelGGL(k_big_crf<T>, dim3(hp.lvl[l]), dim3(256), lds, st, S, tb, ws, l);
+  }
+  hipLaunchKernelGGL(k_big_thv, dim3(ws.nchunk, tb.n_inst), dim3(64), 0, st, S, tb, ws, rthp);
+  hipLaunchKernelGGL(k_big_border_solve, dim3(tb.n_inst), dim3(256), lds, st, S, tb, ws, rhs, dx);
+  for (int l = tb.L; l >= 1; --l)
+    if (hp.lvl[l] > 0) hipLaunchKernelGGL(k_big_crb<T>, dim3(hp.lvl[l]), dim3(256), lds, st, S, tb, ws, l, dx);
+  hipLaunchKernelGGL(k_big_bwd<T>, dim3(E), dim3(256), lds, st, S, tb, ws, dx);
+  if (cb) cb(ctx, 4, 0, st);
+  return ok_or();
+}
+
+int launch_solve_big(const Shape& S, const Tab& tb, const HostPlan& hp, const Ws& ws, const double* rhs,
+                     const double* rthp, double* dx, phase_cb cb, void* ctx, hipStream_t st) {
+  return ws.prec ? big_solve_t<float>(S, tb, hp, ws, rhs, rthp, dx, cb, ctx, st)
+                 : big_solve_t<double>(S, tb, hp, ws, rhs, rthp, dx, cb, ctx, st);
+}
+
+// Dynamic LDS above 64 KiB must be declared per kernel.
+int big_prepare_attrs(const Shape& S) {
+  const size_t a = big_asm_lds(S), s = big_solve_lds(S);
+  int rc = 0;
+  auto set = [&](const void* fn, size_t bytes) {
+    if (bytes > 64 * 1024 && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
+      rc = -1;
+  };
+  set((const void*)k_big_asm<double>, a);
+  set((const void*)k_big_asm<float>, a);
+  for (const void* fn : {(const void*)k_big_fwd<double>, (const void*)k_big_fwd<float>, (const void*)k_big_crf<double>,
+                         (const void*)k_big_crf<float>, (const void*)k_big_crb<double>, (const void*)k_big_crb<float>,
+                         (const void*)k_big_bwd<double>, (const void*)k_big_bwd<float>, (const void*)k_big_border_solve})
+    set(fn, s);
+  return rc;
+}
+
+}  // namespace cl

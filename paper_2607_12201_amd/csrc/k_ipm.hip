@@ -758,6 +758,23 @@ size_t ipm_eval_lds(const Shape& S, int nt) {
   return sizeof(double) * (5 * S.b + 2 * S.ns + S.np * 2 + S.nr + 4 * S.K * S.nr + nt);
 }
 
+size_t ipm_trial_lds(const Shape& S, int max_ls) {
+  return sizeof(double) * (4 * (size_t)S.b + 2 * S.ns + 2 * S.np + (size_t)max_ls * S.nr + 3 * 256);
+}
+
+// Dynamic LDS above 64 KiB (large networks) is declared for the evaluation and trial kernels.
+int ipm_prepare_attrs(const Shape& S) {
+  int rc = 0;
+  const size_t ev = ipm_eval_lds(S, elem_threads(S)), tr = ipm_trial_lds(S, CL_MAX_LS);
+  if (ev > 64 * 1024 &&
+      hipFuncSetAttribute((const void*)k_ipm_eval, hipFuncAttributeMaxDynamicSharedMemorySize, (int)ev) != hipSuccess)
+    rc = -1;
+  if (tr > 64 * 1024 &&
+      hipFuncSetAttribute((const void*)k_ipm_trial, hipFuncAttributeMaxDynamicSharedMemorySize, (int)tr) != hipSuccess)
+    rc = -1;
+  return rc;
+}
+
 // FP32_IR helpers.  Materialise the theta part of the condensed right-hand side (barrier terms
 // already in st.rhs plus the element partials, fixed order) so the refinement residual sees it.
 // An instance that once needed the FP64 fallback stays on FP64 factors: its later iterations
@@ -842,9 +859,7 @@ int launch_ipm_step(const Shape& S, const Tab& tb, const HostPlan& hp, const Ipm
   hipLaunchKernelGGL(k_ipm_steplen, dim3(tb.n_inst), dim3(256), 0, s, S, tb, st, ws, o);
   if (cb) cb(ctx, COLLOC_PH_STEP, 0, s);
   if (cb) cb(ctx, COLLOC_PH_LINESEARCH, 1, s);
-  hipLaunchKernelGGL(k_ipm_trial, dim3(ne), dim3(256),
-                     sizeof(double) * (4 * S.b + 2 * S.ns + 2 * S.np + o.max_ls * S.nr + 3 * 256), s,
-                     S, tb, st, ws, o);
+  hipLaunchKernelGGL(k_ipm_trial, dim3(ne), dim3(256), ipm_trial_lds(S, o.max_ls), s, S, tb, st, ws, o);
   hipLaunchKernelGGL(k_ipm_select, dim3(tb.n_inst), dim3(256), 0, s, S, tb, st, ws, o);
   hipLaunchKernelGGL(k_ipm_update, dim3(ne), dim3(nt), 0, s, S, tb, st, ws, o);
   if (cb) cb(ctx, COLLOC_PH_LINESEARCH, 0, s);

@@ -265,6 +265,45 @@ __global__ void __launch_bounds__(256) k_assemble(Shape S, Tab tb, Ws ws, const 
   for (int t = tid(); t < np; t += nthr()) ws.rthp[e * np + t] = -outth[t];
 }
 
+// kkt_assemble on the tiled path: the derivative values, Ds and dw are stored for the factor
+// (which assembles the element matrices from them) and the matrix-free product; the z part of the
+// right-hand side per element, its theta partials to rthp.
+__global__ void __launch_bounds__(256) k_assemble_rhs(Shape S, Tab tb, Ws ws, const double* __restrict__ jac,
+                                                      const double* __restrict__ hess, const double* __restrict__ sigma_s,
+                                                      const double* __restrict__ delta_w, const double* __restrict__ r_x,
+                                                      const double* __restrict__ r_s, const double* __restrict__ r_y,
+                                                      double* __restrict__ rhs) {
+  extern __shared__ double lds_raw[];
+  const int64_t e = blockIdx.x;
+  const int inst = tb.elem_inst[e], i = tb.elem_loc[e];
+  const int N = tb.inst_N[inst];
+  const double h = tb.elem_h[e];
+  const int ns = S.ns, np = S.np, b = S.b;
+  const double dw = delta_w[inst];
+  const int64_t gi = tb.inst_g[inst] + (int64_t)i * b;
+  const int64_t xi = tb.inst_x[inst] + (int64_t)i * b;
+  const int64_t jl = (int64_t)S.K * S.nr;
+  for (int t = tid(); t < jl * 3; t += nthr()) ws.jac[e * jl * 3 + t] = jac[e * jl * 3 + t];
+  for (int t = tid(); t < jl * 4; t += nthr()) ws.hess[e * jl * 4 + t] = hess[e * jl * 4 + t];
+  for (int t = tid(); t < b; t += nthr()) ws.Ds[gi + t] = sigma_s[gi + t] + dw;
+  if (i == 0 && tid() == 0) ws.dw[inst] = dw;
+  double* w = lds_raw;
+  double* wn = w + b;
+  double* phi = wn + ns;
+  double* outz = phi + S.K * S.nr;
+  double* outth = outz + b;
+  for (int t = tid(); t < b; t += nthr()) w[t] = (sigma_s[gi + t] + dw) * r_y[gi + t] + r_s[gi + t];
+  if (i + 1 < N)
+    for (int t = tid(); t < ns; t += nthr()) wn[t] = (sigma_s[gi + b + t] + dw) * r_y[gi + b + t] + r_s[gi + b + t];
+  __syncthreads();
+  reaction_weights(S, tb, inst, w, phi);
+  __syncthreads();
+  jtu_rows(S, tb, inst, h, jac + e * jl * 3, w, (i + 1 < N) ? wn : nullptr, phi, outz, outth);
+  __syncthreads();
+  for (int t = tid(); t < b; t += nthr()) rhs[xi + t] = -r_x[xi + t] - outz[t];
+  for (int t = tid(); t < np; t += nthr()) ws.rthp[e * np + t] = -outth[t];
+}
+
 // rhs theta part: -r_x(theta) + sum_e partials (fixed order); sigma_x + dw kept for the border.
 __global__ void k_rhs_theta(Shape S, Tab tb, Ws ws, const double* __restrict__ r_x,
                             const double* __restrict__ sigma_x, const double* __restrict__ delta_w,
@@ -963,7 +1002,10 @@ int launch_assemble(const Shape& S, const Tab& tb, const Ws& ws, const double* j
   size_t lds = level0_lds_bytes(S, ws.prec);
   size_t lds_rhs = sizeof(double) * (2 * S.b + S.ns + S.K * S.nr + S.np);
   if (lds_rhs > lds) lds = lds_rhs;
-  if (ws.prec)
+  if (S.big)
+    hipLaunchKernelGGL(k_assemble_rhs, dim3((unsigned)tb.n_elem), dim3(256), lds_rhs, st, S, tb, ws, jac, hess,
+                       sigma_s, delta_w, r_x, r_s, r_y, rhs);
+  else if (ws.prec)
     hipLaunchKernelGGL(k_assemble<float>, dim3((unsigned)tb.n_elem), dim3(nt), lds, st, S, tb, ws,
                        jac, hess, sigma_s, delta_w, r_x, r_s, r_y, rhs);
   else
@@ -1000,6 +1042,8 @@ static int factor_t(const Shape& S, const Tab& tb, const HostPlan& hp, const Ws&
 
 int launch_factor_nc(const Shape& S, const Tab& tb, const HostPlan& hp, const Ws& ws, int prec,
                      bool fused, phase_cb cb, void* ctx, hipStream_t st) {
+  // the tiled path always assembles from the stored derivative values (its own kernel)
+  if (S.big) return launch_factor_big(S, tb, hp, ws, prec, cb, ctx, st);
   return prec ? factor_t<float>(S, tb, hp, ws, fused, cb, ctx, st)
               : factor_t<double>(S, tb, hp, ws, fused, cb, ctx, st);
 }
@@ -1041,6 +1085,7 @@ static int solve_t(const Shape& S, const Tab& tb, const HostPlan& hp, const Ws& 
 int launch_solve_p(const Shape& S, const Tab& tb, const HostPlan& hp, const Ws& ws,
                    const double* rhs, const double* rthp, double* dx, phase_cb cb, void* ctx,
                    hipStream_t st) {
+  if (S.big) return launch_solve_big(S, tb, hp, ws, rhs, rthp, dx, cb, ctx, st);
   return ws.prec ? solve_t<float>(S, tb, hp, ws, rhs, rthp, dx, cb, ctx, st)
                  : solve_t<double>(S, tb, hp, ws, rhs, rthp, dx, cb, ctx, st);
 }

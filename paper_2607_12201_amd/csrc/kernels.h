@@ -67,5 +67,14 @@ int launch_matvec(const Shape& S, const Tab& tb, const Ws& ws, const double* v, 
                   hipStream_t st);
 int launch_copy_flags(const Tab& tb, const Ws& ws, int* info, hipStream_t st);
 
+// Tiled matrix-core path (Shape::big), k_big.hip.
+int launch_factor_big(const Shape& S, const Tab& tb, const HostPlan& hp, const Ws& ws, int prec,
+                      phase_cb cb, void* ctx, hipStream_t st);
+int launch_solve_big(const Shape& S, const Tab& tb, const HostPlan& hp, const Ws& ws, const double* rhs,
+                     const double* rthp, double* dx, phase_cb cb, void* ctx, hipStream_t st);
+size_t big_asm_lds(const Shape& S);
+size_t big_solve_lds(const Shape& S);
+int big_prepare_attrs(const Shape& S);
+
 
 }  // namespace cl

@@ -1,5 +1,7 @@
 """Shared helpers of the GPU parity tests: seeded states and oracle references.
 Inputs and expected values come from the generator and the oracle only."""
+import contextlib
+import os
 import sys
 
 import numpy as np
@@ -34,6 +36,27 @@ CASES = {
     "interior_tau": lambda: workloads.random_network(7, n_s=5, n_r=9, N=12, n_obs=2, n_times=12,
                                                      n_fixed=1, meas_tau=0.37),
 }
+
+
+@contextlib.contextmanager
+def factor_path(path):
+    """Handles created inside use this factorization path ("tiled" or "register")."""
+    old = os.environ.get("COLLOC_FACTOR_PATH")
+    os.environ["COLLOC_FACTOR_PATH"] = path
+    try:
+        yield
+    finally:
+        if old is None:
+            os.environ.pop("COLLOC_FACTOR_PATH", None)
+        else:
+            os.environ["COLLOC_FACTOR_PATH"] = old
+
+
+def net100(seed, N):
+    """The 100-species, 250-reaction, 200-parameter stiff network on a short mesh (one
+    measurement time per element)."""
+    return workloads.random_network(seed, n_s=100, n_r=250, N=N, n_obs=20, n_times=N, klo=1e-3, khi=1e4,
+                                    n_fixed=50, stiff=True)
 
 
 def random_state(m, rng, tau_r=1.0, yscale=0.1):

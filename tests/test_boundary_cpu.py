@@ -148,9 +148,33 @@ def test_create_rejects_bad_input(lib, case):
     assert not h.value
 
 
-def test_create_reports_unsupported_shapes(lib):
+def _synthetic(n_s, n_r, N=2, seed=0):
+    """A structurally valid instance without simulated data (host validation only)."""
+    rng = np.random.default_rng(seed)
+    react = rng.integers(-1, n_s, size=(n_r, 2)).astype(np.int32)
+    react[:, 0] = rng.integers(0, n_s, size=n_r)
+    prod = rng.integers(0, n_s, size=(n_r, 2)).astype(np.int32)
+    return dict(n_s=n_s, n_r=n_r, n_p=n_r, N=N, react=react, prod=prod, param=np.arange(n_r, dtype=np.int32),
+                logk_fixed=np.zeros(n_r), h=np.full(N, 0.1), z0=np.ones(n_s), meas_elem=np.zeros(1, np.int32),
+                meas_species=np.zeros(1, np.int32), meas_tau=np.ones(1), meas_y=np.ones(1),
+                meas_sigma=np.ones(1), theta_lo=np.full(n_r, -5.0), theta_hi=np.full(n_r, 5.0))
+
+
+def test_create_picks_the_tiled_path_for_large_blocks(lib, monkeypatch):
+    # 60 species, 60 parameters: 360-row element blocks, beyond the register-resident kernels;
+    # accepted (tiled path) unless the register path is demanded
     inst = workloads.random_network(0, n_s=60, n_r=60, N=4, n_obs=2, n_times=2)
     rc, h = _create(lib, [inst])
+    assert rc == colloc.OK
+    lib.colloc_destroy(h)
+    monkeypatch.setenv("COLLOC_FACTOR_PATH", "register")
+    rc, h = _create(lib, [inst])
+    assert rc == colloc.EUNSUPPORTED
+
+
+def test_create_reports_unsupported_shapes(lib):
+    # 3000 reactions: the line-search trial kernel's per-candidate rate constants exceed LDS
+    rc, h = _create(lib, [_synthetic(40, 3000)])
     assert rc == colloc.EUNSUPPORTED
 
 
