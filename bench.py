@@ -1,12 +1,15 @@
 """Benchmark: interior-point Newton steps per second on one MI355X.
 
-Workload: random mass-action network, 20 species, 40 reactions, 40 log-rate parameters,
-N = 1000 Radau finite elements with K = 3 (80,040 variables), FP64, one instance.  A step is
-one full ipm_step (evaluation + derivatives, assembly, factorization with inertia retries,
-solve, line search, update) with all inputs resident in HBM.  value = Newton steps completed
-per second over the timed region.  The level-0 factorization kernel (fused assembly and
-static condensation of every element) is timed with HIP events on the library's stream for
-the roofline line; the CPU oracle's Newton step is timed on a bounded sample for context.
+Default workload: the stiff random mass-action network with 100 species, 250 reactions (200 rate
+constants estimated, 50 known), 20 observed species at 200 times, N = 10,000 Radau finite
+elements with K = 3 (4,000,200 variables), one instance, FP64.  A step is one full ipm_step
+(evaluation and derivatives, assembly, factorization with inertia retries, solve, line search,
+update) replayed from a captured HIP graph with every input resident in HBM; value = Newton
+iterations completed per second over the timed region (an inertia-correction retry is a step
+that completes no iteration).  The same steps then run with FP32 block factors + FP64 refinement
+(the mixed-precision form) and eagerly with the library's per-phase HIP events, which give the
+per-kernel times for the roofline line and the per-step latency percentiles.  The CPU oracle's
+Newton step is timed on a bounded sample for context.
 """
 from __future__ import annotations
 
@@ -24,47 +27,58 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 (vector and matrix), 256 CU x 2.4 GHz x 128 flop/clk
 PEAK_HBM_GBS = 8000.0
 
-# HBM bytes per launch of the element kernel at this workload, per thread grid, from FETCH_SIZE and
-# WRITE_SIZE counter passes scaled by a 256 MiB calibration copy (profiles/level0_*_traffic.md).
-# An entry holds only for the kernel source it was taken on (fingerprint of the shared headers
-# and the translation unit that instantiates that grid).
-L0_COMMON = ["level0_impl.h", "regchol.h", "elem.h", "common.h", "kernels.h"]
-L0_TRAFFIC = {20: {"tu": "k_level0_u.hip", "sha": "0cefb2fdc47464c9", "bytes": 113392642.0}}
+WORKLOADS = {
+    "net100_n10000": "stiff random mass-action network, 100 species, 250 reactions (200 estimated), "
+                     "200 params, 20 observables at 200 times, N=10000 Radau elements K=3 "
+                     "(4,000,200 variables), one instance",
+    "net20_n1000": "random mass-action network, 20 species, 40 reactions, 40 params, N=1000 Radau "
+                   "elements K=3 (80,040 variables), one instance",
+}
 
 
-def level0_traffic(tile):
-    import hashlib
-    ent = L0_TRAFFIC.get(tile)
-    if ent is None:
-        return None
-    h = hashlib.sha256()
-    for n in L0_COMMON + [ent["tu"]]:
-        with open(os.path.join(ROOT, "paper_2607_12201_amd", "csrc", n), "rb") as f:
-            h.update(f.read())
-    return ent["bytes"] if h.hexdigest()[:16] == ent["sha"] else None
+def make_instance(name, N=None):
+    from paper_2607_12201_amd import workloads
+    if name == "net100_n10000":
+        if N is None:
+            return workloads.stiff_network(0)
+        # the same network (seed, reactions, rates, initial state) on a shorter mesh
+        return workloads.random_network(0, n_s=100, n_r=250, N=N, n_obs=20, n_times=N, klo=1e-3, khi=1e4,
+                                        n_fixed=50, stiff=True)
+    return workloads.random_network(0, N=N or 1000, n_times=50 if (N or 1000) % 50 == 0 else (N or 1000))
 
 
-def level0_flops(ns, np_, K):
-    """Algorithmic flops of one element's dense condensed block factorization:
-    b^3/3 + b^2 p + b p^2 with b = (K+1) n_s (Cholesky of the element block, border solve,
-    border Schur update)."""
-    b = (K + 1) * ns
-    return b ** 3 / 3.0 + b * b * np_ + b * np_ * np_
+def element_flops(ns, np_, K, tiled):
+    """Algorithmic flops (2 per multiply-add) of one element's factorization, split by kernel.
+    panel: left-looking partial Cholesky of the mI = K ns interior columns of the R-row element
+    matrix (R = mI + 2 ns + np), sum over columns c of (R - c) c multiply-adds; schur: the
+    trailing Schur complement of the remaining R - mI rows and columns with the mI eliminated
+    columns, without its np x np parameter block (formed separately for the border)."""
+    mI = K * ns
+    R = mI + 2 * ns + np_
+    panel = 2.0 * sum((R - c) * c for c in range(mI))
+    t = R - mI
+    schur = 2.0 * mI * (t * (t + 1) / 2 - (np_ * (np_ + 1) / 2 if tiled else 0))
+    return panel, schur
 
 
-def level0_bytes(ns, np_, K):
-    """Algorithmic bytes of one element's factor in FP64: S_e = b(b+1)/2 + n_s^2 + b p doubles
-    written once."""
-    b = (K + 1) * ns
-    return 8.0 * (b * (b + 1) / 2 + ns * ns + b * np_)
+def assembly_bytes(ns, np_, K):
+    """Algorithmic bytes of one element's assembly: the lower triangle of its R x R matrix written
+    once in FP64 (the theta block to its FP64 side array)."""
+    R = (K + 2) * ns + np_
+    return 8.0 * R * (R + 1) / 2
 
 
-def cpu_baseline(inst, K, seconds=20.0):
-    """The oracle's Newton iteration (natural-order block Cholesky path) on the same workload,
-    timed on the host for a bounded number of iterations."""
+def cpu_baseline(name, K, seconds=20.0):
+    """The oracle's Newton iteration (natural-order block Cholesky path) timed on the host on a
+    bounded sample: the same network on a mesh short enough for ~seconds of CPU work, the rate
+    scaled to the full mesh by the element ratio (the oracle's cost per iteration is linear in
+    the number of elements)."""
     from oracle import ipm, problem
     from paper_2607_12201_amd import workloads
 
+    N_full = 10000 if name == "net100_n10000" else 1000
+    N_s = 10 if name == "net100_n10000" else 1000
+    inst = make_instance(name, N_s)
     m = problem.Model(inst, K)
     opt = ipm.Options()
     st = ipm.init_state(m, workloads.initial_point(inst, K), opt)
@@ -79,23 +93,24 @@ def cpu_baseline(inst, K, seconds=20.0):
         cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
         cores = os.cpu_count()
-    return dict(value=n / dt, unit="Newton steps/s", cores=int(cores), kind="oracle",
-                sample=f"first {n} oracle IPM iterations (natural-order block Cholesky) on the "
-                       f"same 20-species N=1000 instance, {dt:.1f} s")
+    return dict(value=n / dt * N_s / N_full, unit="Newton steps/s", cores=int(cores), kind="oracle",
+                sample=f"first {n} oracle IPM iterations (natural-order block Cholesky) on the same "
+                       f"network with N={N_s} elements in {dt:.1f} s, rate scaled by {N_s}/{N_full}")
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=60)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=12)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the FP32-factor + FP64-refinement leg")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--workload", default="net20_n1000", choices=["net20_n1000", "multistart", "serving"],
-                    help="net20_n1000: one 20-species instance, FP64 (the headline line); "
-                         "multistart: 256 uneven A<->B instances batched, FP32 factors + FP64 "
-                         "refinement, graph-replayed steps, autotuned thread grids; serving: "
-                         "Poisson arrivals of uneven requests through the continuous-batching "
+    ap.add_argument("--workload", default="net100_n10000",
+                    choices=["net100_n10000", "net20_n1000", "multistart", "serving"],
+                    help="net100_n10000: one 100-species N=10000 instance (the headline line); "
+                         "net20_n1000: one 20-species N=1000 instance; multistart: 256 uneven A<->B "
+                         "instances batched; serving: Poisson arrivals through the continuous-batching "
                          "loop against the sequential per-instance FP64 path")
     ap.add_argument("--requests", type=int, default=60)
     ap.add_argument("--load", type=float, default=0.8,
@@ -108,93 +123,141 @@ def main():
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(instances are independent and shard across GPUs one process per GPU)", file=sys.stderr)
         sys.exit(2)
-
     if args.workload == "multistart":
         return bench_multistart(args)
     if args.workload == "serving":
         return bench_serving(args)
+    return bench_single(args)
 
+
+def _timed_leg(P, x0, opts, precision, steps, warmup, side, calib_mib=0):
+    """Graph-replayed timed region, then the same steps eagerly with per-phase events and a
+    per-step wall clock.  Returns the measurements."""
     import torch
-    from paper_2607_12201_amd import colloc, workloads
-
-    K = 3
-    inst = workloads.random_network(0)
-    x0 = workloads.initial_point(inst, K)
-    P = colloc.Problem(inst, K)
-    opts = colloc.default_opts()
-    from paper_2607_12201_amd import autotune
-    tiles = autotune.tune(P)           # thread grids per kernel (device-timed, cached per shape)
-    side = torch.cuda.Stream()
     with torch.cuda.stream(side):
-        ws, state = P.workspace(), P.state()
-        x0d = torch.tensor(x0, dtype=torch.float64, device="cuda")
-        # one interior-point step captured as a HIP graph, replayed once per step
+        ws, state = P.workspace(precision), P.state()
         graph = P.graph_create(state, ws, opts, steps=1)
-        P.ipm_init(x0d, state, ws, opts)
-        for _ in range(args.warmup):
+        P.ipm_init(x0, state, ws, opts)
+        for _ in range(warmup):
             P.graph_launch(graph)
         side.synchronize()
-        if args.calib_copy_mib:
-            n = args.calib_copy_mib * 2 ** 20 // 8
+        if calib_mib:
+            n = calib_mib * 2 ** 20 // 8
             src = torch.ones(n, dtype=torch.float64, device="cuda")
             dst = torch.empty_like(src)
             dst.copy_(src)
             side.synchronize()
             del src, dst
-        P.ipm_init(x0d, state, ws, opts)          # timed region starts from the same point
+        P.ipm_init(x0, state, ws, opts)          # timed region starts from the same point
         side.synchronize()
         it0 = int(P.info(state)[0]["iter"])
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(steps):
             P.graph_launch(graph)
         side.synchronize()
         dt = time.perf_counter() - t0
         info = P.info(state)[0]
-        # the same steps again, eager, with the library's per-phase HIP events (the events are
-        # recorded on this stream around each phase; a graph replay records none)
-        P.ipm_init(x0d, state, ws, opts)
-        P.timing(True)
-        for _ in range(args.steps):
-            P.ipm_step(state, ws, opts)
+        P.graph_destroy(graph)
+        # eager pass: the library's per-phase HIP events are recorded on this stream around
+        # each phase (a graph replay records none); the host clock per synchronized step gives
+        # the latency distribution
+        P.ipm_init(x0, state, ws, opts)
         side.synchronize()
+        P.timing(True)
+        lat = []
+        for _ in range(steps):
+            t1 = time.perf_counter()
+            P.ipm_step(state, ws, opts)
+            side.synchronize()
+            lat.append(time.perf_counter() - t1)
         ph_ms, ph_n = P.timing_read()
         P.timing(False)
-        P.graph_destroy(graph)
-    newton = int(info["iter"]) - it0
-    value = newton / dt
-    ms_per_step = 1e3 * dt / args.steps
+        info2 = P.info(state)[0]
+        del ws, state
+    return dict(dt=dt, newton=int(info["iter"]) - it0, info=info, ph_ms=ph_ms, ph_n=ph_n,
+                lat_ms=1e3 * np.array(lat), ir_fallbacks=int(info2["ir_fallbacks"]),
+                iter_eager=int(info2["iter"]))
+
+
+def bench_single(args):
+    import torch
+    from paper_2607_12201_amd import colloc, workloads
+
+    K = 3
+    name = args.workload
+    inst = make_instance(name)
+    x0 = workloads.initial_point(inst, K)
+    P = colloc.Problem(inst, K)
+    # element blocks above 160 rows take the tiled matrix-core path (one fixed tiling)
+    tiled = (K + 2) * P.ns + P.np_ > 160 or os.environ.get("COLLOC_FACTOR_PATH") == "tiled"
+    tiles = None
+    if not tiled:
+        from paper_2607_12201_amd import autotune
+        tiles = autotune.tune(P)           # thread grids per kernel (device-timed, cached per shape)
+    side = torch.cuda.Stream()
+    x0d = torch.tensor(x0, dtype=torch.float64, device="cuda")
+    r64 = _timed_leg(P, x0d, colloc.default_opts(), colloc.FP64, args.steps, args.warmup, side,
+                     args.calib_copy_mib)
+    rmx = None
+    if not args.no_mixed:
+        torch.cuda.empty_cache()
+        rmx = _timed_leg(P, x0d, colloc.default_opts(precision=colloc.FP32_IR), colloc.FP32_IR, args.steps,
+                         args.warmup, side)
+    value = r64["newton"] / r64["dt"]
     E = P.n_elem
-    l0_ms = ph_ms["level0"] / max(1, ph_n["level0"])
-    flops = level0_flops(P.ns, P.np_, K) * E
-    achieved = flops / (l0_ms * 1e-3) / 1e12
+    ph = {k: r64["ph_ms"][k] / max(1, r64["ph_n"][k]) for k in r64["ph_ms"]}
+    if tiled:
+        f_panel, f_schur = element_flops(P.ns, P.np_, K, True)
+        cand = {"level0": ("k_pchol_panel (element interior-column factorization)", "mfma", f_panel * E),
+                "schur": ("k_pchol_syrk (element Schur complement tiles)", "mfma", f_schur * E),
+                "assembly": ("k_big_asm (element matrix assembly)", "hbm",
+                             assembly_bytes(P.ns, P.np_, K) * E)}
+        key = max(cand, key=lambda k: ph.get(k, 0.0))
+        kname, bound, work = cand[key]
+    else:
+        f_panel, f_schur = element_flops(P.ns, P.np_, K, False)
+        key, kname, bound, work = "level0", "k_level0r (fused assembly + element condensation)", "mfma", \
+            (f_panel + f_schur) * E
+    ms = ph[key]
+    if bound == "hbm":
+        achieved, peak, unit = work / (ms * 1e-3) / 1e9, PEAK_HBM_GBS, "GB/s"
+    else:
+        achieved, peak, unit = work / (ms * 1e-3) / 1e12, PEAK_FP64_TFLOPS, "TFLOP/s"
+    cfg = {"workload": WORKLOADS[name], "factor_path": "tiled" if tiled else "register",
+           "newton_steps": r64["newton"], "ipm_step_calls": args.steps, "graph_replay": True,
+           "final_status": int(r64["info"]["status"]), "iter_end": int(r64["info"]["iter"]),
+           "phase_ms_per_call": ph,
+           "step_latency_ms": {"p50": float(np.percentile(r64["lat_ms"], 50)),
+                               "p99": float(np.percentile(r64["lat_ms"], 99))}}
+    if tiles:
+        cfg["tiles"] = {k: tiles[k] for k in colloc.Problem.TILE_KERNELS}
+    if rmx is not None:
+        cfg["fp32_ir"] = {"newton_steps_per_s": rmx["newton"] / rmx["dt"], "newton_steps": rmx["newton"],
+                          "ms_per_step": 1e3 * rmx["dt"] / args.steps,
+                          "ir_fallbacks": rmx["ir_fallbacks"], "iter_eager": rmx["iter_eager"],
+                          "phase_ms_per_call": {k: rmx["ph_ms"][k] / max(1, rmx["ph_n"][k]) for k in rmx["ph_ms"]},
+                          "step_latency_ms": {"p50": float(np.percentile(rmx["lat_ms"], 50)),
+                                              "p99": float(np.percentile(rmx["lat_ms"], 99))}}
     line = {
-        "metric": "IPM Newton steps/s (AD+KKT factor+solve)",
+        "metric": "IPM Newton steps/s (AD+KKT factor+solve) FP64 vs mixed-batched; p50/p99 latency",
         "value": value,
         "unit": "Newton steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": 1e3 * r64["dt"] / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "random mass-action network, 20 species, 40 reactions, 40 params, "
-                               "N=1000 Radau elements K=3, FP64 plain IPM, one instance",
-                   "newton_steps": newton, "ipm_step_calls": args.steps, "graph_replay": True,
-                   "final_status": int(info["status"]), "iter_end": int(info["iter"]),
-                   "tiles": {k: tiles[k] for k in colloc.Problem.TILE_KERNELS},
-                   "phase_ms_per_call": {k: ph_ms[k] / max(1, ph_n[k]) for k in ph_ms}},
-        "roofline": {"bound": "alu", "kernel": "k_level0 (fused assembly + element condensation)",
-                     "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": level0_traffic(tiles["level0"]),
-                     "avg_launch_ms": l0_ms,
-                     "algorithmic_flops_per_launch": flops,
-                     "algorithmic_bytes_per_launch": level0_bytes(P.ns, P.np_, K) * E},
+        "config": cfg,
+        "roofline": {"bound": bound, "kernel": kname, "achieved": achieved, "peak": peak, "unit": unit,
+                     "frac": achieved / peak, "traffic": None, "avg_launch_ms": ms,
+                     ("algorithmic_flops_per_launch" if bound != "hbm" else "algorithmic_bytes_per_launch"): work},
     }
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(inst, K, args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline(name, K, args.cpu_seconds)
     print(json.dumps(line), flush=True)
 
 

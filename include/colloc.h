@@ -273,10 +273,14 @@ typedef struct colloc_state_layout {
 int colloc_state_layout_get(const colloc_problem* p, colloc_state_layout* out);
 
 /* Per-phase timing with HIP events recorded on the call's stream around each phase launch:
- * enable, then read accumulated milliseconds and launch counts per phase. */
+ * enable, then read accumulated milliseconds and launch counts per phase.  LEVEL0 is the element
+ * condensation (with the fused assembly on the register path); on the tiled path ASSEMBLY is the
+ * element assembly, LEVEL0 the interior-column panel factorization and SCHUR the element Schur
+ * complement tiles. */
 enum {
   COLLOC_PH_EVAL = 0, COLLOC_PH_LEVEL0 = 1, COLLOC_PH_CR = 2, COLLOC_PH_BORDER = 3,
-  COLLOC_PH_SOLVE = 4, COLLOC_PH_STEP = 5, COLLOC_PH_LINESEARCH = 6, COLLOC_N_PHASES = 7
+  COLLOC_PH_SOLVE = 4, COLLOC_PH_STEP = 5, COLLOC_PH_LINESEARCH = 6, COLLOC_PH_ASSEMBLY = 7,
+  COLLOC_PH_SCHUR = 8, COLLOC_N_PHASES = 9
 };
 int colloc_timing_enable(colloc_problem* p, int32_t enable);
 int colloc_timing_read(colloc_problem* p, double* ms, int64_t* launches, int32_t n);

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libcolloc.so")
 OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED = 0, -1, -2, -3, -4
 RUNNING, SOLVED, ACCEPTABLE, MAXITER, TIMEOUT, ENOTPD, ENONFINITE, RESTORATION_REQUIRED = range(8)
 FP64, FP32_IR = 0, 1
-PHASES = ("eval", "level0", "cr", "border", "solve", "step", "linesearch")
+PHASES = ("eval", "level0", "cr", "border", "solve", "step", "linesearch", "assembly", "schur")
 MAX_LS = 48
 FILTER_CAP = 128
 

@@ -21,6 +21,7 @@
 
 #include <algorithm>
 
+#include "../../include/colloc.h"
 #include "big.h"
 #include "elem.h"
 #include "kernels.h"
@@ -165,8 +166,19 @@ __device__ inline double big_entry(const Shape& S, const AsmLds& L, int i, doubl
   return (c == r) ? d0[p] : 0.0;
 }
 
+// Column-major lower-triangle index t of an R x R matrix -> (row r, column c): column c holds rows
+// c..R-1 starting at c R - c (c - 1) / 2.
+__device__ inline void tri_col(int t, int R, int& r, int& c) {
+  const double B = 2.0 * R + 1.0;
+  c = (int)((B - sqrt(B * B - 8.0 * (double)t)) * 0.5);
+  if (c < 0) c = 0;
+  while (c > 0 && c * R - c * (c - 1) / 2 > t) --c;
+  while ((c + 1) * R - (c + 1) * c / 2 <= t) ++c;
+  r = c + (t - (c * R - c * (c - 1) / 2));
+}
+
 template <typename T>
-__global__ void __launch_bounds__(256) k_big_asm(Shape S, Tab tb, Ws ws) {
+__global__ void __launch_bounds__(1024) k_big_asm(Shape S, Tab tb, Ws ws) {
   extern __shared__ double lds[];
   const int64_t e = blockIdx.x;
   const int inst = tb.elem_inst[e], i = tb.elem_loc[e];
@@ -236,17 +248,18 @@ __global__ void __launch_bounds__(256) k_big_asm(Shape S, Tab tb, Ws ws) {
   __syncthreads();
   T* A = (T*)ws.ebuf + e * (int64_t)G.Rp * G.Rp;
   double* ath = ws.ath + e * (int64_t)np * np;
-  // column by column, consecutive threads on consecutive rows (coalesced stores)
-  for (int c = 0; c < R; ++c) {
-    for (int r = c + tid(); r < R; r += nthr()) {
-      const bool tt = r >= b && r < b + np && c >= b;   // theta-theta: FP64 side array
-      const double v = big_entry(S, L, i, h, dw, r, c);
-      if (tt) {
-        ath[(r - b) * np + (c - b)] = v;
-        A[r + (int64_t)c * G.Rp] = (T)0;
-      } else {
-        A[r + (int64_t)c * G.Rp] = (T)v;
-      }
+  // the lower triangle in column-major order: consecutive threads on consecutive rows of a column
+  const int ntri = R * (R + 1) / 2;
+  for (int t = tid(); t < ntri; t += nthr()) {
+    int r, c;
+    tri_col(t, R, r, c);
+    const bool tt = r >= b && r < b + np && c >= b;   // theta-theta: FP64 side array
+    const double v = big_entry(S, L, i, h, dw, r, c);
+    if (tt) {
+      ath[(r - b) * np + (c - b)] = v;
+      A[r + (int64_t)c * G.Rp] = (T)0;
+    } else {
+      A[r + (int64_t)c * G.Rp] = (T)v;
     }
   }
 }
@@ -587,8 +600,8 @@ __global__ void __launch_bounds__(256) k_big_theta(Shape S, Tab tb, Ws ws) {
 }
 
 // Border matrix of each instance (FP64, ld Bp): [T_0 | G_0^T; G_0 | S_thth], where separator 0
-// takes the contributions of the separator eliminated at the last level and S_thth = sum of the
-// chunk partials + Sx + dw.
+// takes the contributions of the separator eliminated at the last level (its theta-theta block is
+// written by k_border_theta).
 template <typename T>
 __global__ void __launch_bounds__(256) k_border_build(Shape S, Tab tb, Ws ws) {
   const int inst = blockIdx.x;
@@ -612,16 +625,31 @@ __global__ void __launch_bounds__(256) k_border_build(Shape S, Tab tb, Ws ws) {
     if (hu) v += (double)sep_at<T>(ws, G, e0 + u, 3 * ns + c, ns + q);
     B[ns + c + (int64_t)q * G.Bp] = v;
   }
+}
+
+// theta-theta block of the border matrix: sum of the chunk partials in chunk order + Sx + dw;
+// grid (entry tile of 256, instance).
+__global__ void __launch_bounds__(256) k_border_theta(Shape S, Tab tb, Ws ws) {
+  const int inst = blockIdx.y;
+  if (block_flag(&ws.flag[inst])) return;
+  const int ns = S.ns, np = S.np, N = tb.inst_N[inst];
+  const BigGeom G = big_geom(S);
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= np * np) return;
+  const int r = idx / np, c = idx - r * np;
+  if (c > r) return;
   const int nch = (int)cl_ceil_div(N, CL_THCHUNK);
-  for (int idx = tid(); idx < np * np; idx += nthr()) {
-    const int r = idx / np, c = idx - r * np;
-    if (c > r) continue;
-    const double* src = ws.thred + (int64_t)inst * ws.nchunk * np * np + idx;
-    double acc = 0.0;
-    for (int ch = 0; ch < nch; ++ch) acc += src[(int64_t)ch * np * np];
-    if (r == c) acc += ws.sxdw[inst * np + r];
-    B[ns + r + (int64_t)(ns + c) * G.Bp] = acc;
+  const double* src = ws.thred + (int64_t)inst * ws.nchunk * np * np + idx;
+  double a0 = 0.0, a1 = 0.0;   // two interleaved partial sums, combined in a fixed order
+  int ch = 0;
+  for (; ch + 2 <= nch; ch += 2) {
+    a0 += src[(int64_t)ch * np * np];
+    a1 += src[(int64_t)(ch + 1) * np * np];
   }
+  if (ch < nch) a0 += src[(int64_t)ch * np * np];
+  double acc = a0 + a1;
+  if (r == c) acc += ws.sxdw[inst * np + r];
+  ws.bbuf[(int64_t)inst * G.Bp * G.Bp + ns + r + (int64_t)(ns + c) * G.Bp] = acc;
 }
 
 // ---------------------------------------------------------------- solves
@@ -924,15 +952,19 @@ static int big_factor_t(const Shape& S, const Tab& tb, const HostPlan& hp, const
   const BigGeom G = big_geom(S);
   const int E = (int)tb.n_elem;
   const int64_t esz = (int64_t)G.Rp * G.Rp, ssz = (int64_t)G.Lp * G.Lp;
-  if (cb) cb(ctx, 1, 1, st);
-  hipLaunchKernelGGL(k_big_asm<T>, dim3(E), dim3(256), big_asm_lds(S), st, S, tb, ws);
+  if (cb) cb(ctx, COLLOC_PH_ASSEMBLY, 1, st);
+  hipLaunchKernelGGL(k_big_asm<T>, dim3(E), dim3(1024), big_asm_lds(S), st, S, tb, ws);
+  if (cb) cb(ctx, COLLOC_PH_ASSEMBLY, 0, st);
+  if (cb) cb(ctx, COLLOC_PH_LEVEL0, 1, st);
   PArgs ea = pargs(ws.ebuf, esz, G.Rp, S.R, S.mI, E, 0, 0);
   hipLaunchKernelGGL(k_pchol_panel<T>, dim3(E), dim3(256), 0, st, tb, ws, ea);
+  if (cb) cb(ctx, COLLOC_PH_LEVEL0, 0, st);
+  if (cb) cb(ctx, COLLOC_PH_SCHUR, 1, st);
   // the theta-theta block is formed by k_big_theta; its tiles here are skipped
   ea.skip0 = S.b;
   ea.skip1 = S.b + S.np;
   syrk<T>(tb, ws, ea, st);
-  if (cb) cb(ctx, 1, 0, st);
+  if (cb) cb(ctx, COLLOC_PH_SCHUR, 0, st);
   if (cb) cb(ctx, 2, 1, st);
   hipLaunchKernelGGL(k_sep_init<T>, dim3(E), dim3(256), 0, st, S, tb, ws);
   for (int l = 1; l <= tb.L; ++l) {
@@ -953,6 +985,9 @@ static int big_factor_t(const Shape& S, const Tab& tb, const HostPlan& hp, const
   if (nt > 0)
     hipLaunchKernelGGL(k_big_theta<T>, dim3(ws.nchunk, nt * (nt + 1) / 2, tb.n_inst), dim3(256), 0, st, S, tb, ws);
   hipLaunchKernelGGL(k_border_build<T>, dim3(tb.n_inst), dim3(256), 0, st, S, tb, ws);
+  if (S.np > 0)
+    hipLaunchKernelGGL(k_border_theta, dim3((unsigned)cl_ceil_div(S.np * S.np, 256), tb.n_inst), dim3(256), 0, st,
+                       S, tb, ws);
   PArgs ba = pargs(ws.bbuf, (int64_t)G.Bp * G.Bp, G.Bp, G.Br, G.Br, tb.n_inst, 2, 0);
   hipLaunchKernelGGL(k_pchol_panel<double>, dim3(tb.n_inst), dim3(256), 0, st, tb, ws, ba);
   if (cb) cb(ctx, 3, 0, st);
