@@ -67,7 +67,7 @@ struct AsmLds {
 
 size_t big_asm_lds(const Shape& S) {
   const size_t nd = (size_t)(S.K + 1) * S.ns + (size_t)S.K * (S.lcf + S.lct) + 4 * (size_t)S.K * S.nr +
-                    (size_t)S.mmax * (S.K + 1) + 8;
+                    (size_t)S.mmax * (S.K + 1) + 8 + 16 * (size_t)S.K * S.ns;
   const size_t ni = (S.ns + 1) + (size_t)S.lcf + (S.np + 1) + S.lct + (S.ns + 1) + 2 * (size_t)S.lrq +
                     (S.np + 1) + S.lpc + 3 * (size_t)S.nr + S.mmax + 8;
   return sizeof(double) * nd + sizeof(int) * ni;
@@ -102,8 +102,11 @@ __device__ inline double a_dot(const int* p1, const int* s1, const double* v1, i
 // (initial condition / continuity, eq. 2c-2d), the measurement Hessian and dw on z, and for every
 // collocation point k the product of its rows a_jk e_(j,s) - h F_k on node k - h Fth_k on theta,
 // weighted by Ds, plus the reaction second derivatives (W).  theta-theta entries exclude Sx + dw
-// (added once per instance at the border).
-__device__ inline double big_entry(const Shape& S, const AsmLds& L, int i, double h, double dw, int r, int c) {
+// (added once per instance at the border).  wv holds the column's dense weights (see
+// column_weights), which turn the products F^T Ds F, F^T Ds Fth and Fth^T Ds Fth into one pass
+// over the row's column list.
+__device__ inline double big_entry(const Shape& S, const AsmLds& L, int i, double h, double dw, int r, int c,
+                                   const double* wv) {
   const int ns = S.ns, np = S.np, b = S.b, K = S.K, nr = S.nr;
   const double* d0 = L.D;
   if (r < b) {
@@ -115,18 +118,19 @@ __device__ inline double big_entry(const Shape& S, const AsmLds& L, int i, doubl
         if (L.msp[q] == s1) v += L.mw[q * (K + 1) + j1] * L.mw[q * (K + 1) + j2];
       for (int k = 1; k <= K; ++k) v += L.D[k * ns + s1] * S.a[j1][k] * S.a[j2][k];
     }
-    if (j2 >= 1) v -= h * S.a[j1][j2] * L.D[j2 * ns + s1] * a_F(L, S.lcf, j2, s1, s2);
+    if (j2 >= 1) v -= h * S.a[j1][j2] * wv[s1];   // wv[s] = Ds_(j2,s) F_j2[s][s2]
     if (j1 >= 1) v -= h * S.a[j2][j1] * L.D[j1 * ns + s2] * a_F(L, S.lcf, j1, s2, s1);
     if (j1 == j2 && j1 >= 1) {
       const int k = j1;
-      v += h * h * a_dot(L.cfp, L.cfs, L.vF + (k - 1) * S.lcf, s1, L.cfp, L.cfs, L.vF + (k - 1) * S.lcf, s2,
-                         L.D + k * ns);
+      const double* vf = L.vF + (k - 1) * S.lcf;
+      double q1 = 0.0;   // (F^T Ds F)[s1][s2] = sum over column s1's entries of F[s][s1] wv[s]
+      for (int o = L.cfp[s1]; o < L.cfp[s1 + 1]; ++o) q1 += vf[o] * wv[L.cfs[o]];
       double wz = 0.0;   // reactions with s1 in a slot and s2 in the other
       for (int o = L.rqp[s1]; o < L.rqp[s1 + 1]; ++o) {
         const int rr = L.rqr[o], sl = L.rqt[o];
         wz += (L.rea[2 * rr + 1 - sl] == s2) ? L.hv[((k - 1) * nr + rr) * 4] : 0.0;
       }
-      v += wz;
+      v += h * h * q1 + wz;
     }
     return v;
   }
@@ -138,22 +142,26 @@ __device__ inline double big_entry(const Shape& S, const AsmLds& L, int i, doubl
       for (int k = 1; k <= K; ++k) v -= h * S.a[j][k] * L.D[k * ns + s] * a_T(L, S.lct, k, s, th);
       if (j >= 1) {
         const int k = j;
-        v += h * h * a_dot(L.cfp, L.cfs, L.vF + (k - 1) * S.lcf, s, L.ctp, L.cts, L.vT + (k - 1) * S.lct, th,
-                           L.D + k * ns);
+        const double* vt = L.vT + (k - 1) * S.lct;
+        double q2 = 0.0;   // (Fth^T Ds F)[th][s]
+        for (int o = L.ctp[th]; o < L.ctp[th + 1]; ++o) q2 += vt[o] * wv[L.cts[o]];
         double wt = 0.0;   // reactions with s in a slot and rate parameter th
         for (int o = L.rqp[s]; o < L.rqp[s + 1]; ++o) {
           const int rr = L.rqr[o], sl = L.rqt[o];
           wt += (L.par[rr] == th) ? L.hv[((k - 1) * nr + rr) * 4 + 1 + sl] : 0.0;
         }
-        v += wt;
+        v += h * h * q2 + wt;
       }
       return v;
     }
     const int th2 = c - b;
     double v = 0.0;
     for (int k = 1; k <= K; ++k) {
-      v += h * h * a_dot(L.ctp, L.cts, L.vT + (k - 1) * S.lct, th, L.ctp, L.cts, L.vT + (k - 1) * S.lct, th2,
-                         L.D + k * ns);
+      const double* vt = L.vT + (k - 1) * S.lct;
+      const double* w = wv + (k - 1) * ns;   // w[s] = Ds_(k,s) Fth_k[s][th2]
+      double q3 = 0.0;
+      for (int o = L.ctp[th]; o < L.ctp[th + 1]; ++o) q3 += vt[o] * w[L.cts[o]];
+      v += h * h * q3;
       if (th == th2)
         for (int o = L.pcp[th]; o < L.pcp[th + 1]; ++o) v += L.hv[((k - 1) * nr + L.pcr[o]) * 4 + 3];
     }
@@ -166,17 +174,49 @@ __device__ inline double big_entry(const Shape& S, const AsmLds& L, int i, doubl
   return (c == r) ? d0[p] : 0.0;
 }
 
-// Column-major lower-triangle index t of an R x R matrix -> (row r, column c): column c holds rows
-// c..R-1 starting at c R - c (c - 1) / 2.
-__device__ inline void tri_col(int t, int R, int& r, int& c) {
-  const double B = 2.0 * R + 1.0;
-  c = (int)((B - sqrt(B * B - 8.0 * (double)t)) * 0.5);
-  if (c < 0) c = 0;
-  while (c > 0 && c * R - c * (c - 1) / 2 > t) --c;
-  while ((c + 1) * R - (c + 1) * c / 2 <= t) ++c;
-  r = c + (t - (c * R - c * (c - 1) / 2));
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Dense weights of column c, built by one wave in its private LDS slice: for a z column (j, s2)
+// with j >= 1, wv[s] = Ds_(j,s) F_j[s][s2]; for a theta column th, wv[(k-1) ns + s] =
+// Ds_(k,s) Fth_k[s][th] for every point k.  A column list may name a species once per reaction,
+// so one lane per point adds its list in order.
+__device__ inline void column_weights(const Shape& S, const AsmLds& L, int c, int lane, double* wv) {
+  const int ns = S.ns, np = S.np, b = S.b, K = S.K;
+  if (c < b) {
+    const int j = c / ns, s2 = c - j * ns;
+    if (j == 0) return;
+    for (int s = lane; s < ns; s += 64) wv[s] = 0.0;
+    wave_sync();
+    if (lane == 0) {
+      const double* vf = L.vF + (j - 1) * S.lcf;
+      for (int o = L.cfp[s2]; o < L.cfp[s2 + 1]; ++o) {
+        const int s = L.cfs[o];
+        wv[s] += L.D[j * ns + s] * vf[o];
+      }
+    }
+  } else if (c < b + np) {
+    const int th = c - b;
+    for (int t = lane; t < K * ns; t += 64) wv[t] = 0.0;
+    wave_sync();
+    if (lane < K) {
+      const int k = lane + 1;
+      const double* vt = L.vT + (k - 1) * S.lct;
+      for (int o = L.ctp[th]; o < L.ctp[th + 1]; ++o) {
+        const int s = L.cts[o];
+        wv[(k - 1) * ns + s] += L.D[k * ns + s] * vt[o];
+      }
+    }
+  }
+  wave_sync();
+}
+
+// One workgroup of 16 waves per element; each wave assembles whole columns (column c by wave
+// c mod 16), its lanes on consecutive rows (coalesced stores), after building the column's dense
+// weights.
 template <typename T>
 __global__ void __launch_bounds__(1024) k_big_asm(Shape S, Tab tb, Ws ws) {
   extern __shared__ double lds[];
@@ -192,7 +232,8 @@ __global__ void __launch_bounds__(1024) k_big_asm(Shape S, Tab tb, Ws ws) {
   L.vT = L.vF + K * S.lcf;
   L.hv = L.vT + K * S.lct;
   L.mw = L.hv + 4 * K * nr;
-  int* ip = (int*)(L.mw + S.mmax * (K + 1) + 8);
+  double* wscr = L.mw + S.mmax * (K + 1) + 8;   // 16 wave slices of K ns doubles
+  int* ip = (int*)(wscr + 16 * K * ns);
   L.cfp = ip; ip += ns + 1;
   L.cfs = ip; ip += S.lcf;
   L.ctp = ip; ip += np + 1;
@@ -248,19 +289,21 @@ __global__ void __launch_bounds__(1024) k_big_asm(Shape S, Tab tb, Ws ws) {
   __syncthreads();
   T* A = (T*)ws.ebuf + e * (int64_t)G.Rp * G.Rp;
   double* ath = ws.ath + e * (int64_t)np * np;
-  // the lower triangle in column-major order: consecutive threads on consecutive rows of a column
-  const int ntri = R * (R + 1) / 2;
-  for (int t = tid(); t < ntri; t += nthr()) {
-    int r, c;
-    tri_col(t, R, r, c);
-    const bool tt = r >= b && r < b + np && c >= b;   // theta-theta: FP64 side array
-    const double v = big_entry(S, L, i, h, dw, r, c);
-    if (tt) {
-      ath[(r - b) * np + (c - b)] = v;
-      A[r + (int64_t)c * G.Rp] = (T)0;
-    } else {
-      A[r + (int64_t)c * G.Rp] = (T)v;
+  const int wid = tid() >> 6, lane = tid() & 63;
+  double* wv = wscr + wid * K * ns;
+  for (int c = wid; c < R; c += 16) {
+    column_weights(S, L, c, lane, wv);
+    for (int r = c + lane; r < R; r += 64) {
+      const bool tt = r >= b && r < b + np && c >= b;   // theta-theta: FP64 side array
+      const double v = big_entry(S, L, i, h, dw, r, c, wv);
+      if (tt) {
+        ath[(r - b) * np + (c - b)] = v;
+        A[r + (int64_t)c * G.Rp] = (T)0;
+      } else {
+        A[r + (int64_t)c * G.Rp] = (T)v;
+      }
     }
+    wave_sync();
   }
 }
 
@@ -269,17 +312,22 @@ __global__ void __launch_bounds__(1024) k_big_asm(Shape S, Tab tb, Ws ws) {
 // column-major, leading dimension ld), one workgroup of four waves per matrix.  Columns are
 // eliminated in panels of 32: the panel's rows are brought up to date with all earlier panels in
 // chunks of 128 rows (C = A - L_rows L_panel^T as 16x16x4 matrix-core products, operands staged
-// through LDS 16 columns at a time), then the panel's 32 x 32 diagonal block is factored by one
-// wave and every row below it solved against that factor (FP64 arithmetic), and the chunk is
-// stored back.  A non-positive or non-finite pivot sets the instance's flag.
+// through LDS 32 columns at a time, the next 32 loaded into registers while the current ones are
+// multiplied), then the panel's 32 x 32 diagonal block is factored by one wave and every row
+// below it solved against that factor in registers (FP64 arithmetic), and the chunk is stored
+// back.  A non-positive or non-finite pivot sets the instance's flag.
 template <typename T>
-__global__ void __launch_bounds__(256) k_pchol_panel(Tab tb, Ws ws, PArgs a) {
-  constexpr int NB = 32, CH = 128, KC = 16, PC = NB + 1;
-  __shared__ T sA[KC * CH];
-  __shared__ T sB[KC * NB];
-  __shared__ double sC[CH * PC];
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_pchol_panel(Tab tb, Ws ws, PArgs a) {
+  constexpr int NB = 32, CH = 128, KC = 32, PC = NB + 1;
+  constexpr int NA = KC * CH / 256, NBL = KC * NB / 256;   // staged values per thread
+  constexpr int STAGE = (KC * CH + KC * NB) * (int)sizeof(T), CBYTES = CH * PC * 8;
+  __shared__ double raw[(STAGE > CBYTES ? STAGE : CBYTES) / 8];
   __shared__ double sL[NB * PC];
+  __shared__ double sR[NB];
   __shared__ int sflag;
+  T* sA = (T*)raw;
+  T* sB = sA + KC * CH;
+  double* sC = raw;   // the chunk's values, after the products (shares the staging area)
   typedef typename Mma<T>::acc acc_t;
   if ((int)blockIdx.x >= a.count) return;
   int64_t mat;
@@ -291,21 +339,32 @@ __global__ void __launch_bounds__(256) k_pchol_panel(Tab tb, Ws ws, PArgs a) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   for (int k0 = 0; k0 < m; k0 += NB) {
     const int wd = min(NB, m - k0);
+    // the previous panel's columns, stored by every thread, are this panel's operands
+    __syncthreads();
     for (int r0 = k0; r0 < n; r0 += CH) {
       acc_t c00 = {0, 0, 0, 0}, c01 = {0, 0, 0, 0}, c10 = {0, 0, 0, 0}, c11 = {0, 0, 0, 0};
+      T ra[NA], rb[NBL];
+      auto load = [&](int kc) {
+#pragma unroll
+        for (int q = 0; q < NA; ++q) {
+          const int ii = t & (CH - 1), kk = (t >> 7) + 2 * q, r = r0 + ii;
+          ra[q] = r < n ? A[r + (int64_t)(kc + kk) * ld] : (T)0;
+        }
+#pragma unroll
+        for (int q = 0; q < NBL; ++q) {
+          const int j = t & (NB - 1), kk = (t >> 5) + 8 * q;
+          rb[q] = j < wd ? A[(k0 + j) + (int64_t)(kc + kk) * ld] : (T)0;
+        }
+      };
+      if (k0 > 0) load(0);
       for (int kc = 0; kc < k0; kc += KC) {
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < (KC * CH) / 256; ++q) {
-          const int idx = t + 256 * q, ii = idx & (CH - 1), kk = idx / CH, r = r0 + ii;
-          sA[kk * CH + ii] = r < n ? A[r + (int64_t)(kc + kk) * ld] : (T)0;
-        }
+        for (int q = 0; q < NA; ++q) sA[((t >> 7) + 2 * q) * CH + (t & (CH - 1))] = ra[q];
 #pragma unroll
-        for (int q = 0; q < (KC * NB) / 256; ++q) {
-          const int idx = t + 256 * q, j = idx & (NB - 1), kk = idx / NB;
-          sB[kk * NB + j] = j < wd ? A[(k0 + j) + (int64_t)(kc + kk) * ld] : (T)0;
-        }
+        for (int q = 0; q < NBL; ++q) sB[((t >> 5) + 8 * q) * NB + (t & (NB - 1))] = rb[q];
         __syncthreads();
+        if (kc + KC < k0) load(kc + KC);
 #pragma unroll
         for (int s = 0; s < KC / 4; ++s) {
           const int kk = 4 * s + (lane >> 4), li = lane & 15;
@@ -361,17 +420,25 @@ __global__ void __launch_bounds__(256) k_pchol_panel(Tab tb, Ws ws, PArgs a) {
           const int ii = idx / NB, j = idx - ii * NB;
           sL[ii * PC + j] = (ii < wd && j <= ii) ? sC[ii * PC + j] : 0.0;
         }
+        if (t < NB) sR[t] = t < wd ? 1.0 / sC[t * PC + t] : 0.0;
         __syncthreads();
         i0 = wd;
       }
-      // rows below the diagonal block: x = c L^{-T}, one thread per row
+      // rows below the diagonal block: x = c L^{-T}, one thread per row, the row in registers
       for (int ii = i0 + t; ii < CH && r0 + ii < n; ii += 256) {
-        double* x = sC + ii * PC;
-        for (int j = 0; j < wd; ++j) {
+        double x[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) x[j] = sC[ii * PC + j];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
           double s = x[j];
+#pragma unroll
           for (int p = 0; p < j; ++p) s -= x[p] * sL[j * PC + p];
-          x[j] = s / sL[j * PC + j];
+          x[j] = s * sR[j];
+          __asm__ volatile("" ::: "memory");   // keep the factor reads of row j here (registers)
         }
+#pragma unroll
+        for (int j = 0; j < NB; ++j) sC[ii * PC + j] = x[j];
       }
       __syncthreads();
       for (int idx = t; idx < CH * NB; idx += 256) {
