@@ -61,13 +61,14 @@ struct AsmLds {
   double *vF, *vT;      // K x lcf, K x lct list values of the F and Fth columns per point
   double *hv;           // K nr 4 weighted second-derivative values
   double *mw;           // element measurements' weights (mmax x (K + 1))
+  double *a;            // collocation weights a[j * 8 + k] = l_j'(tau_k)
   int *cfp, *cfs, *ctp, *cts, *rqp, *rqr, *rqt, *pcp, *pcr, *rea, *par, *msp;
   int nmeas;
 };
 
 size_t big_asm_lds(const Shape& S) {
   const size_t nd = (size_t)(S.K + 1) * S.ns + (size_t)S.K * (S.lcf + S.lct) + 4 * (size_t)S.K * S.nr +
-                    (size_t)S.mmax * (S.K + 1) + 8 + 16 * (size_t)S.K * S.ns;
+                    (size_t)S.mmax * (S.K + 1) + 64 + 16 * (size_t)(S.K + 1) * S.ns;
   const size_t ni = (S.ns + 1) + (size_t)S.lcf + (S.np + 1) + S.lct + (S.ns + 1) + 2 * (size_t)S.lrq +
                     (S.np + 1) + S.lpc + 3 * (size_t)S.nr + S.mmax + 8;
   return sizeof(double) * nd + sizeof(int) * ni;
@@ -116,10 +117,10 @@ __device__ inline double big_entry(const Shape& S, const AsmLds& L, int i, doubl
       if (j1 == 0 && j2 == 0) v += d0[s1];
       for (int q = 0; q < L.nmeas; ++q)
         if (L.msp[q] == s1) v += L.mw[q * (K + 1) + j1] * L.mw[q * (K + 1) + j2];
-      for (int k = 1; k <= K; ++k) v += L.D[k * ns + s1] * S.a[j1][k] * S.a[j2][k];
+      for (int k = 1; k <= K; ++k) v += L.D[k * ns + s1] * L.a[j1 * 8 + k] * L.a[j2 * 8 + k];
     }
-    if (j2 >= 1) v -= h * S.a[j1][j2] * wv[s1];   // wv[s] = Ds_(j2,s) F_j2[s][s2]
-    if (j1 >= 1) v -= h * S.a[j2][j1] * L.D[j1 * ns + s2] * a_F(L, S.lcf, j1, s2, s1);
+    if (j2 >= 1) v -= h * L.a[j1 * 8 + j2] * wv[s1];   // wv[s] = Ds_(j2,s) F_j2[s][s2]
+    if (j1 >= 1) v -= h * L.a[j2 * 8 + j1] * L.D[j1 * ns + s2] * wv[ns + (j1 - 1) * ns + s1];   // F_j1[s2][s1]
     if (j1 == j2 && j1 >= 1) {
       const int k = j1;
       const double* vf = L.vF + (k - 1) * S.lcf;
@@ -139,7 +140,7 @@ __device__ inline double big_entry(const Shape& S, const AsmLds& L, int i, doubl
     if (c < b) {
       const int j = c / ns, s = c - j * ns;
       double v = 0.0;
-      for (int k = 1; k <= K; ++k) v -= h * S.a[j][k] * L.D[k * ns + s] * a_T(L, S.lct, k, s, th);
+      for (int k = 1; k <= K; ++k) v -= h * L.a[j * 8 + k] * L.D[k * ns + s] * a_T(L, S.lct, k, s, th);
       if (j >= 1) {
         const int k = j;
         const double* vt = L.vT + (k - 1) * S.lct;
@@ -180,22 +181,34 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Dense weights of column c, built by one wave in its private LDS slice: for a z column (j, s2)
-// with j >= 1, wv[s] = Ds_(j,s) F_j[s][s2]; for a theta column th, wv[(k-1) ns + s] =
-// Ds_(k,s) Fth_k[s][th] for every point k.  A column list may name a species once per reaction,
-// so one lane per point adds its list in order.
-__device__ inline void column_weights(const Shape& S, const AsmLds& L, int c, int lane, double* wv) {
-  const int ns = S.ns, np = S.np, b = S.b, K = S.K;
+// Dense weights of column c, built by one wave in its private LDS slice.  For a z column (j, s2):
+// wv[s] = Ds_(j,s) F_j[s][s2] (j >= 1) and wv[ns + (k-1) ns + u] = F_k[s2][u], row s2 of every
+// point's F; for a theta column th, wv[(k-1) ns + s] = Ds_(k,s) Fth_k[s][th] for every point k.
+// A list may name a species more than once, so one lane per vector adds its list in order.
+__device__ inline void column_weights(const Shape& S, const Tab& tb, const AsmLds& L, int inst, const double* jac,
+                                      int c, int lane, double* wv) {
+  const int ns = S.ns, np = S.np, b = S.b, K = S.K, nr = S.nr;
   if (c < b) {
     const int j = c / ns, s2 = c - j * ns;
-    if (j == 0) return;
-    for (int s = lane; s < ns; s += 64) wv[s] = 0.0;
+    for (int s = lane; s < (K + 1) * ns; s += 64) wv[s] = 0.0;
     wave_sync();
-    if (lane == 0) {
+    if (lane == 0 && j >= 1) {
       const double* vf = L.vF + (j - 1) * S.lcf;
       for (int o = L.cfp[s2]; o < L.cfp[s2 + 1]; ++o) {
         const int s = L.cfs[o];
         wv[s] += L.D[j * ns + s] * vf[o];
+      }
+    } else if (lane >= 1 && lane <= K) {   // row s2 of F_k: reactions that change s2, by slot
+      const int k = lane;
+      double* fr = wv + ns + (k - 1) * ns;
+      const int p0 = tb.sp_ptr[inst * (ns + 1) + s2], p1 = tb.sp_ptr[inst * (ns + 1) + s2 + 1];
+      for (int q = p0; q < p1; ++q) {
+        const int r = tb.sp_r[q];
+        const double nu = tb.sp_nu[q];
+        const double* jr = jac + ((k - 1) * nr + r) * 3;
+        const int u0 = L.rea[2 * r], u1 = L.rea[2 * r + 1];
+        if (u0 >= 0) fr[u0] += nu * jr[0];
+        if (u1 >= 0) fr[u1] += nu * jr[1];
       }
     }
   } else if (c < b + np) {
@@ -232,8 +245,9 @@ __global__ void __launch_bounds__(1024) k_big_asm(Shape S, Tab tb, Ws ws) {
   L.vT = L.vF + K * S.lcf;
   L.hv = L.vT + K * S.lct;
   L.mw = L.hv + 4 * K * nr;
-  double* wscr = L.mw + S.mmax * (K + 1) + 8;   // 16 wave slices of K ns doubles
-  int* ip = (int*)(wscr + 16 * K * ns);
+  L.a = L.mw + S.mmax * (K + 1);
+  double* wscr = L.a + 64;   // 16 wave slices of (K + 1) ns doubles
+  int* ip = (int*)(wscr + 16 * (K + 1) * ns);
   L.cfp = ip; ip += ns + 1;
   L.cfs = ip; ip += S.lcf;
   L.ctp = ip; ip += np + 1;
@@ -276,6 +290,7 @@ __global__ void __launch_bounds__(1024) k_big_asm(Shape S, Tab tb, Ws ws) {
   for (int t = tid(); t < nm; t += nthr()) L.msp[t] = tb.meas_sp[m0 + t];
   for (int t = tid(); t < nm * (K + 1); t += nthr()) L.mw[t] = tb.meas_w[(int64_t)m0 * (K + 1) + t];
   for (int t = tid(); t < b; t += nthr()) L.D[t] = ws.Ds[gi + t];
+  for (int t = tid(); t < 64; t += nthr()) L.a[t] = ((t >> 3) <= K && (t & 7) <= K) ? S.a[t >> 3][t & 7] : 0.0;
   for (int t = tid(); t < 4 * jl; t += nthr()) L.hv[t] = hes[t];
   for (int t = tid(); t < K * ncf; t += nthr()) {
     const int k = t / ncf, o = t - k * ncf;
@@ -290,18 +305,14 @@ __global__ void __launch_bounds__(1024) k_big_asm(Shape S, Tab tb, Ws ws) {
   T* A = (T*)ws.ebuf + e * (int64_t)G.Rp * G.Rp;
   double* ath = ws.ath + e * (int64_t)np * np;
   const int wid = tid() >> 6, lane = tid() & 63;
-  double* wv = wscr + wid * K * ns;
+  double* wv = wscr + wid * (K + 1) * ns;
   for (int c = wid; c < R; c += 16) {
-    column_weights(S, L, c, lane, wv);
+    column_weights(S, tb, L, inst, jac, c, lane, wv);
     for (int r = c + lane; r < R; r += 64) {
       const bool tt = r >= b && r < b + np && c >= b;   // theta-theta: FP64 side array
       const double v = big_entry(S, L, i, h, dw, r, c, wv);
-      if (tt) {
-        ath[(r - b) * np + (c - b)] = v;
-        A[r + (int64_t)c * G.Rp] = (T)0;
-      } else {
-        A[r + (int64_t)c * G.Rp] = (T)v;
-      }
+      if (tt) ath[(r - b) * np + (c - b)] = v;
+      else A[r + (int64_t)c * G.Rp] = (T)v;
     }
     wave_sync();
   }
@@ -455,7 +466,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
 // and shared by its tiles.  Tiles inside [skip0, skip1)^2 are not computed.
 template <typename T>
 __global__ void __launch_bounds__(256) k_pchol_syrk(Tab tb, Ws ws, PArgs a) {
-  constexpr int TM = 64, KC = 16;
+  constexpr int TM = 64, KC = 32, NL = KC * TM / 256;
   __shared__ T sA[KC * TM];
   __shared__ T sB[KC * TM];
   typedef typename Mma<T>::acc acc_t;
@@ -476,16 +487,26 @@ __global__ void __launch_bounds__(256) k_pchol_syrk(Tab tb, Ws ws, PArgs a) {
   T* A = (T*)a.base + mat * a.stride;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, wr = w >> 1, wc = w & 1;
   acc_t c00 = {0, 0, 0, 0}, c01 = {0, 0, 0, 0}, c10 = {0, 0, 0, 0}, c11 = {0, 0, 0, 0};
+  T ra[NL], rb[NL];
+  auto load = [&](int kc) {
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int ii = t & (TM - 1), kk = (t >> 6) + 4 * q, k = kc + kk;
+      const int r = R0 + ii, c = C0 + ii;
+      ra[q] = (r < n && k < m) ? A[r + (int64_t)k * ld] : (T)0;
+      rb[q] = (c < n && k < m) ? A[c + (int64_t)k * ld] : (T)0;
+    }
+  };
+  load(0);
   for (int kc = 0; kc < m; kc += KC) {
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < (KC * TM) / 256; ++q) {
-      const int idx = t + 256 * q, ii = idx & (TM - 1), kk = idx / TM, k = kc + kk;
-      const int r = R0 + ii, c = C0 + ii;
-      sA[kk * TM + ii] = (r < n && k < m) ? A[r + (int64_t)k * ld] : (T)0;
-      sB[kk * TM + ii] = (c < n && k < m) ? A[c + (int64_t)k * ld] : (T)0;
+    for (int q = 0; q < NL; ++q) {
+      sA[((t >> 6) + 4 * q) * TM + (t & (TM - 1))] = ra[q];
+      sB[((t >> 6) + 4 * q) * TM + (t & (TM - 1))] = rb[q];
     }
     __syncthreads();
+    if (kc + KC < m) load(kc + KC);
 #pragma unroll
     for (int s = 0; s < KC / 4; ++s) {
       const int kk = 4 * s + (lane >> 4), li = lane & 15;
@@ -499,11 +520,11 @@ __global__ void __launch_bounds__(256) k_pchol_syrk(Tab tb, Ws ws, PArgs a) {
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const int rb = R0 + 32 * wr + Mma<T>::row(lane, v), cb = C0 + 32 * wc + (lane & 15);
+    const int rb0 = R0 + 32 * wr + Mma<T>::row(lane, v), cb = C0 + 32 * wc + (lane & 15);
     const T vals[4] = {c00[v], c01[v], c10[v], c11[v]};
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int r = rb + 16 * (q >> 1), c = cb + 16 * (q & 1);
+      const int r = rb0 + 16 * (q >> 1), c = cb + 16 * (q & 1);
       if (r < n && c < n && r >= c) {
         T* p = A + r + (int64_t)c * ld;
         *p = a.zero ? -vals[q] : *p - vals[q];
@@ -604,7 +625,7 @@ __global__ void __launch_bounds__(256) k_sep_step(Shape S, Tab tb, Ws ws, int le
 // columns each).  grid (chunk, tile, instance).
 template <typename T>
 __global__ void __launch_bounds__(256) k_big_theta(Shape S, Tab tb, Ws ws) {
-  constexpr int TM = 64, KC = 16;
+  constexpr int TM = 64, KC = 32, NL = KC * TM / 256;
   __shared__ double sA[KC * TM];
   __shared__ double sB[KC * TM];
   const int inst = blockIdx.z, chunk = blockIdx.x, tile = blockIdx.y;
@@ -627,15 +648,25 @@ __global__ void __launch_bounds__(256) k_big_theta(Shape S, Tab tb, Ws ws) {
       const T* X = src == 0 ? (const T*)ws.ebuf + (e0 + ii) * (int64_t)G.Rp * G.Rp + b
                             : (const T*)ws.sbuf + (e0 + ii) * (int64_t)G.Lp * G.Lp + 3 * ns;
       const int ldx = src == 0 ? G.Rp : G.Lp, kn = src == 0 ? mI : ns;
+      double ra[NL], rb[NL];
+      auto load = [&](int kc) {
+#pragma unroll
+        for (int q = 0; q < NL; ++q) {
+          const int r = t & (TM - 1), kk = (t >> 6) + 4 * q, k = kc + kk;
+          ra[q] = (R0 + r < np && k < kn) ? (double)X[R0 + r + (int64_t)k * ldx] : 0.0;
+          rb[q] = (C0 + r < np && k < kn) ? (double)X[C0 + r + (int64_t)k * ldx] : 0.0;
+        }
+      };
+      load(0);
       for (int kc = 0; kc < kn; kc += KC) {
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < (KC * TM) / 256; ++q) {
-          const int idx = t + 256 * q, r = idx & (TM - 1), kk = idx / TM, k = kc + kk;
-          sA[kk * TM + r] = (R0 + r < np && k < kn) ? (double)X[R0 + r + (int64_t)k * ldx] : 0.0;
-          sB[kk * TM + r] = (C0 + r < np && k < kn) ? (double)X[C0 + r + (int64_t)k * ldx] : 0.0;
+        for (int q = 0; q < NL; ++q) {
+          sA[((t >> 6) + 4 * q) * TM + (t & (TM - 1))] = ra[q];
+          sB[((t >> 6) + 4 * q) * TM + (t & (TM - 1))] = rb[q];
         }
         __syncthreads();
+        if (kc + KC < kn) load(kc + KC);
 #pragma unroll
         for (int s = 0; s < KC / 4; ++s) {
           const int kk = 4 * s + (lane >> 4), li = lane & 15;
