@@ -130,6 +130,7 @@ struct Ws {
   double* bbuf;               // [n_inst][Bp x Bp] border matrices / factors (FP64)
   double* evec;               // [n_elem][Rp] element forward vectors
   double* svec;               // [n_elem][Lp] separator forward vectors
+  double* linv;               // [n_elem][32 x 32] inverse diagonal factors of the current panel
 };
 
 // Element partial-sum slots (colloc_eval and the interior-point reductions).

@@ -655,6 +655,7 @@ static Ws ws_layout(const colloc_problem* p, int prec, void* base, size_t* bytes
     w.evec = c.take<double>(E * G.Rp);
     w.svec = c.take<double>(E * G.Lp);
     w.bbuf = c.take<double>(I * G.Bp * G.Bp);
+    w.linv = c.take<double>(E * 32 * 32);
     w.ebuf = c.take<char>(E * G.Rp * G.Rp, sz);
     w.sbuf = c.take<char>(E * G.Lp * G.Lp, sz);
   }

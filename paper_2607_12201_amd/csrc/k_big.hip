@@ -6,15 +6,17 @@
 //   assembly   k_big_asm       one workgroup per element writes the lower triangle of its
 //                              matrix over [z | theta | P] (eq. 2b-2d through J^T Ds J + W) from
 //                              the per-pattern derivative values, the theta-theta block in FP64
-//   level 0    k_pchol_panel   left-looking partial Cholesky of the interior columns, 32-column
-//                              panels, updates as 16x16x4 matrix-core products
+//   level 0    k_pchol_diag / k_pchol_strip  left-looking partial Cholesky of the interior
+//                              columns in 32-column panels: the diagonal block (one wave per
+//                              matrix), then the strips below it (one wave per 32 rows), updates
+//                              and solves as 16x16x4 matrix-core products
 //              k_pchol_syrk    trailing Schur complement (all rows below the interior block)
 //                              as matrix-core tiles, the tiles of one element on one XCD
 //   chain      k_sep_init / k_sep_step gather each separator's local matrix; the same two
 //                              kernels eliminate the separators of every cyclic-reduction level
 //   border     k_big_theta     theta-theta Schur complement in FP64 on matrix cores, split over
 //                              16-element chunks (fixed order); k_border_build sums the chunks
-//                              into the border matrix, k_pchol_panel factors it
+//                              into the border matrix, the same panel kernels factor it
 //   solve      blocked forward/backward substitution through the same levels (FP64 vectors)
 #include <stdio.h>
 #include <stdlib.h>
@@ -320,25 +322,81 @@ __global__ void __launch_bounds__(1024) k_big_asm(Shape S, Tab tb, Ws ws) {
 
 // ---------------------------------------------------------------- partial Cholesky
 // Left-looking partial Cholesky of the first m columns of an n x n SPD matrix (lower triangle,
-// column-major, leading dimension ld), one workgroup of four waves per matrix.  Columns are
-// eliminated in panels of 32: the panel's rows are brought up to date with all earlier panels in
-// chunks of 128 rows (C = A - L_rows L_panel^T as 16x16x4 matrix-core products, operands staged
-// through LDS 32 columns at a time, the next 32 loaded into registers while the current ones are
-// multiplied), then the panel's 32 x 32 diagonal block is factored by one wave and every row
-// below it solved against that factor in registers (FP64 arithmetic), and the chunk is stored
-// back.  A non-positive or non-finite pivot sets the instance's flag.
+// column-major, leading dimension ld), for every matrix of a batch.  Columns are eliminated in
+// panels of 32, each in two launches:
+//   k_pchol_diag   one wave per matrix brings the panel's 32 x 32 diagonal block up to date with
+//                  the earlier columns, factors it (each lane one row in registers) and writes the
+//                  factor, and its inverse (FP64, row-major) to ws.linv
+//   k_pchol_strip  one wave per 32-row strip below: C = A - L_strip L_panel^T, then X = C L^-T,
+//                  both as 16x16x4 matrix-core products, with no LDS: the update is formed
+//                  transposed (L_panel L_strip^T), and that accumulator is already laid out as
+//                  the operand of the solve X^T = L^-1 C^T
+// A non-positive or non-finite pivot sets the instance's flag; later launches skip the instance.
+
+// Update products of a 32-row strip (rows r0..) with the panel (rows k0..) over the columns
+// [0, k0): acc[jt][rt] element v of the lane = sum_k L[k0 + 16 jt + i][k] L[r0 + 16 rt + li][k],
+// i = Mma<T>::row(lane, v), the (panel, strip) block of L L^T transposed.  Operands are loaded
+// from memory straight into the product's register layout (32-bit byte offsets from the matrix
+// base, rows clamped to the matrix: rows past its end give products that are never used), the
+// next 16 columns in flight while the current ones are multiplied.  k0 is a multiple of 32.
 template <typename T>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_pchol_panel(Tab tb, Ws ws, PArgs a) {
-  constexpr int NB = 32, CH = 128, KC = 32, PC = NB + 1;
-  constexpr int NA = KC * CH / 256, NBL = KC * NB / 256;   // staged values per thread
-  constexpr int STAGE = (KC * CH + KC * NB) * (int)sizeof(T), CBYTES = CH * PC * 8;
-  __shared__ double raw[(STAGE > CBYTES ? STAGE : CBYTES) / 8];
-  __shared__ double sL[NB * PC];
-  __shared__ double sR[NB];
-  __shared__ int sflag;
-  T* sA = (T*)raw;
-  T* sB = sA + KC * CH;
-  double* sC = raw;   // the chunk's values, after the products (shares the staging area)
+__device__ inline void panel_products(const T* A, int ld, int n, int k0, int r0, int lane,
+                                      typename Mma<T>::acc (&c)[2][2]) {
+  constexpr int KU = 4;
+  const int li = lane & 15, lk = lane >> 4;
+  const char* base = (const char*)A;
+  const uint32_t cs = (uint32_t)ld * sizeof(T);
+  const uint32_t op0 = (uint32_t)min(k0 + li, n - 1) * sizeof(T) + lk * cs;
+  const uint32_t op1 = (uint32_t)min(k0 + 16 + li, n - 1) * sizeof(T) + lk * cs;
+  const uint32_t os0 = (uint32_t)min(r0 + li, n - 1) * sizeof(T) + lk * cs;
+  const uint32_t os1 = (uint32_t)min(r0 + 16 + li, n - 1) * sizeof(T) + lk * cs;
+  T cp0[KU], cp1[KU], cs0[KU], cs1[KU], np0[KU], np1[KU], ns0[KU], ns1[KU];
+  auto load = [&](int kc, T* p0, T* p1, T* s0, T* s1) {
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+      const uint32_t off = (uint32_t)(kc + 4 * u) * cs;
+      p0[u] = *(const T*)(base + (op0 + off));
+      p1[u] = *(const T*)(base + (op1 + off));
+      s0[u] = *(const T*)(base + (os0 + off));
+      s1[u] = *(const T*)(base + (os1 + off));
+    }
+  };
+  auto mult = [&](const T* p0, const T* p1, const T* s0, const T* s1) {
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+      c[0][0] = Mma<T>::mma(p0[u], s0[u], c[0][0]);
+      c[0][1] = Mma<T>::mma(p0[u], s1[u], c[0][1]);
+      c[1][0] = Mma<T>::mma(p1[u], s0[u], c[1][0]);
+      c[1][1] = Mma<T>::mma(p1[u], s1[u], c[1][1]);
+    }
+  };
+  if (k0 == 0) return;
+  load(0, cp0, cp1, cs0, cs1);
+  for (int kc = 0; kc < k0; kc += 8 * KU) {
+    load(kc + 4 * KU, np0, np1, ns0, ns1);
+    mult(cp0, cp1, cs0, cs1);
+    if (kc + 8 * KU < k0) load(kc + 8 * KU, cp0, cp1, cs0, cs1);
+    mult(np0, np1, ns0, ns1);
+  }
+}
+
+// threadIdx.x % 64 through an empty asm: values derived from it are neither hoisted out of
+// loops nor kept alive between the points where it is re-read (register pressure in long
+// unrolled code)
+__device__ inline int opaque_lane() {
+  int l = threadIdx.x & 63;
+  __asm__ volatile("" : "+v"(l));
+  return l;
+}
+
+// One wave per matrix: the diagonal block of the panel at column k0 (wd = min(32, m - k0)
+// columns, padded with the identity), its factor into the matrix and its inverse into
+// ws.linv[item] (32 x 32, row-major).
+template <typename T>
+__global__ void __launch_bounds__(64) k_pchol_diag(Tab tb, Ws ws, PArgs a, int k0) {
+  constexpr int NB = 32, PC = NB + 1;
+  __shared__ double sC[NB * PC];   // the updated block, then the factor, then its inverse
+  __shared__ double sR[NB];        // reciprocals of the pivots' square roots
   typedef typename Mma<T>::acc acc_t;
   if ((int)blockIdx.x >= a.count) return;
   int64_t mat;
@@ -346,118 +404,143 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
   pitem(tb, a, blockIdx.x, mat, inst);
   if (block_flag(&ws.flag[inst])) return;
   T* A = (T*)a.base + mat * a.stride;
-  const int n = a.n, m = a.m, ld = a.ld;
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  for (int k0 = 0; k0 < m; k0 += NB) {
-    const int wd = min(NB, m - k0);
-    // the previous panel's columns, stored by every thread, are this panel's operands
-    __syncthreads();
-    for (int r0 = k0; r0 < n; r0 += CH) {
-      acc_t c00 = {0, 0, 0, 0}, c01 = {0, 0, 0, 0}, c10 = {0, 0, 0, 0}, c11 = {0, 0, 0, 0};
-      T ra[NA], rb[NBL];
-      auto load = [&](int kc) {
+  const int n = a.n, ld = a.ld, wd = min(NB, a.m - k0);
+  int lane = opaque_lane();
+  {
+    acc_t c[2][2] = {{{0, 0, 0, 0}, {0, 0, 0, 0}}, {{0, 0, 0, 0}, {0, 0, 0, 0}}};
+    panel_products<T>(A, ld, n, k0, k0, lane, c);
+    const int li = lane & 15;
 #pragma unroll
-        for (int q = 0; q < NA; ++q) {
-          const int ii = t & (CH - 1), kk = (t >> 7) + 2 * q, r = r0 + ii;
-          ra[q] = r < n ? A[r + (int64_t)(kc + kk) * ld] : (T)0;
+    for (int jt = 0; jt < 2; ++jt)
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int j = 16 * jt + Mma<T>::row(lane, v), r = 16 * rt + li;
+          const int hi = min(max(r, j), wd - 1), lo = min(min(r, j), wd - 1);   // lower triangle, clamped
+          sC[r * PC + j] = (double)A[k0 + hi + (int64_t)(k0 + lo) * ld] - (double)c[jt][rt][v];
         }
+  }
+  wave_sync();
+  lane = opaque_lane();
+  const int r = lane & 31;
+  double x[NB];
 #pragma unroll
-        for (int q = 0; q < NBL; ++q) {
-          const int j = t & (NB - 1), kk = (t >> 5) + 8 * q;
-          rb[q] = j < wd ? A[(k0 + j) + (int64_t)(kc + kk) * ld] : (T)0;
-        }
-      };
-      if (k0 > 0) load(0);
-      for (int kc = 0; kc < k0; kc += KC) {
-        __syncthreads();
+  for (int j = 0; j < NB; ++j) x[j] = (r < wd) ? (j < wd ? sC[r * PC + j] : 0.0) : (r == j ? 1.0 : 0.0);
+  wave_sync();
+  bool good = true;
+  // column j of the updated block passes through row j of sC; lane r keeps row r
 #pragma unroll
-        for (int q = 0; q < NA; ++q) sA[((t >> 7) + 2 * q) * CH + (t & (CH - 1))] = ra[q];
+  for (int j = 0; j < NB; ++j) {
+    if (lane < NB) sC[j * PC + lane] = x[j];
+    wave_sync();
+    const double piv = sC[j * PC + j];
+    if (j < wd) good = good && piv > 0.0 && isfinite(piv);
+    const double d = sqrt(piv), inv = 1.0 / d, l = x[j] * inv;
 #pragma unroll
-        for (int q = 0; q < NBL; ++q) sB[((t >> 5) + 8 * q) * NB + (t & (NB - 1))] = rb[q];
-        __syncthreads();
-        if (kc + KC < k0) load(kc + KC);
+    for (int k = j + 1; k < NB; ++k) x[k] -= l * (sC[j * PC + k] * inv);
+    x[j] = (r == j) ? d : l;
+    if (lane == 0) sR[j] = inv;
+    // the updates happen at this step (not sunk towards their use, which would keep every
+    // step's multipliers alive)
 #pragma unroll
-        for (int s = 0; s < KC / 4; ++s) {
-          const int kk = 4 * s + (lane >> 4), li = lane & 15;
-          const T a0 = sA[kk * CH + 32 * w + li], a1 = sA[kk * CH + 32 * w + 16 + li];
-          const T b0 = sB[kk * NB + li], b1 = sB[kk * NB + 16 + li];
-          c00 = Mma<T>::mma(a0, b0, c00);
-          c01 = Mma<T>::mma(a0, b1, c01);
-          c10 = Mma<T>::mma(a1, b0, c10);
-          c11 = Mma<T>::mma(a1, b1, c11);
-        }
-      }
-      __syncthreads();
+    for (int k = j + 1; k < NB; ++k) __asm__ volatile("" : "+v"(x[k]));
+  }
+  if (!good) {
+    if (lane == 0) atomicOr(&ws.flag[inst], 1);
+    return;
+  }
+  wave_sync();
+  if (lane < NB) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int rr = 32 * w + Mma<T>::row(lane, v), cc = lane & 15;
-        sC[rr * PC + cc] = (double)c00[v];
-        sC[rr * PC + 16 + cc] = (double)c01[v];
-        sC[(rr + 16) * PC + cc] = (double)c10[v];
-        sC[(rr + 16) * PC + 16 + cc] = (double)c11[v];
-      }
-      __syncthreads();
-      for (int idx = t; idx < CH * NB; idx += 256) {
-        const int ii = idx & (CH - 1), j = idx / CH, r = r0 + ii;
-        if (r < n && j < wd && r >= k0 + j) sC[ii * PC + j] = (double)A[r + (int64_t)(k0 + j) * ld] - sC[ii * PC + j];
-      }
-      __syncthreads();
-      int i0 = 0;
-      if (r0 == k0) {   // the chunk holds the panel's diagonal block: factor it (wave 0)
-        if (w == 0) {
-          bool good = true;
-          for (int j = 0; j < wd; ++j) {
-            const double piv = sC[j * PC + j];
-            good = good && piv > 0.0 && isfinite(piv);
-            const double ljj = good ? sqrt(piv) : 1.0;
-            __builtin_amdgcn_wave_barrier();
-            if (lane == j) sC[j * PC + j] = ljj;
-            if (lane > j && lane < wd) sC[lane * PC + j] /= ljj;
-            __builtin_amdgcn_wave_barrier();
-            if (lane > j && lane < wd) {
-              const double lij = sC[lane * PC + j];
-              for (int jj = j + 1; jj <= lane; ++jj) sC[lane * PC + jj] -= lij * sC[jj * PC + j];
-            }
-            __builtin_amdgcn_wave_barrier();
-          }
-          if (lane == 0) sflag = good ? 1 : 0;
-        }
-        __syncthreads();
-        if (!sflag) {
-          if (t == 0) atomicOr(&ws.flag[inst], 1);
-          return;
-        }
-        for (int idx = t; idx < NB * NB; idx += 256) {
-          const int ii = idx / NB, j = idx - ii * NB;
-          sL[ii * PC + j] = (ii < wd && j <= ii) ? sC[ii * PC + j] : 0.0;
-        }
-        if (t < NB) sR[t] = t < wd ? 1.0 / sC[t * PC + t] : 0.0;
-        __syncthreads();
-        i0 = wd;
-      }
-      // rows below the diagonal block: x = c L^{-T}, one thread per row, the row in registers
-      for (int ii = i0 + t; ii < CH && r0 + ii < n; ii += 256) {
-        double x[NB];
-#pragma unroll
-        for (int j = 0; j < NB; ++j) x[j] = sC[ii * PC + j];
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-          double s = x[j];
-#pragma unroll
-          for (int p = 0; p < j; ++p) s -= x[p] * sL[j * PC + p];
-          x[j] = s * sR[j];
-          __asm__ volatile("" ::: "memory");   // keep the factor reads of row j here (registers)
-        }
-#pragma unroll
-        for (int j = 0; j < NB; ++j) sC[ii * PC + j] = x[j];
-      }
-      __syncthreads();
-      for (int idx = t; idx < CH * NB; idx += 256) {
-        const int ii = idx & (CH - 1), j = idx / CH, r = r0 + ii;
-        if (r < n && j < wd && r >= k0 + j) A[r + (int64_t)(k0 + j) * ld] = (T)sC[ii * PC + j];
-      }
+    for (int j = 0; j < NB; ++j) {
+      sC[r * PC + j] = j <= r ? x[j] : 0.0;
+      if (j <= r && r < wd) A[k0 + r + (int64_t)(k0 + j) * ld] = (T)x[j];
     }
   }
+  wave_sync();
+  // inverse: lane c forms column c by forward substitution; every lane reads row i of the
+  // factor before row i of the inverse replaces it
+  double* Li = ws.linv + (int64_t)blockIdx.x * NB * NB;
+  double y[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    double sum = (i == r) ? 1.0 : 0.0;
+#pragma unroll
+    for (int p = 0; p < i; ++p) sum -= sC[i * PC + p] * y[p];
+    y[i] = sum * sR[i];
+    if (lane < NB) Li[i * NB + r] = y[i];
+    __asm__ volatile("" ::: "memory");   // row by row: keeps the factor reads from piling up in registers
+  }
+}
+
+// Strips below the diagonal block of the panel at column k0: grid = items x groups of four
+// strips (one per wave), the groups of one item on one XCD (block id mod 8) in consecutive
+// dispatch order so that its panel rows and inverse factor are shared through that XCD's L2.
+// Strips start at s0 (0 when the panel is narrower than 32 and its diagonal strip holds rows
+// below the block); only rows at or below k0 + wd are written.
+template <typename T>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+k_pchol_strip(Tab tb, Ws ws, PArgs a, int k0, int s0, int groups) {
+  constexpr int NB = 32;
+  typedef typename Mma<T>::acc acc_t;
+  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  const int item = (slot / groups) * 8 + xcd, g = slot % groups;
+  if (item >= a.count) return;
+  int64_t mat;
+  int inst;
+  pitem(tb, a, item, mat, inst);
+  if (block_flag(&ws.flag[inst])) return;
+  const int n = a.n, ld = a.ld, wd = min(NB, a.m - k0);
+  const int r0 = k0 + NB * (s0 + 4 * g + (int)(threadIdx.x >> 6));
+  if (r0 >= n) return;
+  T* A = (T*)a.base + mat * a.stride;
+  int lane = opaque_lane();
+  acc_t c[2][2] = {{{0, 0, 0, 0}, {0, 0, 0, 0}}, {{0, 0, 0, 0}, {0, 0, 0, 0}}};
+  panel_products<T>(A, ld, n, k0, r0, lane, c);
+  // C^T = A^T - products (FP64), in place of the accumulators' layout; 0 right of the panel
+  lane = opaque_lane();
+  const int li = lane & 15, lk = lane >> 4;
+  double ct[2][2][4];
+#pragma unroll
+  for (int jt = 0; jt < 2; ++jt)
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int j = 16 * jt + Mma<T>::row(lane, v), r = min(r0 + 16 * rt + li, n - 1);
+        const double av = (double)A[r + (int64_t)(k0 + min(j, wd - 1)) * ld];
+        ct[jt][rt][v] = j < wd ? av - (double)c[jt][rt][v] : 0.0;
+      }
+  // X^T = L^-1 C^T on matrix cores: K index j of step (jt, v) for lane group lk is
+  // 16 jt + Mma<T>::row(lane, v), the layout the update products left C^T in; the inverse is
+  // lower triangular, so rows [0, 16) of X^T need only j < 16
+  const double* Li = ws.linv + (int64_t)item * NB * NB;
+  dvec4 x[2][2] = {{{0, 0, 0, 0}, {0, 0, 0, 0}}, {{0, 0, 0, 0}, {0, 0, 0, 0}}};
+#pragma unroll
+  for (int jt = 0; jt < 2; ++jt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int j = 16 * jt + Mma<T>::row(lane, v);
+      const double a1 = Li[(16 + li) * NB + j];
+      x[1][0] = Mma<double>::mma(a1, ct[jt][0][v], x[1][0]);
+      x[1][1] = Mma<double>::mma(a1, ct[jt][1][v], x[1][1]);
+      if (jt == 0) {
+        const double a0 = Li[li * NB + j];
+        x[0][0] = Mma<double>::mma(a0, ct[0][0][v], x[0][0]);
+        x[0][1] = Mma<double>::mma(a0, ct[0][1][v], x[0][1]);
+      }
+    }
+  // element v of x[ct][rt]: X[r0 + 16 rt + li][k0 + 16 ct + lk + 4 v]
+#pragma unroll
+  for (int ctl = 0; ctl < 2; ++ctl)
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = r0 + 16 * rt + li, j = 16 * ctl + lk + 4 * v;
+        if (j < wd && r < n && r >= k0 + wd) A[r + (int64_t)(k0 + j) * ld] = (T)x[ctl][rt][v];
+      }
 }
 
 // Trailing update C = C - X X^T (or -X X^T when the block starts at zero) of the rows and columns
@@ -1044,6 +1127,23 @@ static void syrk(const Tab& tb, const Ws& ws, PArgs a, hipStream_t st) {
   hipLaunchKernelGGL(k_pchol_syrk<T>, dim3(grid), dim3(256), 0, st, tb, ws, a);
 }
 
+// Partial Cholesky of the first a.m columns of every matrix of the batch: two launches per panel
+// of 32 columns (the diagonal block, then the strips below it).
+template <typename T>
+static void pchol(const Tab& tb, const Ws& ws, const PArgs& a, hipStream_t st) {
+  if (a.count == 0) return;
+  for (int k0 = 0; k0 < a.m; k0 += 32) {
+    const int wd = std::min(32, a.m - k0);
+    hipLaunchKernelGGL(k_pchol_diag<T>, dim3(a.count), dim3(64), 0, st, tb, ws, a, k0);
+    if (a.n <= k0 + wd) continue;   // no rows below the block
+    const int s0 = wd < 32 ? 0 : 1;
+    const int nstrip = (int)cl_ceil_div(a.n - k0, 32) - s0;
+    const int groups = (int)cl_ceil_div(nstrip, 4);
+    const unsigned grid = (unsigned)(cl_ceil_div(a.count, 8) * 8 * groups);
+    hipLaunchKernelGGL(k_pchol_strip<T>, dim3(grid), dim3(256), 0, st, tb, ws, a, k0, s0, groups);
+  }
+}
+
 template <typename T>
 static int big_factor_t(const Shape& S, const Tab& tb, const HostPlan& hp, const Ws& ws, phase_cb cb,
                         void* ctx, hipStream_t st) {
@@ -1055,7 +1155,7 @@ static int big_factor_t(const Shape& S, const Tab& tb, const HostPlan& hp, const
   if (cb) cb(ctx, COLLOC_PH_ASSEMBLY, 0, st);
   if (cb) cb(ctx, COLLOC_PH_LEVEL0, 1, st);
   PArgs ea = pargs(ws.ebuf, esz, G.Rp, S.R, S.mI, E, 0, 0);
-  hipLaunchKernelGGL(k_pchol_panel<T>, dim3(E), dim3(256), 0, st, tb, ws, ea);
+  pchol<T>(tb, ws, ea, st);
   if (cb) cb(ctx, COLLOC_PH_LEVEL0, 0, st);
   if (cb) cb(ctx, COLLOC_PH_SCHUR, 1, st);
   // the theta-theta block is formed by k_big_theta; its tiles here are skipped
@@ -1071,7 +1171,7 @@ static int big_factor_t(const Shape& S, const Tab& tb, const HostPlan& hp, const
     const int cnt = hp.lvl[l];
     if (cnt == 0) continue;
     PArgs ca = pargs(ws.sbuf, ssz, G.Lp, G.Lr, S.ns, cnt, 1, l);
-    hipLaunchKernelGGL(k_pchol_panel<T>, dim3(cnt), dim3(256), 0, st, tb, ws, ca);
+    pchol<T>(tb, ws, ca, st);
     ca.zero = 1;
     ca.skip0 = 3 * S.ns;
     ca.skip1 = G.Lr;
@@ -1087,7 +1187,7 @@ static int big_factor_t(const Shape& S, const Tab& tb, const HostPlan& hp, const
     hipLaunchKernelGGL(k_border_theta, dim3((unsigned)cl_ceil_div(S.np * S.np, 256), tb.n_inst), dim3(256), 0, st,
                        S, tb, ws);
   PArgs ba = pargs(ws.bbuf, (int64_t)G.Bp * G.Bp, G.Bp, G.Br, G.Br, tb.n_inst, 2, 0);
-  hipLaunchKernelGGL(k_pchol_panel<double>, dim3(tb.n_inst), dim3(256), 0, st, tb, ws, ba);
+  pchol<double>(tb, ws, ba, st);
   if (cb) cb(ctx, 3, 0, st);
   return ok_or();
 }
