@@ -333,50 +333,59 @@ __global__ void __launch_bounds__(1024) k_big_asm(Shape S, Tab tb, Ws ws) {
 //                  the operand of the solve X^T = L^-1 C^T
 // A non-positive or non-finite pivot sets the instance's flag; later launches skip the instance.
 
-// Update products of a 32-row strip (rows r0..) with the panel (rows k0..) over the columns
-// [0, k0): acc[jt][rt] element v of the lane = sum_k L[k0 + 16 jt + i][k] L[r0 + 16 rt + li][k],
-// i = Mma<T>::row(lane, v), the (panel, strip) block of L L^T transposed.  Operands are loaded
-// from memory straight into the product's register layout (32-bit byte offsets from the matrix
-// base, rows clamped to the matrix: rows past its end give products that are never used), the
-// next 16 columns in flight while the current ones are multiplied.  k0 is a multiple of 32.
-template <typename T>
-__device__ inline void panel_products(const T* A, int ld, int n, int k0, int r0, int lane,
-                                      typename Mma<T>::acc (&c)[2][2]) {
-  constexpr int KU = 4;
+// Update products of a 32-row strip (rows r0..) with NP panels of 32 rows (rows pr, pr + 32, ..)
+// over the columns [kb, ke): acc[q][jt][rt] element v of the lane = sum_k L[pr + 32 q + 16 jt + i][k]
+// L[r0 + 16 rt + li][k], i = Mma<T>::row(lane, v): the (panel, strip) blocks of L L^T transposed.
+// Operands are loaded from memory straight into the product's register layout (32-bit byte
+// offsets from the matrix base, rows clamped to the matrix: rows past its end give products that
+// are never used), the next columns in flight while the current ones are multiplied.  ke - kb is
+// a multiple of 16.
+template <typename T, int NP>
+__device__ inline void panel_products(const T* A, int ld, int n, int kb, int ke, int pr, int r0, int lane,
+                                      typename Mma<T>::acc (&c)[NP][2][2]) {
+  constexpr int KU = NP == 1 ? 4 : 2;
   const int li = lane & 15, lk = lane >> 4;
   const char* base = (const char*)A;
   const uint32_t cs = (uint32_t)ld * sizeof(T);
-  const uint32_t op0 = (uint32_t)min(k0 + li, n - 1) * sizeof(T) + lk * cs;
-  const uint32_t op1 = (uint32_t)min(k0 + 16 + li, n - 1) * sizeof(T) + lk * cs;
+  uint32_t op[NP][2];
+#pragma unroll
+  for (int q = 0; q < NP; ++q)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) op[q][h] = (uint32_t)min(pr + 32 * q + 16 * h + li, n - 1) * sizeof(T) + lk * cs;
   const uint32_t os0 = (uint32_t)min(r0 + li, n - 1) * sizeof(T) + lk * cs;
   const uint32_t os1 = (uint32_t)min(r0 + 16 + li, n - 1) * sizeof(T) + lk * cs;
-  T cp0[KU], cp1[KU], cs0[KU], cs1[KU], np0[KU], np1[KU], ns0[KU], ns1[KU];
-  auto load = [&](int kc, T* p0, T* p1, T* s0, T* s1) {
+  T cp[NP][2][KU], cs0[KU], cs1[KU], np_[NP][2][KU], ns0[KU], ns1[KU];
+  auto load = [&](int kc, T (&p)[NP][2][KU], T* s0, T* s1) {
 #pragma unroll
     for (int u = 0; u < KU; ++u) {
       const uint32_t off = (uint32_t)(kc + 4 * u) * cs;
-      p0[u] = *(const T*)(base + (op0 + off));
-      p1[u] = *(const T*)(base + (op1 + off));
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        p[q][0][u] = *(const T*)(base + (op[q][0] + off));
+        p[q][1][u] = *(const T*)(base + (op[q][1] + off));
+      }
       s0[u] = *(const T*)(base + (os0 + off));
       s1[u] = *(const T*)(base + (os1 + off));
     }
   };
-  auto mult = [&](const T* p0, const T* p1, const T* s0, const T* s1) {
+  auto mult = [&](const T (&p)[NP][2][KU], const T* s0, const T* s1) {
 #pragma unroll
-    for (int u = 0; u < KU; ++u) {
-      c[0][0] = Mma<T>::mma(p0[u], s0[u], c[0][0]);
-      c[0][1] = Mma<T>::mma(p0[u], s1[u], c[0][1]);
-      c[1][0] = Mma<T>::mma(p1[u], s0[u], c[1][0]);
-      c[1][1] = Mma<T>::mma(p1[u], s1[u], c[1][1]);
-    }
+    for (int u = 0; u < KU; ++u)
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        c[q][0][0] = Mma<T>::mma(p[q][0][u], s0[u], c[q][0][0]);
+        c[q][0][1] = Mma<T>::mma(p[q][0][u], s1[u], c[q][0][1]);
+        c[q][1][0] = Mma<T>::mma(p[q][1][u], s0[u], c[q][1][0]);
+        c[q][1][1] = Mma<T>::mma(p[q][1][u], s1[u], c[q][1][1]);
+      }
   };
-  if (k0 == 0) return;
-  load(0, cp0, cp1, cs0, cs1);
-  for (int kc = 0; kc < k0; kc += 8 * KU) {
-    load(kc + 4 * KU, np0, np1, ns0, ns1);
-    mult(cp0, cp1, cs0, cs1);
-    if (kc + 8 * KU < k0) load(kc + 8 * KU, cp0, cp1, cs0, cs1);
-    mult(np0, np1, ns0, ns1);
+  if (ke <= kb) return;
+  load(kb, cp, cs0, cs1);
+  for (int kc = kb; kc < ke; kc += 8 * KU) {
+    load(kc + 4 * KU, np_, ns0, ns1);
+    mult(cp, cs0, cs1);
+    if (kc + 8 * KU < ke) load(kc + 8 * KU, cp, cs0, cs1);
+    mult(np_, ns0, ns1);
   }
 }
 
@@ -390,10 +399,11 @@ __device__ inline int opaque_lane() {
 }
 
 // One wave per matrix: the diagonal block of the panel at column k0 (wd = min(32, m - k0)
-// columns, padded with the identity), its factor into the matrix and its inverse into
-// ws.linv[item] (32 x 32, row-major).
+// columns, padded with the identity) brought up to date with the columns [kb, k0) (the earlier
+// ones are already applied), its factor into the matrix and its inverse into ws.linv[item]
+// (32 x 32, row-major).
 template <typename T>
-__global__ void __launch_bounds__(64) k_pchol_diag(Tab tb, Ws ws, PArgs a, int k0) {
+__global__ void __launch_bounds__(64) k_pchol_diag(Tab tb, Ws ws, PArgs a, int k0, int kb) {
   constexpr int NB = 32, PC = NB + 1;
   __shared__ double sC[NB * PC];   // the updated block, then the factor, then its inverse
   __shared__ double sR[NB];        // reciprocals of the pivots' square roots
@@ -407,8 +417,8 @@ __global__ void __launch_bounds__(64) k_pchol_diag(Tab tb, Ws ws, PArgs a, int k
   const int n = a.n, ld = a.ld, wd = min(NB, a.m - k0);
   int lane = opaque_lane();
   {
-    acc_t c[2][2] = {{{0, 0, 0, 0}, {0, 0, 0, 0}}, {{0, 0, 0, 0}, {0, 0, 0, 0}}};
-    panel_products<T>(A, ld, n, k0, k0, lane, c);
+    acc_t c[1][2][2] = {{{{0, 0, 0, 0}, {0, 0, 0, 0}}, {{0, 0, 0, 0}, {0, 0, 0, 0}}}};
+    panel_products<T, 1>(A, ld, n, kb, k0, k0, k0, lane, c);
     const int li = lane & 15;
 #pragma unroll
     for (int jt = 0; jt < 2; ++jt)
@@ -418,7 +428,7 @@ __global__ void __launch_bounds__(64) k_pchol_diag(Tab tb, Ws ws, PArgs a, int k
         for (int v = 0; v < 4; ++v) {
           const int j = 16 * jt + Mma<T>::row(lane, v), r = 16 * rt + li;
           const int hi = min(max(r, j), wd - 1), lo = min(min(r, j), wd - 1);   // lower triangle, clamped
-          sC[r * PC + j] = (double)A[k0 + hi + (int64_t)(k0 + lo) * ld] - (double)c[jt][rt][v];
+          sC[r * PC + j] = (double)A[k0 + hi + (int64_t)(k0 + lo) * ld] - (double)c[0][jt][rt][v];
         }
   }
   wave_sync();
@@ -477,12 +487,14 @@ __global__ void __launch_bounds__(64) k_pchol_diag(Tab tb, Ws ws, PArgs a, int k
 // Strips below the diagonal block of the panel at column k0: grid = items x groups of four
 // strips (one per wave), the groups of one item on one XCD (block id mod 8) in consecutive
 // dispatch order so that its panel rows and inverse factor are shared through that XCD's L2.
-// Strips start at s0 (0 when the panel is narrower than 32 and its diagonal strip holds rows
-// below the block); only rows at or below k0 + wd are written.
-template <typename T>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
-k_pchol_strip(Tab tb, Ws ws, PArgs a, int k0, int s0, int groups) {
-  constexpr int NB = 32;
+// The strips are brought up to date with the columns [kb, k0) and solved.  Strips start at s0
+// (0 when the panel is narrower than 32 and its diagonal strip holds rows below the block); only
+// rows at or below k0 + wd are written.  LOOK: the same pass over the strip rows also applies
+// the columns [kb, k0) to the next panel's columns (k0 + 32..), which then need only this panel.
+template <typename T, int LOOK>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LOOK ? 3 : 4)))
+k_pchol_strip(Tab tb, Ws ws, PArgs a, int k0, int kb, int s0, int groups) {
+  constexpr int NB = 32, NP = LOOK ? 2 : 1;
   typedef typename Mma<T>::acc acc_t;
   const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
   const int item = (slot / groups) * 8 + xcd, g = slot % groups;
@@ -496,11 +508,31 @@ k_pchol_strip(Tab tb, Ws ws, PArgs a, int k0, int s0, int groups) {
   if (r0 >= n) return;
   T* A = (T*)a.base + mat * a.stride;
   int lane = opaque_lane();
-  acc_t c[2][2] = {{{0, 0, 0, 0}, {0, 0, 0, 0}}, {{0, 0, 0, 0}, {0, 0, 0, 0}}};
-  panel_products<T>(A, ld, n, k0, r0, lane, c);
-  // C^T = A^T - products (FP64), in place of the accumulators' layout; 0 right of the panel
+  acc_t c[NP][2][2];
+#pragma unroll
+  for (int q = 0; q < NP; ++q)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) c[q][h][0] = c[q][h][1] = acc_t{0, 0, 0, 0};
+  panel_products<T, NP>(A, ld, n, kb, k0, k0, r0, lane, c);
   lane = opaque_lane();
   const int li = lane & 15, lk = lane >> 4;
+  if (LOOK) {
+    // next panel (columns k1..): A -= products, rows at or below the diagonal
+    const int k1 = k0 + NB, wd1 = min(NB, a.m - k1);
+#pragma unroll
+    for (int jt = 0; jt < 2; ++jt)
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int j = 16 * jt + Mma<T>::row(lane, v), r = r0 + 16 * rt + li;
+          if (j < wd1 && r < n && r >= k1 + j) {
+            T* p = A + r + (int64_t)(k1 + j) * ld;
+            *p = (T)((double)*p - (double)c[NP - 1][jt][rt][v]);
+          }
+        }
+  }
+  // C^T = A^T - products (FP64), in the accumulators' layout; 0 right of the panel
   double ct[2][2][4];
 #pragma unroll
   for (int jt = 0; jt < 2; ++jt)
@@ -510,7 +542,7 @@ k_pchol_strip(Tab tb, Ws ws, PArgs a, int k0, int s0, int groups) {
       for (int v = 0; v < 4; ++v) {
         const int j = 16 * jt + Mma<T>::row(lane, v), r = min(r0 + 16 * rt + li, n - 1);
         const double av = (double)A[r + (int64_t)(k0 + min(j, wd - 1)) * ld];
-        ct[jt][rt][v] = j < wd ? av - (double)c[jt][rt][v] : 0.0;
+        ct[jt][rt][v] = j < wd ? av - (double)c[0][jt][rt][v] : 0.0;
       }
   // X^T = L^-1 C^T on matrix cores: K index j of step (jt, v) for lane group lk is
   // 16 jt + Mma<T>::row(lane, v), the layout the update products left C^T in; the inverse is
@@ -1128,19 +1160,26 @@ static void syrk(const Tab& tb, const Ws& ws, PArgs a, hipStream_t st) {
 }
 
 // Partial Cholesky of the first a.m columns of every matrix of the batch: two launches per panel
-// of 32 columns (the diagonal block, then the strips below it).
+// of 32 columns (the diagonal block, then the strips below it).  Panels go in pairs: the first
+// panel's strip pass also applies every earlier column to the second panel, so the second
+// panel's launches need only the first panel's columns and the strip rows are read once per pair.
 template <typename T>
 static void pchol(const Tab& tb, const Ws& ws, const PArgs& a, hipStream_t st) {
   if (a.count == 0) return;
-  for (int k0 = 0; k0 < a.m; k0 += 32) {
+  for (int p = 0, k0 = 0; k0 < a.m; ++p, k0 += 32) {
     const int wd = std::min(32, a.m - k0);
-    hipLaunchKernelGGL(k_pchol_diag<T>, dim3(a.count), dim3(64), 0, st, tb, ws, a, k0);
+    const int kb = (p & 1) ? k0 - 32 : 0;   // columns not yet applied to this panel
+    const bool look = !(p & 1) && k0 + 32 < a.m;
+    hipLaunchKernelGGL(k_pchol_diag<T>, dim3(a.count), dim3(64), 0, st, tb, ws, a, k0, kb);
     if (a.n <= k0 + wd) continue;   // no rows below the block
     const int s0 = wd < 32 ? 0 : 1;
     const int nstrip = (int)cl_ceil_div(a.n - k0, 32) - s0;
     const int groups = (int)cl_ceil_div(nstrip, 4);
     const unsigned grid = (unsigned)(cl_ceil_div(a.count, 8) * 8 * groups);
-    hipLaunchKernelGGL(k_pchol_strip<T>, dim3(grid), dim3(256), 0, st, tb, ws, a, k0, s0, groups);
+    if (look)
+      hipLaunchKernelGGL((k_pchol_strip<T, 1>), dim3(grid), dim3(256), 0, st, tb, ws, a, k0, kb, s0, groups);
+    else
+      hipLaunchKernelGGL((k_pchol_strip<T, 0>), dim3(grid), dim3(256), 0, st, tb, ws, a, k0, kb, s0, groups);
   }
 }
 
