@@ -737,13 +737,17 @@ __global__ void __launch_bounds__(256) k_sep_step(Shape S, Tab tb, Ws ws, int le
 // theta-theta partials of one 16-element chunk and one 64 x 64 lower tile of the parameter
 // block, in FP64 on matrix cores: sum of the elements' assembled theta blocks minus the products of
 // their transformed theta rows (elements: mI columns each; separators 1.. of the chunk: ns
-// columns each).  grid (chunk, tile, instance).
+// columns each).  grid (chunk-tile slots, instance): the tiles of one chunk go to one XCD (block id
+// mod 8) in consecutive dispatch order, so each theta row is read from HBM once and shared by the
+// chunk's tiles through that XCD's L2.
 template <typename T>
-__global__ void __launch_bounds__(256) k_big_theta(Shape S, Tab tb, Ws ws) {
+__global__ void __launch_bounds__(256) k_big_theta(Shape S, Tab tb, Ws ws, int ntile) {
   constexpr int TM = 64, KC = 32, NL = KC * TM / 256;
   __shared__ double sA[KC * TM];
   __shared__ double sB[KC * TM];
-  const int inst = blockIdx.z, chunk = blockIdx.x, tile = blockIdx.y;
+  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  const int inst = blockIdx.y, chunk = (slot / ntile) * 8 + xcd, tile = slot % ntile;
+  if (chunk >= ws.nchunk) return;
   if (block_flag(&ws.flag[inst])) return;
   const int np = S.np, ns = S.ns, b = S.b, mI = S.mI, N = tb.inst_N[inst];
   const BigGeom G = big_geom(S);
@@ -1220,7 +1224,8 @@ static int big_factor_t(const Shape& S, const Tab& tb, const HostPlan& hp, const
   if (cb) cb(ctx, 3, 1, st);
   const int nt = (int)cl_ceil_div(S.np, 64);
   if (nt > 0)
-    hipLaunchKernelGGL(k_big_theta<T>, dim3(ws.nchunk, nt * (nt + 1) / 2, tb.n_inst), dim3(256), 0, st, S, tb, ws);
+    hipLaunchKernelGGL(k_big_theta<T>, dim3((unsigned)(cl_ceil_div(ws.nchunk, 8) * 8 * (nt * (nt + 1) / 2)), tb.n_inst),
+                       dim3(256), 0, st, S, tb, ws, nt * (nt + 1) / 2);
   hipLaunchKernelGGL(k_border_build<T>, dim3(tb.n_inst), dim3(256), 0, st, S, tb, ws);
   if (S.np > 0)
     hipLaunchKernelGGL(k_border_theta, dim3((unsigned)cl_ceil_div(S.np * S.np, 256), tb.n_inst), dim3(256), 0, st,
