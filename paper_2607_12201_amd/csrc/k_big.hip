@@ -10,8 +10,8 @@
 //                              columns in 32-column panels: the diagonal block (one wave per
 //                              matrix), then the strips below it (one wave per 32 rows), updates
 //                              and solves as 16x16x4 matrix-core products
-//              k_pchol_syrk    trailing Schur complement (all rows below the interior block)
-//                              as matrix-core tiles, the tiles of one element on one XCD
+//              k_pchol_trail   trailing Schur complement (all rows below the interior block)
+//                              as 32 x 64 matrix-core blocks, the blocks of one element on one XCD
 //   chain      k_sep_init / k_sep_step gather each separator's local matrix; the same two
 //                              kernels eliminate the separators of every cyclic-reduction level
 //   border     k_big_theta     theta-theta Schur complement in FP64 on matrix cores, split over
@@ -37,9 +37,8 @@ struct PArgs {
   void* base;
   int64_t stride;   // elements between matrices
   int ld, n, m, count, mode, level;
-  int zero;         // syrk: the trailing block starts at zero (not read)
-  int skip0, skip1; // syrk: tiles inside [skip0, skip1)^2 are not computed
-  int ntile;        // syrk: lower tiles per item
+  int zero;         // trailing update: the trailing block starts at zero (not read)
+  int skip0, skip1; // trailing update: blocks inside [skip0, skip1)^2 are not computed
 };
 
 __device__ inline void pitem(const Tab& tb, const PArgs& a, int k, int64_t& mat, int& inst) {
@@ -338,8 +337,7 @@ __global__ void __launch_bounds__(1024) k_big_asm(Shape S, Tab tb, Ws ws) {
 // L[r0 + 16 rt + li][k], i = Mma<T>::row(lane, v): the (panel, strip) blocks of L L^T transposed.
 // Operands are loaded from memory straight into the product's register layout (32-bit byte
 // offsets from the matrix base, rows clamped to the matrix: rows past its end give products that
-// are never used), the next columns in flight while the current ones are multiplied.  ke - kb is
-// a multiple of 16.
+// are never used), the next columns in flight while the current ones are multiplied.
 template <typename T, int NP>
 __device__ inline void panel_products(const T* A, int ld, int n, int kb, int ke, int pr, int r0, int lane,
                                       typename Mma<T>::acc (&c)[NP][2][2]) {
@@ -379,13 +377,35 @@ __device__ inline void panel_products(const T* A, int ld, int n, int kb, int ke,
         c[q][1][1] = Mma<T>::mma(p[q][1][u], s1[u], c[q][1][1]);
       }
   };
-  if (ke <= kb) return;
-  load(kb, cp, cs0, cs1);
-  for (int kc = kb; kc < ke; kc += 8 * KU) {
-    load(kc + 4 * KU, np_, ns0, ns1);
-    mult(cp, cs0, cs1);
-    if (kc + 8 * KU < ke) load(kc + 8 * KU, cp, cs0, cs1);
-    mult(np_, ns0, ns1);
+  const int kfull = kb + (ke > kb ? (ke - kb) / (8 * KU) * (8 * KU) : 0);
+  if (kfull > kb) {
+    load(kb, cp, cs0, cs1);
+    for (int kc = kb; kc < kfull; kc += 8 * KU) {
+      load(kc + 4 * KU, np_, ns0, ns1);
+      mult(cp, cs0, cs1);
+      if (kc + 8 * KU < kfull) load(kc + 8 * KU, cp, cs0, cs1);
+      mult(np_, ns0, ns1);
+    }
+  }
+  // ragged end (the trailing update's K = m): columns at or past ke read as zero
+  for (int kc = kfull; kc < ke; kc += 4) {
+    const bool ok = kc + lk < ke;
+    const uint32_t off = (uint32_t)(ok ? kc : ke - 1 - lk) * cs;
+    T p[NP][2][1], s0[1], s1[1];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      p[q][0][0] = ok ? *(const T*)(base + (op[q][0] + off)) : (T)0;
+      p[q][1][0] = ok ? *(const T*)(base + (op[q][1] + off)) : (T)0;
+    }
+    s0[0] = ok ? *(const T*)(base + (os0 + off)) : (T)0;
+    s1[0] = ok ? *(const T*)(base + (os1 + off)) : (T)0;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      c[q][0][0] = Mma<T>::mma(p[q][0][0], s0[0], c[q][0][0]);
+      c[q][0][1] = Mma<T>::mma(p[q][0][0], s1[0], c[q][0][1]);
+      c[q][1][0] = Mma<T>::mma(p[q][1][0], s0[0], c[q][1][0]);
+      c[q][1][1] = Mma<T>::mma(p[q][1][0], s1[0], c[q][1][1]);
+    }
   }
 }
 
@@ -576,76 +596,72 @@ k_pchol_strip(Tab tb, Ws ws, PArgs a, int k0, int kb, int s0, int groups) {
 }
 
 // Trailing update C = C - X X^T (or -X X^T when the block starts at zero) of the rows and columns
-// [m, n), X = L[m:n, 0:m], lower 64 x 64 tiles.  Tiles of one matrix go to one XCD (block id mod 8)
-// in consecutive dispatch order, so the matrix's X rows are read from HBM into that XCD's L2 once
-// and shared by its tiles.  Tiles inside [skip0, skip1)^2 are not computed.
+// [m, n), X = L[m:n, 0:m], in blocks of 32 rows x 64 columns of the lower triangle, one per wave:
+// the strip products above with the block's columns in the place of the panel rows.  Blocks
+// inside [skip0, skip1)^2 are left out.  The blocks of one matrix go to one XCD (block id mod 8)
+// in consecutive dispatch order, so its X rows are read from HBM into that XCD's L2 once.
+__host__ __device__ inline bool trail_skipped(const PArgs& a, int s, int cb) {
+  const int r0 = a.m + 32 * s, c0 = a.m + 64 * cb;
+  return r0 >= a.skip0 && min(r0 + 32, a.n) <= a.skip1 && c0 >= a.skip0 && min(c0 + 64, a.n) <= a.skip1;
+}
+// Block bi of the enumeration (strips in order, then column blocks): s, cb; false past the end.
+__host__ __device__ inline bool trail_block(const PArgs& a, int bi, int& s, int& cb) {
+  const int t = a.n - a.m, nst = (t + 31) / 32, ncb = (t + 63) / 64;
+  int k = 0;
+  for (int ss = 0; ss < nst; ++ss) {
+    const int cmax = min(ncb - 1, (32 * ss + 31) / 64);
+    for (int cc = 0; cc <= cmax; ++cc) {
+      if (trail_skipped(a, ss, cc)) continue;
+      if (k == bi) {
+        s = ss;
+        cb = cc;
+        return true;
+      }
+      ++k;
+    }
+  }
+  return false;
+}
+
 template <typename T>
-__global__ void __launch_bounds__(256) k_pchol_syrk(Tab tb, Ws ws, PArgs a) {
-  constexpr int TM = 64, KC = 32, NL = KC * TM / 256;
-  __shared__ T sA[KC * TM];
-  __shared__ T sB[KC * TM];
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+k_pchol_trail(Tab tb, Ws ws, PArgs a, int groups) {
   typedef typename Mma<T>::acc acc_t;
   const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
-  const int item = (slot / a.ntile) * 8 + xcd, tile = slot % a.ntile;
+  const int item = (slot / groups) * 8 + xcd, g = slot % groups;
   if (item >= a.count) return;
+  int s, cb;
+  if (!trail_block(a, 4 * g + (int)(threadIdx.x >> 6), s, cb)) return;
   int64_t mat;
   int inst;
   pitem(tb, a, item, mat, inst);
   if (block_flag(&ws.flag[inst])) return;
-  int ti = (int)((sqrtf(8.0f * (float)tile + 1.0f) - 1.0f) * 0.5f);
-  while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
-  while (ti * (ti + 1) / 2 > tile) --ti;
-  const int tj = tile - ti * (ti + 1) / 2;
-  const int n = a.n, m = a.m, ld = a.ld;
-  const int R0 = m + TM * ti, C0 = m + TM * tj;
-  if (R0 >= a.skip0 && R0 + TM <= a.skip1 && C0 >= a.skip0 && C0 + TM <= a.skip1) return;
+  const int n = a.n, ld = a.ld, r0 = a.m + 32 * s, c0 = a.m + 64 * cb;
   T* A = (T*)a.base + mat * a.stride;
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6, wr = w >> 1, wc = w & 1;
-  acc_t c00 = {0, 0, 0, 0}, c01 = {0, 0, 0, 0}, c10 = {0, 0, 0, 0}, c11 = {0, 0, 0, 0};
-  T ra[NL], rb[NL];
-  auto load = [&](int kc) {
+  int lane = opaque_lane();
+  acc_t c[2][2][2];
 #pragma unroll
-    for (int q = 0; q < NL; ++q) {
-      const int ii = t & (TM - 1), kk = (t >> 6) + 4 * q, k = kc + kk;
-      const int r = R0 + ii, c = C0 + ii;
-      ra[q] = (r < n && k < m) ? A[r + (int64_t)k * ld] : (T)0;
-      rb[q] = (c < n && k < m) ? A[c + (int64_t)k * ld] : (T)0;
-    }
-  };
-  load(0);
-  for (int kc = 0; kc < m; kc += KC) {
-    __syncthreads();
+  for (int q = 0; q < 2; ++q)
 #pragma unroll
-    for (int q = 0; q < NL; ++q) {
-      sA[((t >> 6) + 4 * q) * TM + (t & (TM - 1))] = ra[q];
-      sB[((t >> 6) + 4 * q) * TM + (t & (TM - 1))] = rb[q];
-    }
-    __syncthreads();
-    if (kc + KC < m) load(kc + KC);
+    for (int h = 0; h < 2; ++h) c[q][h][0] = c[q][h][1] = acc_t{0, 0, 0, 0};
+  panel_products<T, 2>(A, ld, n, 0, a.m, c0, r0, lane, c);
+  lane = opaque_lane();
+  const int li = lane & 15;
+  // element v of c[q][jt][rt]: column c0 + 32 q + 16 jt + row(lane, v), row r0 + 16 rt + li
 #pragma unroll
-    for (int s = 0; s < KC / 4; ++s) {
-      const int kk = 4 * s + (lane >> 4), li = lane & 15;
-      const T a0 = sA[kk * TM + 32 * wr + li], a1 = sA[kk * TM + 32 * wr + 16 + li];
-      const T b0 = sB[kk * TM + 32 * wc + li], b1 = sB[kk * TM + 32 * wc + 16 + li];
-      c00 = Mma<T>::mma(a0, b0, c00);
-      c01 = Mma<T>::mma(a0, b1, c01);
-      c10 = Mma<T>::mma(a1, b0, c10);
-      c11 = Mma<T>::mma(a1, b1, c11);
-    }
-  }
+  for (int q = 0; q < 2; ++q)
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int rb0 = R0 + 32 * wr + Mma<T>::row(lane, v), cb = C0 + 32 * wc + (lane & 15);
-    const T vals[4] = {c00[v], c01[v], c10[v], c11[v]};
+    for (int jt = 0; jt < 2; ++jt)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int r = rb0 + 16 * (q >> 1), c = cb + 16 * (q & 1);
-      if (r < n && c < n && r >= c) {
-        T* p = A + r + (int64_t)c * ld;
-        *p = a.zero ? -vals[q] : *p - vals[q];
-      }
-    }
-  }
+      for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int col = c0 + 32 * q + 16 * jt + Mma<T>::row(lane, v), row = r0 + 16 * rt + li;
+          if (row < n && row >= col) {
+            T* p = A + row + (int64_t)col * ld;
+            *p = a.zero ? -c[q][jt][rt][v] : *p - c[q][jt][rt][v];
+          }
+        }
 }
 
 // ---------------------------------------------------------------- cyclic reduction gathers
@@ -1151,16 +1167,18 @@ static PArgs pargs(void* base, int64_t stride, int ld, int n, int m, int count, 
   a.level = level;
   a.zero = 0;
   a.skip0 = a.skip1 = 0;
-  const int nt = (int)cl_ceil_div(n - m, 64);
-  a.ntile = nt * (nt + 1) / 2;
   return a;
 }
 
 template <typename T>
-static void syrk(const Tab& tb, const Ws& ws, PArgs a, hipStream_t st) {
-  if (a.count == 0 || a.ntile == 0) return;
-  const unsigned grid = (unsigned)(cl_ceil_div(a.count, 8) * 8 * a.ntile);
-  hipLaunchKernelGGL(k_pchol_syrk<T>, dim3(grid), dim3(256), 0, st, tb, ws, a);
+static void trail(const Tab& tb, const Ws& ws, const PArgs& a, hipStream_t st) {
+  if (a.count == 0 || a.n <= a.m) return;
+  int nblk = 0, s, cb;
+  while (trail_block(a, nblk, s, cb)) ++nblk;
+  if (nblk == 0) return;
+  const int groups = (int)cl_ceil_div(nblk, 4);
+  const unsigned grid = (unsigned)(cl_ceil_div(a.count, 8) * 8 * groups);
+  hipLaunchKernelGGL(k_pchol_trail<T>, dim3(grid), dim3(256), 0, st, tb, ws, a, groups);
 }
 
 // Partial Cholesky of the first a.m columns of every matrix of the batch: two launches per panel
@@ -1201,10 +1219,10 @@ static int big_factor_t(const Shape& S, const Tab& tb, const HostPlan& hp, const
   pchol<T>(tb, ws, ea, st);
   if (cb) cb(ctx, COLLOC_PH_LEVEL0, 0, st);
   if (cb) cb(ctx, COLLOC_PH_SCHUR, 1, st);
-  // the theta-theta block is formed by k_big_theta; its tiles here are skipped
+  // the theta-theta block is formed by k_big_theta; its blocks here are skipped
   ea.skip0 = S.b;
   ea.skip1 = S.b + S.np;
-  syrk<T>(tb, ws, ea, st);
+  trail<T>(tb, ws, ea, st);
   if (cb) cb(ctx, COLLOC_PH_SCHUR, 0, st);
   if (cb) cb(ctx, 2, 1, st);
   hipLaunchKernelGGL(k_sep_init<T>, dim3(E), dim3(256), 0, st, S, tb, ws);
@@ -1218,7 +1236,7 @@ static int big_factor_t(const Shape& S, const Tab& tb, const HostPlan& hp, const
     ca.zero = 1;
     ca.skip0 = 3 * S.ns;
     ca.skip1 = G.Lr;
-    syrk<T>(tb, ws, ca, st);
+    trail<T>(tb, ws, ca, st);
   }
   if (cb) cb(ctx, 2, 0, st);
   if (cb) cb(ctx, 3, 1, st);
