@@ -678,10 +678,87 @@ __device__ inline T elem_at(const Ws& ws, const BigGeom& G, int64_t e, int r, in
   return ((const T*)ws.ebuf)[e * (int64_t)G.Rp * G.Rp + r + (int64_t)c * G.Rp];
 }
 
+// One band of 32 rows of a destination block (rows x cols, column-major, ld ldd) filled in 32 x 32
+// tiles: v = (add ? dst : 0) + s1 + s2, summed in that order, lower triangle only if `lower`.  A
+// source is read straight (src[r + c ld]) or transposed (src[c + r ld]); a transposed one is
+// staged through LDS, so every read and write is coalesced.  Absent sources (p == nullptr) add
+// nothing.
+struct GSrc {
+  const void* p;
+  int ld, tr;
+};
+template <typename T>
+__device__ inline double gsrc(const GSrc& g, int r, int c) {
+  const T* q = (const T*)g.p;
+  return g.tr ? (double)q[c + (int64_t)r * g.ld] : (double)q[r + (int64_t)c * g.ld];
+}
+template <typename T>
+__device__ void gather_band(T* dst, int ldd, int rows, int cols, int r0, bool add, bool lower, GSrc s1,
+                            GSrc s2, double* tiles) {
+  // four groups of 256 threads take four column tiles at a time
+  const int t = threadIdx.x & 255, grp = threadIdx.x >> 8;
+  double* tile = tiles + grp * 32 * 33;
+  const bool tr = (s1.p && s1.tr) || (s2.p && s2.tr);
+  for (int cg = 0; cg < cols; cg += 128) {
+    const int c0 = cg + 32 * grp;
+    const bool act = c0 < cols && !(lower && c0 > r0 + 31);
+    double v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int idx = t + 256 * k, r = r0 + (idx & 31), c = c0 + (idx >> 5);
+      double x = 0.0;
+      if (act && r < rows && c < cols) {
+        if (add) x = (double)dst[r + (int64_t)c * ldd];
+        if (s1.p && !s1.tr) x += gsrc<T>(s1, r, c);
+        if (s2.p && !s2.tr) x += gsrc<T>(s2, r, c);
+      }
+      v[k] = x;
+    }
+    if (tr) {
+      __syncthreads();   // the previous tiles' reads are done
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int idx = t + 256 * k, c = c0 + (idx & 31), rr = idx >> 5, r = r0 + rr;
+        double x = 0.0;
+        if (act && r < rows && c < cols) {
+          if (s1.p && s1.tr) x += gsrc<T>(s1, r, c);
+          if (s2.p && s2.tr) x += gsrc<T>(s2, r, c);
+        }
+        tile[rr * 33 + (idx & 31)] = x;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int idx = t + 256 * k;
+        v[k] += tile[(idx & 31) * 33 + (idx >> 5)];
+      }
+    }
+    if (act) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int idx = t + 256 * k, r = r0 + (idx & 31), c = c0 + (idx >> 5);
+        if (r < rows && c < cols && (!lower || r >= c)) dst[r + (int64_t)c * ldd] = (T)v[k];
+      }
+    }
+  }
+}
+
+// Bands of a separator's gathers: T (ns rows), E_L (ns), E_R (ns), G (np), 32 rows each.
+__host__ __device__ inline int gather_bands(const Shape& S) {
+  return 3 * (int)cl_ceil_div(S.ns, 32) + (int)cl_ceil_div(S.np, 32);
+}
+__device__ inline void gather_op(const Shape& S, int band, int& op, int& r0) {
+  const int bs = (int)cl_ceil_div(S.ns, 32);
+  op = band < 3 * bs ? band / bs : 3;
+  r0 = 32 * (op < 3 ? band - op * bs : band - 3 * bs);
+}
+
 // After level 0: every separator's T_s and G_s from the Schur complements of element s (its S
 // block) and element s + 1 (its P block); the couplings of the separators eliminated at level 1.
+// grid (element, band).
 template <typename T>
-__global__ void __launch_bounds__(256) k_sep_init(Shape S, Tab tb, Ws ws) {
+__global__ void __launch_bounds__(1024) k_sep_init(Shape S, Tab tb, Ws ws) {
+  __shared__ double tile[4 * 32 * 33];
   const int64_t es = blockIdx.x;
   const int inst = tb.elem_inst[es], s = tb.elem_loc[es];
   if (block_flag(&ws.flag[inst])) return;
@@ -689,32 +766,33 @@ __global__ void __launch_bounds__(256) k_sep_init(Shape S, Tab tb, Ws ws) {
   const BigGeom G = big_geom(S);
   const bool nxt = s + 1 < N, elim1 = (s & 1) != 0;
   const int P0 = b + np;   // first P row of an element
-  for (int idx = tid(); idx < ns * ns; idx += nthr()) {
-    const int q = idx / ns, a = idx - q * ns;   // column q, row a
-    if (a >= q) {
-      double v = (double)elem_at<T>(ws, G, es, mI + a, mI + q);
-      if (nxt) v += (double)elem_at<T>(ws, G, es + 1, P0 + a, P0 + q);
-      sep_at<T>(ws, G, es, a, q) = (T)v;
-    }
-    if (elim1) {
-      sep_at<T>(ws, G, es, ns + a, q) = elem_at<T>(ws, G, es, P0 + a, mI + q);
-      sep_at<T>(ws, G, es, 2 * ns + a, q) = nxt ? elem_at<T>(ws, G, es + 1, P0 + q, mI + a) : (T)0;
-    }
-  }
-  for (int idx = tid(); idx < np * ns; idx += nthr()) {
-    const int q = idx / np, c = idx - q * np;
-    double v = (double)elem_at<T>(ws, G, es, b + c, mI + q);
-    if (nxt) v += (double)elem_at<T>(ws, G, es + 1, P0 + q, b + c);
-    sep_at<T>(ws, G, es, 3 * ns + c, q) = (T)v;
-  }
+  int op, r0;
+  gather_op(S, blockIdx.y, op, r0);
+  if ((op == 1 || op == 2) && !elim1) return;
+  const T* e = (const T*)ws.ebuf + es * (int64_t)G.Rp * G.Rp;
+  const T* en = e + (int64_t)G.Rp * G.Rp;   // element s + 1 (read only when it exists)
+  T* d = &sep_at<T>(ws, G, es, 0, 0);
+  const GSrc none = {nullptr, 0, 0};
+  if (op == 0)   // T_s = S block of element s + P block of element s + 1
+    gather_band<T>(d, G.Lp, ns, ns, r0, false, true, GSrc{e + mI + (int64_t)mI * G.Rp, G.Rp, 0},
+                   nxt ? GSrc{en + P0 + (int64_t)P0 * G.Rp, G.Rp, 0} : none, tile);
+  else if (op == 1)   // E_L(a, q) = K(P_a of element s, S_q)
+    gather_band<T>(d + ns, G.Lp, ns, ns, r0, false, false, GSrc{e + P0 + (int64_t)mI * G.Rp, G.Rp, 0}, none, tile);
+  else if (op == 2)   // E_R(a, q) = K(P_q of element s + 1, S_a of element s + 1)
+    gather_band<T>(d + 2 * ns, G.Lp, ns, ns, r0, false, false,
+                   nxt ? GSrc{en + P0 + (int64_t)mI * G.Rp, G.Rp, 1} : none, none, tile);
+  else   // G_s(c, q) = K(theta_c, S_q) of element s + K(P_q, theta_c) of element s + 1
+    gather_band<T>(d + 3 * ns, G.Lp, np, ns, r0, false, false, GSrc{e + b + (int64_t)mI * G.Rp, G.Rp, 0},
+                   nxt ? GSrc{en + P0 + (int64_t)b * G.Rp, G.Rp, 1} : none, tile);
 }
 
 // Step l (1..L-1): separators t that are multiples of 2^l add the contributions of the
 // separators eliminated at level l on either side (u1 = t - 2^(l-1): t is its right neighbour;
 // u2 = t + 2^(l-1): t is its left neighbour), in that order; those eliminated at level l+1 also
-// take their new couplings.
+// take their new couplings.  grid (separator, band).
 template <typename T>
-__global__ void __launch_bounds__(256) k_sep_step(Shape S, Tab tb, Ws ws, int level) {
+__global__ void __launch_bounds__(1024) k_sep_step(Shape S, Tab tb, Ws ws, int level) {
+  __shared__ double tile[4 * 32 * 33];
   const int it = tb.st_ptr[level - 1] + blockIdx.x;
   if (it >= tb.st_ptr[level]) return;
   const int inst = tb.st_inst[it], t = tb.st_s[it];
@@ -727,26 +805,27 @@ __global__ void __launch_bounds__(256) k_sep_step(Shape S, Tab tb, Ws ws, int le
   const int64_t u1 = e0 + t - half, u2 = e0 + t + half;
   const bool elim = ((t >> level) & 1) != 0;
   const bool right = elim && h2 && t + 2 * half < N;
-  for (int idx = tid(); idx < ns * ns; idx += nthr()) {
-    const int q = idx / ns, a = idx - q * ns;
-    if (a >= q) {
-      double v = (double)sep_at<T>(ws, G, et, a, q);
-      if (h1) v += (double)sep_at<T>(ws, G, u1, 2 * ns + a, 2 * ns + q);
-      if (h2) v += (double)sep_at<T>(ws, G, u2, ns + a, ns + q);
-      sep_at<T>(ws, G, et, a, q) = (T)v;
-    }
-    if (elim) {
-      sep_at<T>(ws, G, et, ns + a, q) = sep_at<T>(ws, G, u1, 2 * ns + q, ns + a);
-      sep_at<T>(ws, G, et, 2 * ns + a, q) = right ? sep_at<T>(ws, G, u2, 2 * ns + a, ns + q) : (T)0;
-    }
-  }
-  for (int idx = tid(); idx < np * ns; idx += nthr()) {
-    const int q = idx / np, c = idx - q * np;
-    double v = (double)sep_at<T>(ws, G, et, 3 * ns + c, q);
-    if (h1) v += (double)sep_at<T>(ws, G, u1, 3 * ns + c, 2 * ns + q);
-    if (h2) v += (double)sep_at<T>(ws, G, u2, 3 * ns + c, ns + q);
-    sep_at<T>(ws, G, et, 3 * ns + c, q) = (T)v;
-  }
+  int op, r0;
+  gather_op(S, blockIdx.y, op, r0);
+  if ((op == 1 || op == 2) && !elim) return;
+  T* d = &sep_at<T>(ws, G, et, 0, 0);
+  const T* a1 = h1 ? &sep_at<T>(ws, G, u1, 0, 0) : nullptr;
+  const T* a2 = h2 ? &sep_at<T>(ws, G, u2, 0, 0) : nullptr;
+  const GSrc none = {nullptr, 0, 0};
+  if (op == 0)   // T_t += C_RR of u1 + C_LL of u2
+    gather_band<T>(d, G.Lp, ns, ns, r0, true, true,
+                   h1 ? GSrc{a1 + 2 * ns + (int64_t)2 * ns * G.Lp, G.Lp, 0} : none,
+                   h2 ? GSrc{a2 + ns + (int64_t)ns * G.Lp, G.Lp, 0} : none, tile);
+  else if (op == 1)   // E_L(a, q) = C_RL of u1 at (q, a)
+    gather_band<T>(d + ns, G.Lp, ns, ns, r0, false, false, GSrc{a1 + 2 * ns + (int64_t)ns * G.Lp, G.Lp, 1},
+                   none, tile);
+  else if (op == 2)   // E_R(a, q) = C_RL of u2 at (a, q) when t + 2^l is a separator
+    gather_band<T>(d + 2 * ns, G.Lp, ns, ns, r0, false, false,
+                   right ? GSrc{a2 + 2 * ns + (int64_t)ns * G.Lp, G.Lp, 0} : none, none, tile);
+  else   // G_t += C_thR of u1 + C_thL of u2
+    gather_band<T>(d + 3 * ns, G.Lp, np, ns, r0, true, false,
+                   h1 ? GSrc{a1 + 3 * ns + (int64_t)2 * ns * G.Lp, G.Lp, 0} : none,
+                   h2 ? GSrc{a2 + 3 * ns + (int64_t)ns * G.Lp, G.Lp, 0} : none, tile);
 }
 
 // ---------------------------------------------------------------- border
@@ -1182,16 +1261,22 @@ static void trail(const Tab& tb, const Ws& ws, const PArgs& a, hipStream_t st) {
 }
 
 // Partial Cholesky of the first a.m columns of every matrix of the batch: two launches per panel
-// of 32 columns (the diagonal block, then the strips below it).  Panels go in pairs: the first
-// panel's strip pass also applies every earlier column to the second panel, so the second
-// panel's launches need only the first panel's columns and the strip rows are read once per pair.
+// of 32 columns (the diagonal block, then the strips below it).  Panels go in pairs: from column
+// kLookMin on, the first panel's strip pass also applies every earlier column to the second
+// panel, so the second panel's launches need only the first panel's columns and the strip rows
+// are read once per pair.  (Before that, the extra read and write of the second panel's columns
+// costs more than the earlier columns it saves reading.)
+constexpr int kLookMin = 128;
 template <typename T>
 static void pchol(const Tab& tb, const Ws& ws, const PArgs& a, hipStream_t st) {
   if (a.count == 0) return;
   for (int p = 0, k0 = 0; k0 < a.m; ++p, k0 += 32) {
     const int wd = std::min(32, a.m - k0);
-    const int kb = (p & 1) ? k0 - 32 : 0;   // columns not yet applied to this panel
-    const bool look = !(p & 1) && k0 + 32 < a.m;
+    // columns not yet applied to this panel: all earlier ones, or only the previous panel's
+    // when that panel's pass looked ahead
+    const bool prev_look = (p & 1) && k0 - 32 >= kLookMin;
+    const int kb = prev_look ? k0 - 32 : 0;
+    const bool look = !(p & 1) && k0 >= kLookMin && k0 + 32 < a.m;
     hipLaunchKernelGGL(k_pchol_diag<T>, dim3(a.count), dim3(64), 0, st, tb, ws, a, k0, kb);
     if (a.n <= k0 + wd) continue;   // no rows below the block
     const int s0 = wd < 32 ? 0 : 1;
@@ -1225,10 +1310,10 @@ static int big_factor_t(const Shape& S, const Tab& tb, const HostPlan& hp, const
   trail<T>(tb, ws, ea, st);
   if (cb) cb(ctx, COLLOC_PH_SCHUR, 0, st);
   if (cb) cb(ctx, 2, 1, st);
-  hipLaunchKernelGGL(k_sep_init<T>, dim3(E), dim3(256), 0, st, S, tb, ws);
+  hipLaunchKernelGGL(k_sep_init<T>, dim3(E, gather_bands(S)), dim3(1024), 0, st, S, tb, ws);
   for (int l = 1; l <= tb.L; ++l) {
     if (l > 1 && hp.st[l - 1] > 0)
-      hipLaunchKernelGGL(k_sep_step<T>, dim3(hp.st[l - 1]), dim3(256), 0, st, S, tb, ws, l - 1);
+      hipLaunchKernelGGL(k_sep_step<T>, dim3(hp.st[l - 1], gather_bands(S)), dim3(1024), 0, st, S, tb, ws, l - 1);
     const int cnt = hp.lvl[l];
     if (cnt == 0) continue;
     PArgs ca = pargs(ws.sbuf, ssz, G.Lp, G.Lr, S.ns, cnt, 1, l);
