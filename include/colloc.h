@@ -111,7 +111,8 @@ typedef struct colloc_ipm_opts {
   int32_t precision;           /* COLLOC_FP64 or COLLOC_FP32_IR */
   int32_t ir_max;              /* refinement sweeps in FP32_IR mode (default 10) */
   int32_t pad_;
-  double ir_tol;               /* relative correction target of the refinement (1e-14) */
+  double ir_tol;               /* normwise backward-error target of the refinement (1e-14), see
+                                  kkt_solve */
 } colloc_ipm_opts;
 
 #define COLLOC_MAX_LS 48
@@ -220,11 +221,16 @@ int kkt_factor(const colloc_problem* p, void* ws_dev, int32_t precision, int32_t
 /* a5 -- solve K dx = rhs with the factor (forward through the elimination levels, parameter
  * block, back substitution).  With ir_max > 0, up to ir_max refinement sweeps follow: the
  * residual r = rhs - K dx is formed matrix-free in FP64 from the derivative values, Ds, Sx and
- * dw of the last assembly (kkt_matvec), the correction solves with the same factor, and an
- * instance stops once its correction satisfies |d|_inf <= ir_tol |dx|_inf.
+ * dw of the last assembly (kkt_matvec), the correction d solves with the same factor and
+ * dx += d.  An instance converges once the dx its residual was taken at has normwise backward
+ * error ||r||_inf <= ir_tol (||K||_inf ||dx||_inf + ||rhs||_inf), ||K||_inf bounded above by the
+ * largest row sum of |J|^T Ds |J| + |W| + the diagonal terms (formed once per call); it fails
+ * when ir_max sweeps are spent or a correction is more than half the previous one (the factor
+ * no longer contracts the error).
  * ir_sweeps[n_inst] (device, may be NULL): the sweeps taken by a converged instance, minus the
- * sweeps taken when ir_max was reached without convergence, 0 without refinement or where the
- * factor failed.  Refinement is what makes COLLOC_FP32_IR factors reach FP64 accuracy. */
+ * sweeps taken by a failed one, 0 without refinement or where the factor failed.  Refinement is
+ * what makes COLLOC_FP32_IR factors reach FP64 accuracy; in ipm_step a failed refinement makes
+ * the instance re-factor in FP64 (counted in ir_fallbacks). */
 int kkt_solve(const colloc_problem* p, void* ws_dev, int32_t precision, const double* rhs_dev,
               double* dx_dev, int32_t ir_max, double ir_tol, int32_t* ir_sweeps_dev,
               hipStream_t stream);

@@ -123,7 +123,9 @@ struct Ws {
   int* runskip;               // [n_inst] 1 = instance not iterating this step
   int* fbflag;                // [n_inst] FP64 fallback mask (0 = re-factor in FP64)
   int* fbneed;                // [n_inst] 1 = the instance re-factors in FP64 this step
-  double* irpart;             // [n_elem][2] refinement partial maxima |d|, |dx|
+  double* irpart;             // [n_elem][6] refinement partial maxima (|d|, |dx| after, |r|, |rhs|,
+                              // |dx| before, row-sum bound of |K|)
+  double* irnorm;             // [n_inst][2] refinement: row-sum bound of |K|, previous |d|
   // tiled path (Shape::big)
   void* ebuf;                 // [n_elem][Rp x Rp] element matrices / factors
   void* sbuf;                 // [n_elem][Lp x Lp] separator local matrices / factors

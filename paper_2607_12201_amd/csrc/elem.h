@@ -74,18 +74,23 @@ __device__ inline void residual_rows(const Shape& S, const Tab& tb, int inst, in
 
 // (J v) for the b rows of element i.  v: element's z (LDS, b), vprevK: node-K values of the
 // previous element (ns) or unused for i == 0, vth: theta part (np), jac: element's values.
+template <bool AB = false>
 __device__ inline void jv_rows(const Shape& S, const Tab& tb, int inst, int i, double h,
                                const double* jac, const double* v, const double* vprevK,
                                const double* vth, double* out) {
+  // AB: every coefficient taken in absolute value and every term added (v >= 0 expected), an
+  // upper bound of |J| v
   const int ns = S.ns, nr = S.nr;
+  auto ab = [](double x) { return AB ? fabs(x) : x; };
   for (int t = tid(); t < S.b; t += nthr()) {
     int j = t / ns, s = t - j * ns;
     double acc;
     if (j == 0) {
-      acc = v[s] - (i == 0 ? 0.0 : vprevK[s]);
+      const double pv = i == 0 ? 0.0 : vprevK[s];
+      acc = AB ? v[s] + pv : v[s] - pv;
     } else {
       acc = 0.0;
-      for (int jj = 0; jj <= S.K; ++jj) acc += S.a[jj][j] * v[jj * ns + s];
+      for (int jj = 0; jj <= S.K; ++jj) acc += ab(S.a[jj][j]) * v[jj * ns + s];
       double f = 0.0;
       int p0 = tb.sp_ptr[inst * (ns + 1) + s], p1 = tb.sp_ptr[inst * (ns + 1) + s + 1];
       for (int q = p0; q < p1; ++q) {
@@ -94,18 +99,19 @@ __device__ inline void jv_rows(const Shape& S, const Tab& tb, int inst, int i, d
         int q0 = tb.react[(inst * nr + r) * 2], q1 = tb.react[(inst * nr + r) * 2 + 1];
         int c = tb.param[inst * nr + r];
         double dr = 0.0;
-        if (q0 >= 0) dr += jr[0] * v[j * ns + q0];
-        if (q1 >= 0) dr += jr[1] * v[j * ns + q1];
-        if (c >= 0) dr += jr[2] * vth[c];
-        f += tb.sp_nu[q] * dr;
+        if (q0 >= 0) dr += ab(jr[0]) * v[j * ns + q0];
+        if (q1 >= 0) dr += ab(jr[1]) * v[j * ns + q1];
+        if (c >= 0) dr += ab(jr[2]) * vth[c];
+        f += ab(tb.sp_nu[q]) * dr;
       }
-      acc -= h * f;
+      acc = AB ? acc + fabs(h) * f : acc - h * f;
     }
     out[t] = acc;
   }
 }
 
 // phi[k-1][r] = sum_s nu_sr u[k][s]: reaction-space projection of row weights (LDS).
+template <bool AB = false>
 __device__ inline void reaction_weights(const Shape& S, const Tab& tb, int inst, const double* u,
                                         double* phi) {
   const int nr = S.nr, ns = S.ns;
@@ -114,7 +120,8 @@ __device__ inline void reaction_weights(const Shape& S, const Tab& tb, int inst,
     double acc = 0.0;
     for (int q = 0; q < 4; ++q) {
       int sp = tb.rx_sp[(inst * nr + r) * 4 + q];
-      if (sp >= 0) acc += tb.rx_nu[(inst * nr + r) * 4 + q] * u[k * ns + sp];
+      const double nu = tb.rx_nu[(inst * nr + r) * 4 + q];
+      if (sp >= 0) acc += (AB ? fabs(nu) : nu) * u[k * ns + sp];
     }
     phi[t] = acc;
   }
@@ -123,24 +130,26 @@ __device__ inline void reaction_weights(const Shape& S, const Tab& tb, int inst,
 // (J^T u) restricted to element i's z variables (b outputs) given the element's row weights
 // u (b), the next element's node-0 row weights unext0 (ns; nullptr for the last element), and
 // phi from reaction_weights.  Theta contributions are returned per parameter (np partials).
+template <bool AB = false>
 __device__ inline void jtu_rows(const Shape& S, const Tab& tb, int inst, double h,
                                 const double* jac, const double* u, const double* unext0,
                                 const double* phi, double* outz, double* outth) {
   const int ns = S.ns, nr = S.nr, K = S.K;
+  auto ab = [](double x) { return AB ? fabs(x) : x; };
   for (int t = tid(); t < S.b; t += nthr()) {
     int j = t / ns, s = t - j * ns;
     double acc = (j == 0) ? u[s] : 0.0;
-    for (int k = 1; k <= K; ++k) acc += S.a[j][k] * u[k * ns + s];
+    for (int k = 1; k <= K; ++k) acc += ab(S.a[j][k]) * u[k * ns + s];
     if (j >= 1) {   // reactant slots of species s (a 2A reaction lists both slots)
       double f = 0.0;
       const int o0 = tb.rq_ptr[inst * (ns + 1) + s], o1 = tb.rq_ptr[inst * (ns + 1) + s + 1];
       for (int o = o0; o < o1; ++o) {
         const int r = tb.rq_r[o];
-        f += jac[((j - 1) * nr + r) * 3 + tb.rq_t[o]] * phi[(j - 1) * nr + r];
+        f += ab(jac[((j - 1) * nr + r) * 3 + tb.rq_t[o]]) * phi[(j - 1) * nr + r];
       }
-      acc -= h * f;
+      acc = AB ? acc + fabs(h) * f : acc - h * f;
     }
-    if (j == K && unext0) acc -= unext0[s];
+    if (j == K && unext0) acc = AB ? acc + unext0[s] : acc - unext0[s];
     outz[t] = acc;
   }
   if (outth) {
@@ -150,19 +159,21 @@ __device__ inline void jtu_rows(const Shape& S, const Tab& tb, int inst, double 
       for (int k = 1; k <= K; ++k)
         for (int o = o0; o < o1; ++o) {
           const int r = tb.pc_r[o];
-          acc += jac[((k - 1) * nr + r) * 3 + 2] * phi[(k - 1) * nr + r];
+          acc += ab(jac[((k - 1) * nr + r) * 3 + 2]) * phi[(k - 1) * nr + r];
         }
-      outth[c] = -h * acc;
+      outth[c] = AB ? fabs(h) * acc : -h * acc;
     }
   }
 }
 
 // (W v) for element i: z outputs (b) and theta partials (np).  W = sum of the reaction
 // second-derivative patterns (hess values) plus the measurement Hessian of the element.
+template <bool AB = false>
 __device__ inline void wv_rows(const Shape& S, const Tab& tb, int inst, int64_t e,
                                const double* hess, const double* v, const double* vth,
                                double* outz, double* outth) {
   const int ns = S.ns, nr = S.nr, K = S.K;
+  auto ab = [](double x) { return AB ? fabs(x) : x; };
   for (int t = tid(); t < S.b; t += nthr()) {
     int j = t / ns, s = t - j * ns;
     double acc = 0.0;
@@ -173,8 +184,8 @@ __device__ inline void wv_rows(const Shape& S, const Tab& tb, int inst, int64_t 
         const int other = tb.react[(inst * nr + r) * 2 + (1 - sl)];
         const int c = tb.param[inst * nr + r];
         const double* H = hess + ((j - 1) * nr + r) * 4;
-        if (other >= 0) acc += H[0] * v[j * ns + other];
-        if (c >= 0) acc += H[1 + sl] * vth[c];
+        if (other >= 0) acc += ab(H[0]) * v[j * ns + other];
+        if (c >= 0) acc += ab(H[1 + sl]) * vth[c];
       }
     }
     int m0 = tb.elem_mptr[e], m1 = tb.elem_mptr[e + 1];
@@ -182,8 +193,8 @@ __device__ inline void wv_rows(const Shape& S, const Tab& tb, int inst, int64_t 
       if (tb.meas_sp[m] != s) continue;
       const double* w = tb.meas_w + (int64_t)m * (K + 1);
       double dot = 0.0;
-      for (int jj = 0; jj <= K; ++jj) dot += w[jj] * v[jj * ns + s];
-      acc += w[j] * dot;
+      for (int jj = 0; jj <= K; ++jj) dot += ab(w[jj]) * v[jj * ns + s];
+      acc += ab(w[j]) * dot;
     }
     outz[t] = acc;
   }
@@ -196,9 +207,9 @@ __device__ inline void wv_rows(const Shape& S, const Tab& tb, int inst, int64_t 
           const int r = tb.pc_r[o];
           int q0 = tb.react[(inst * nr + r) * 2], q1 = tb.react[(inst * nr + r) * 2 + 1];
           const double* H = hess + ((k - 1) * nr + r) * 4;
-          if (q0 >= 0) acc += H[1] * v[k * ns + q0];
-          if (q1 >= 0) acc += H[2] * v[k * ns + q1];
-          acc += H[3] * vth[c];
+          if (q0 >= 0) acc += ab(H[1]) * v[k * ns + q0];
+          if (q1 >= 0) acc += ab(H[2]) * v[k * ns + q1];
+          acc += ab(H[3]) * vth[c];
         }
       outth[c] = acc;
     }

@@ -630,7 +630,8 @@ static Ws ws_layout(const colloc_problem* p, int prec, void* base, size_t* bytes
   w.runskip = c.take<int>(I);
   w.fbflag = c.take<int>(I);
   w.fbneed = c.take<int>(I);
-  w.irpart = c.take<double>(E * 2);
+  w.irpart = c.take<double>(E * 6);
+  w.irnorm = c.take<double>(I * 2);
   w.rthp = c.take<double>(E * S.np);
   w.dcont = c.take<double>(E * S.ns);
   const bool big = S.big != 0;
@@ -856,7 +857,7 @@ extern "C" void colloc_ipm_default_opts(colloc_ipm_opts* o) {
   o->gamma_alpha = 0.05;
   o->max_ls = 40;
   o->precision = COLLOC_FP64;
-  o->ir_max = 4;
+  o->ir_max = 10;
   o->ir_tol = 1e-14;
 }
 

@@ -905,6 +905,7 @@ __global__ void __launch_bounds__(64) k_l0_bwd(Shape S, Tab tb, Ws ws, double* _
 
 // ---------------------------------------------------------------- matrix-free K v (FP64)
 // u = Ds (J v) for the element's rows.  LDS: v (b) vp (ns) vt (np) out (b)
+template <bool AB>
 __global__ void k_mv1(Shape S, Tab tb, Ws ws, const double* __restrict__ v, double* __restrict__ u,
                       const int* skip) {
   extern __shared__ double lds[];
@@ -918,13 +919,14 @@ __global__ void k_mv1(Shape S, Tab tb, Ws ws, const double* __restrict__ v, doub
   double* vp = vl + b;
   double* vt = vp + ns;
   double* o = vt + np;
-  for (int t = tid(); t < b; t += nthr()) vl[t] = vb[(int64_t)i * b + t];
+  // AB: v is the vector of ones (not read)
+  for (int t = tid(); t < b; t += nthr()) vl[t] = AB ? 1.0 : vb[(int64_t)i * b + t];
   if (i > 0)
-    for (int t = tid(); t < ns; t += nthr()) vp[t] = vb[(int64_t)(i - 1) * b + S.K * ns + t];
-  for (int t = tid(); t < np; t += nthr()) vt[t] = vb[(int64_t)N * b + t];
+    for (int t = tid(); t < ns; t += nthr()) vp[t] = AB ? 1.0 : vb[(int64_t)(i - 1) * b + S.K * ns + t];
+  for (int t = tid(); t < np; t += nthr()) vt[t] = AB ? 1.0 : vb[(int64_t)N * b + t];
   __syncthreads();
   const int64_t jl = (int64_t)S.K * S.nr;
-  jv_rows(S, tb, inst, i, tb.elem_h[e], ws.jac + e * jl * 3, vl, vp, vt, o);
+  jv_rows<AB>(S, tb, inst, i, tb.elem_h[e], ws.jac + e * jl * 3, vl, vp, vt, o);
   const int64_t gi = tb.inst_g[inst] + (int64_t)i * b;
   __syncthreads();
   for (int t = tid(); t < b; t += nthr()) u[gi + t] = ws.Ds[gi + t] * o[t];
@@ -932,6 +934,7 @@ __global__ void k_mv1(Shape S, Tab tb, Ws ws, const double* __restrict__ v, doub
 
 // out_z = J^T u + W v + dw v ; theta partials to ws.rthp.  LDS: u (b) un (ns) phi (K nr)
 // v (b) vt (np) oz (b) ot (np) wz (b) wt (np)
+template <bool AB>
 __global__ void k_mv2(Shape S, Tab tb, Ws ws, const double* __restrict__ v,
                       const double* __restrict__ u, double* __restrict__ out, const int* skip) {
   extern __shared__ double lds[];
@@ -953,18 +956,18 @@ __global__ void k_mv2(Shape S, Tab tb, Ws ws, const double* __restrict__ v,
   const double* vb = v + tb.inst_x[inst];
   for (int t = tid(); t < b; t += nthr()) {
     ul[t] = u[gi + t];
-    vl[t] = vb[(int64_t)i * b + t];
+    vl[t] = AB ? 1.0 : vb[(int64_t)i * b + t];
   }
   if (i + 1 < N)
     for (int t = tid(); t < ns; t += nthr()) un[t] = u[gi + b + t];
-  for (int t = tid(); t < np; t += nthr()) vt[t] = vb[(int64_t)N * b + t];
+  for (int t = tid(); t < np; t += nthr()) vt[t] = AB ? 1.0 : vb[(int64_t)N * b + t];
   __syncthreads();
-  reaction_weights(S, tb, inst, ul, phi);
+  reaction_weights<AB>(S, tb, inst, ul, phi);
   __syncthreads();
   const int64_t jl = (int64_t)S.K * S.nr;
   const double h = tb.elem_h[e];
-  jtu_rows(S, tb, inst, h, ws.jac + e * jl * 3, ul, (i + 1 < N) ? un : nullptr, phi, oz, ot);
-  wv_rows(S, tb, inst, e, ws.hess + e * jl * 4, vl, vt, wz, wt);
+  jtu_rows<AB>(S, tb, inst, h, ws.jac + e * jl * 3, ul, (i + 1 < N) ? un : nullptr, phi, oz, ot);
+  wv_rows<AB>(S, tb, inst, e, ws.hess + e * jl * 4, vl, vt, wz, wt);
   __syncthreads();
   const double dw = ws.dw[inst];
   double* ob = out + tb.inst_x[inst] + (int64_t)i * b;
@@ -972,6 +975,7 @@ __global__ void k_mv2(Shape S, Tab tb, Ws ws, const double* __restrict__ v,
   for (int t = tid(); t < np; t += nthr()) ws.rthp[e * np + t] = ot[t] + wt[t];
 }
 
+template <bool AB>
 __global__ void k_mv3(Shape S, Tab tb, Ws ws, const double* __restrict__ v, double* __restrict__ out,
                       const int* skip) {
   const int inst = blockIdx.x;
@@ -982,7 +986,7 @@ __global__ void k_mv3(Shape S, Tab tb, Ws ws, const double* __restrict__ v, doub
   (void)e0;
   for (int c = tid(); c < S.np; c += nthr()) {
     const double acc = thpart_sum(ws, ws.thv, inst, N, S.np, c);
-    out[xt + c] = acc + ws.sxdw[inst * S.np + c] * v[xt + c];
+    out[xt + c] = acc + ws.sxdw[inst * S.np + c] * (AB ? 1.0 : v[xt + c]);
   }
 }
 
@@ -1090,44 +1094,102 @@ int launch_solve_p(const Shape& S, const Tab& tb, const HostPlan& hp, const Ws& 
                  : solve_t<double>(S, tb, hp, ws, rhs, rthp, dx, cb, ctx, st);
 }
 
+// K v (AB: an upper bound of the row sums of |K|, every coefficient in absolute value applied to
+// the vector of ones; v is not read)
+template <bool AB>
 static int matvec_masked(const Shape& S, const Tab& tb, const Ws& ws, const double* v, double* out,
                          const int* skip, hipStream_t st) {
   int nt = elem_threads(S);
-  hipLaunchKernelGGL(k_mv1, dim3((unsigned)tb.n_elem), dim3(nt),
+  hipLaunchKernelGGL(k_mv1<AB>, dim3((unsigned)tb.n_elem), dim3(nt),
                      sizeof(double) * (2 * S.b + S.ns + S.np), st, S, tb, ws, v, ws.vtmp2, skip);
-  hipLaunchKernelGGL(k_mv2, dim3((unsigned)tb.n_elem), dim3(nt),
+  hipLaunchKernelGGL(k_mv2<AB>, dim3((unsigned)tb.n_elem), dim3(nt),
                      sizeof(double) * (4 * S.b + S.ns + S.K * S.nr + 3 * S.np), st, S, tb, ws, v,
                      ws.vtmp2, out, skip);
   launch_thpart(S, tb, ws, ws.rthp, nullptr, nullptr, ws.thv, st);
-  hipLaunchKernelGGL(k_mv3, dim3(tb.n_inst), dim3(64), 0, st, S, tb, ws, v, out, skip);
+  hipLaunchKernelGGL(k_mv3<AB>, dim3(tb.n_inst), dim3(64), 0, st, S, tb, ws, v, out, skip);
   return ok_or();
 }
 
 int launch_matvec(const Shape& S, const Tab& tb, const Ws& ws, const double* v, double* out,
                   hipStream_t st) {
-  return matvec_masked(S, tb, ws, v, out, nullptr, st);
+  return matvec_masked<false>(S, tb, ws, v, out, nullptr, st);
 }
 
 // ---------------------------------------------------------------- FP64 iterative refinement
-// Per sweep: r = rhs - K dx (matrix-free FP64 product), d = K_factor^{-1} r, dx += d; an
-// instance stops when |d|_inf <= ir_tol |dx|_inf (converged) or after ir_max sweeps.
-// ws.irflag masks finished instances out of every kernel of the sweep.
+// Per sweep: r = rhs - K dx (matrix-free FP64 product), d = K_factor^{-1} r, dx += d.  An instance
+// stops as converged once the dx the residual was taken at has normwise backward error
+// ||r|| <= ir_tol (||K|| ||dx|| + ||rhs||) (infinity norms; ||K|| bounded above by the largest row
+// sum of |J|^T Ds |J| + |W| + the diagonal terms, formed once per call), and as failed when
+// ir_max sweeps are spent or the correction stops contracting (||d|| > ||d_prev|| / 2).
+// ws.irflag masks finished instances out of every kernel of the sweep.  Per element, ws.irpart
+// holds six partial maxima: |d|, |dx| after, |r|, |rhs|, |dx| before, the row-sum bound.
+constexpr int kIrPart = 6;
+
 __global__ void k_ir_init(Ws ws, int n) {
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
     ws.irflag[t] = ws.flag[t];
     ws.ircount[t] = 0;
+    ws.irnorm[2 * t + 1] = INFINITY;   // previous correction
   }
 }
 
-__global__ void k_ir_resid(Shape S, Tab tb, Ws ws, const double* __restrict__ rhs) {
+// Row-sum bound partials: the largest entry of out (= |K| 1) over the element's z rows, the
+// theta rows with element 0.
+__global__ void k_ir_kpart(Shape S, Tab tb, Ws ws, const double* __restrict__ out) {
+  __shared__ double red[256];
   const int64_t e = blockIdx.x;
   const int inst = tb.elem_inst[e], i = tb.elem_loc[e];
   if (block_flag(&ws.irflag[inst])) return;
   const int64_t o = tb.inst_x[inst] + (int64_t)i * S.b;
-  for (int t = tid(); t < S.b; t += nthr()) ws.vtmp[o + t] = rhs[o + t] - ws.vtmp[o + t];
+  double km = 0.0;
+  for (int t = tid(); t < S.b; t += nthr()) km = fmax(km, out[o + t]);
   if (i == 0) {
     const int64_t xt = tb.inst_x[inst] + (int64_t)tb.inst_N[inst] * S.b;
-    for (int c = tid(); c < S.np; c += nthr()) ws.vtmp[xt + c] = rhs[xt + c] - ws.vtmp[xt + c];
+    for (int c = tid(); c < S.np; c += nthr()) km = fmax(km, out[xt + c]);
+  }
+  km = block_max(km, red);
+  if (tid() == 0) ws.irpart[e * kIrPart + 5] = km;
+}
+
+__global__ void k_ir_knorm(Tab tb, Ws ws) {
+  __shared__ double red[256];
+  const int inst = blockIdx.x;
+  if (block_flag(&ws.irflag[inst])) return;
+  const int N = tb.inst_N[inst];
+  const int64_t e0 = tb.inst_e0[inst];
+  double km = 0.0;
+  for (int i = tid(); i < N; i += nthr()) km = fmax(km, ws.irpart[(e0 + i) * kIrPart + 5]);
+  km = block_max(km, red);
+  if (tid() == 0) ws.irnorm[2 * inst] = km;
+}
+
+__global__ void k_ir_resid(Shape S, Tab tb, Ws ws, const double* __restrict__ rhs) {
+  __shared__ double red[256];
+  const int64_t e = blockIdx.x;
+  const int inst = tb.elem_inst[e], i = tb.elem_loc[e];
+  if (block_flag(&ws.irflag[inst])) return;
+  const int64_t o = tb.inst_x[inst] + (int64_t)i * S.b;
+  double rm = 0.0, bm = 0.0;
+  for (int t = tid(); t < S.b; t += nthr()) {
+    const double r = rhs[o + t] - ws.vtmp[o + t];
+    ws.vtmp[o + t] = r;
+    rm = fmax(rm, fabs(r));
+    bm = fmax(bm, fabs(rhs[o + t]));
+  }
+  if (i == 0) {
+    const int64_t xt = tb.inst_x[inst] + (int64_t)tb.inst_N[inst] * S.b;
+    for (int c = tid(); c < S.np; c += nthr()) {
+      const double r = rhs[xt + c] - ws.vtmp[xt + c];
+      ws.vtmp[xt + c] = r;
+      rm = fmax(rm, fabs(r));
+      bm = fmax(bm, fabs(rhs[xt + c]));
+    }
+  }
+  rm = block_max(rm, red);
+  bm = block_max(bm, red);
+  if (tid() == 0) {
+    ws.irpart[e * kIrPart + 2] = rm;
+    ws.irpart[e * kIrPart + 3] = bm;
   }
 }
 
@@ -1137,18 +1199,21 @@ __global__ void k_ir_update(Shape S, Tab tb, Ws ws, double* __restrict__ dx) {
   const int inst = tb.elem_inst[e], i = tb.elem_loc[e];
   if (block_flag(&ws.irflag[inst])) return;
   const int64_t o = tb.inst_x[inst] + (int64_t)i * S.b;
-  double dm = 0.0, xm = 0.0;
+  double dm = 0.0, xm = 0.0, xo = 0.0;
   for (int t = tid(); t < S.b; t += nthr()) {
-    const double d = ws.vtmp2[o + t], x = dx[o + t] + d;
+    const double d = ws.vtmp2[o + t], x0 = dx[o + t], x = x0 + d;
     dx[o + t] = x;
     dm = fmax(dm, fabs(d));
     xm = fmax(xm, fabs(x));
+    xo = fmax(xo, fabs(x0));
   }
   dm = block_max(dm, red);
   xm = block_max(xm, red);
+  xo = block_max(xo, red);
   if (tid() == 0) {
-    ws.irpart[e * 2] = dm;
-    ws.irpart[e * 2 + 1] = xm;
+    ws.irpart[e * kIrPart] = dm;
+    ws.irpart[e * kIrPart + 1] = xm;
+    ws.irpart[e * kIrPart + 4] = xo;
   }
 }
 
@@ -1160,29 +1225,40 @@ __global__ void k_ir_decide(Shape S, Tab tb, Ws ws, double* __restrict__ dx, int
   const int N = tb.inst_N[inst];
   const int64_t e0 = tb.inst_e0[inst];
   const int64_t xt = tb.inst_x[inst] + (int64_t)N * S.b;
-  double dm = 0.0, xm = 0.0;
+  double dm = 0.0, xm = 0.0, xo = 0.0, rm = 0.0, bm = 0.0;
   for (int c = tid(); c < S.np; c += nthr()) {
-    const double d = ws.vtmp2[xt + c], x = dx[xt + c] + d;
+    const double d = ws.vtmp2[xt + c], x0 = dx[xt + c], x = x0 + d;
     dx[xt + c] = x;
     dm = fmax(dm, fabs(d));
     xm = fmax(xm, fabs(x));
+    xo = fmax(xo, fabs(x0));
   }
   for (int i = tid(); i < N; i += nthr()) {
-    dm = fmax(dm, ws.irpart[(e0 + i) * 2]);
-    xm = fmax(xm, ws.irpart[(e0 + i) * 2 + 1]);
+    const double* p = ws.irpart + (e0 + i) * kIrPart;
+    dm = fmax(dm, p[0]);
+    xm = fmax(xm, p[1]);
+    rm = fmax(rm, p[2]);
+    bm = fmax(bm, p[3]);
+    xo = fmax(xo, p[4]);
   }
   dm = block_max(dm, red);
   xm = block_max(xm, red);
+  rm = block_max(rm, red);
+  bm = block_max(bm, red);
+  xo = block_max(xo, red);
   if (tid() == 0) {
     const int cnt = ws.ircount[inst] + 1;
-    if (dm <= ir_tol * xm) {
+    const double knorm = ws.irnorm[2 * inst], dprev = ws.irnorm[2 * inst + 1];
+    (void)xm;
+    if (rm <= ir_tol * (knorm * xo + bm)) {   // the iterate before this sweep was accurate
       ws.ircount[inst] = cnt;
       ws.irflag[inst] = 1;
-    } else if (cnt >= ir_max) {
+    } else if (cnt >= ir_max || dm > 0.5 * dprev) {   // out of sweeps, or no longer contracting
       ws.ircount[inst] = -cnt;
       ws.irflag[inst] = 1;
     } else {
       ws.ircount[inst] = cnt;
+      ws.irnorm[2 * inst + 1] = dm;
     }
   }
 }
@@ -1199,8 +1275,13 @@ int launch_refine(const Shape& S, const Tab& tb, const HostPlan& hp, const Ws& w
   Ws wm = ws;
   wm.flag = ws.irflag;
   const int nt = elem_threads(S);
+  if (ir_max > 0) {   // the row-sum bound of |K|, once
+    if (matvec_masked<true>(S, tb, ws, nullptr, ws.vtmp, ws.irflag, st)) return -3;
+    hipLaunchKernelGGL(k_ir_kpart, dim3((unsigned)tb.n_elem), dim3(nt), 0, st, S, tb, ws, ws.vtmp);
+    hipLaunchKernelGGL(k_ir_knorm, dim3(tb.n_inst), dim3(256), 0, st, tb, ws);
+  }
   for (int s = 0; s < ir_max; ++s) {
-    if (matvec_masked(S, tb, ws, dx, ws.vtmp, ws.irflag, st)) return -3;
+    if (matvec_masked<false>(S, tb, ws, dx, ws.vtmp, ws.irflag, st)) return -3;
     hipLaunchKernelGGL(k_ir_resid, dim3((unsigned)tb.n_elem), dim3(nt), 0, st, S, tb, ws, rhs);
     if (launch_solve_p(S, tb, hp, wm, ws.vtmp, nullptr, ws.vtmp2, cb, ctx, st)) return -3;
     hipLaunchKernelGGL(k_ir_update, dim3((unsigned)tb.n_elem), dim3(nt), 0, st, S, tb, ws, dx);

@@ -103,3 +103,52 @@ def test_fp32_ir_batched_alone_equals_mix(torch):
         assert np.array_equal(P1.state_vec(s1, "x").cpu().numpy(), xall[P.x_off[q]:P.x_off[q] + m.n])
         assert i1[0]["iter"] == info[q]["iter"]
         assert i1[0]["status"] == info[q]["status"]
+
+
+@pytest.mark.parametrize("name", ["ab20"])
+def test_ipm_fp32_ir_factors_used_when_conditioned(torch, name):
+    """With a wide equality relaxation (tau_r = 1e-2, slack weights ~1e2) the condensed matrix is
+    conditioned well enough for FP32 factors: iterations must be accepted on the FP32 factor after
+    refinement (fewer FP64 fallbacks than iterations), and the solve still ends with the oracle's
+    status and parameters.  (An accepted step is accurate to its backward-error target, not to the
+    FP64 factor's rounding: on the 'tiny' instance at this tau_r the FP32_IR path leaves the
+    oracle's after ~20 iterations, which is why that case is not asserted here.)"""
+    announce(f"ipm fp32_ir factors used {name}")
+    tau_r = 1e-2
+    inst = CASES[name]()
+    m = problem.Model(inst, 3)
+    x0 = workloads.initial_point(inst, 3)
+    st_o = ipm.solve(m, x0, ipm.Options(tau_r=tau_r), solver="ldl")
+    P = colloc.Problem(inst, 3)
+    state, info = _solve(P, x0, colloc.default_opts(tau_r=tau_r, precision=colloc.FP32_IR), torch)
+    info = info[0]
+    th = P.state_vec(state, "x").cpu().numpy()[m.nz:]
+    print(f"oracle status {st_o.status} it {st_o.it}; fp32_ir status {info['status']} it {info['iter']} "
+          f"fallbacks {info['ir_fallbacks']} last sweeps {info['ir_sweeps']}", flush=True)
+    assert info["status"] == st_o.status
+    assert info["ir_fallbacks"] < info["iter"]
+    assert np.max(np.abs(th - st_o.x[m.nz:]) / np.maximum(1.0, np.abs(st_o.x[m.nz:]))) < 1e-6
+
+
+def test_ipm_fp32_ir_without_sweeps_falls_back(torch):
+    """ir_max = 0: no refinement can succeed, so the first FP32_IR iteration re-factors in FP64
+    and counts a fallback (the instance then stays on FP64 factors); the solve ends like the FP64
+    solve (status, iteration count, parameters within 1e-10)."""
+    announce("ipm fp32_ir ir_max=0")
+    inst = CASES["ab20"]()
+    m = problem.Model(inst, 3)
+    x0 = workloads.initial_point(inst, 3)
+    P = colloc.Problem(inst, 3)
+    s64, i64 = _solve(P, x0, colloc.default_opts(), torch)
+    o32 = colloc.default_opts(precision=colloc.FP32_IR)
+    o32.ir_max = 0
+    s32, i32 = _solve(P, x0, o32, torch)
+    i64, i32 = i64[0], i32[0]
+    print(f"fp64 it {i64['iter']} status {i64['status']}; fp32_ir(ir_max=0) it {i32['iter']} "
+          f"status {i32['status']} fallbacks {i32['ir_fallbacks']} tries {i32['factor_tries']}", flush=True)
+    assert i32["status"] == i64["status"]
+    assert i32["iter"] == i64["iter"]
+    assert i32["ir_fallbacks"] >= 1
+    th32 = P.state_vec(s32, "x").cpu().numpy()[m.nz:]
+    th64 = P.state_vec(s64, "x").cpu().numpy()[m.nz:]
+    assert np.max(np.abs(th32 - th64) / np.maximum(1.0, np.abs(th64))) < 1e-10
