@@ -13,6 +13,9 @@ LIB_PATH = os.path.join(HERE, "libcolloc.so")
 
 OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED = 0, -1, -2, -3, -4
 RUNNING, SOLVED, ACCEPTABLE, MAXITER, TIMEOUT, ENOTPD, ENONFINITE, RESTORATION_REQUIRED = range(8)
+STATUS_NAMES = {RUNNING: "running", SOLVED: "solved", ACCEPTABLE: "acceptable", MAXITER: "maxiter",
+                TIMEOUT: "timeout", ENOTPD: "enotpd", ENONFINITE: "enonfinite",
+                RESTORATION_REQUIRED: "restoration_required"}
 FP64, FP32_IR = 0, 1
 PHASES = ("eval", "level0", "cr", "border", "solve", "step", "linesearch", "assembly", "schur")
 MAX_LS = 48
@@ -234,6 +237,7 @@ class Problem:
         if getattr(self, "h", None):
             self.lib.colloc_destroy(self.h)
             self.h = None
+        self.table = self.table_view = None   # the device tables go with the handle
 
     def __del__(self):
         try:

@@ -1,8 +1,11 @@
 """Continuous-batching serving loop for parameter-estimation requests.
 
-Requests (one estimation instance each) arrive over time.  Each is admitted when the device
-memory it needs fits the HBM budget, joins the running batch of its shape class (n_s, n_r,
-n_p, K) at the next interior-point step boundary, and leaves it when its status is final.
+Requests (one estimation instance each) arrive over time and queue for the running batch of
+their shape class (n_s, n_r, n_p, K).  At the next interior-point step boundary a batch is
+rebuilt: finished members leave, and queued requests join as far as the HBM budget allows.  The
+budget covers the true footprint of every batch (tables, state and workspace sized by the
+batch's longest mesh) and the rebuild itself, during which the old and the new batch are both
+alive; a request's memory is released only when the batch that held it is freed.
 Every shape class runs its batch on its own HIP stream, so the steps of different classes
 overlap on the device, and inside a class the instances share every launch.  The interior-point
 state stays device-resident: an instance moves from one batch to the next by copying its
@@ -57,7 +60,19 @@ def shape_class(inst, K):
 
 def request_bytes(inst, K, precision):
     """Device bytes of the request alone (tables, state, workspace), from a host-only handle."""
-    P = colloc.Problem(inst, K, upload=False)
+    return batch_bytes([inst], K, precision)
+
+
+def admit_bytes(insts, K, precision):
+    """Device bytes a batch of these instances needs while it is built: the batch, plus the
+    rebuild's own temporaries (the starting points and 64 KiB for host-visible copies)."""
+    return batch_bytes(insts, K, precision) + 65536 + 8 * sum(
+        int(i["N"]) * (K + 1) * int(i["n_s"]) + int(i["n_p"]) for i in insts)
+
+
+def batch_bytes(insts, K, precision):
+    """Device bytes of a batch of these instances (its padding included), host-only."""
+    P = colloc.Problem(list(insts), K, upload=False)
     try:
         return P.device_bytes(precision)
     finally:
@@ -115,42 +130,62 @@ class ClassBatch:
         info = self.P.info(self.state)
         return bool(np.all((info["status"] != colloc.RUNNING) | (info["phase"] == 0)))
 
-    def rebuild(self, now):
-        """Apply membership changes at a step boundary: finished members leave, admitted
-        requests join with a fresh ipm_init, continuing members keep their state."""
+    def rebuild(self, now, room):
+        """Apply membership changes at a step boundary: finished members leave, queued requests
+        join with a fresh ipm_init (as many as fit), continuing members keep their state.
+        room: device bytes this class may hold while rebuilding (its current batch included).
+        Returns the bytes held at the peak of the rebuild (old and new batch alive)."""
         torch = self.torch
         keep = [r for r in self.members if r.status == colloc.RUNNING]
+        old = self.device_bytes()
         if len(keep) == len(self.members) and not self.incoming:
-            return
+            return old
         # a pending inertia retry reuses the workspace of its evaluation: the batch changes only
         # when every continuing member is between iterations
         if keep and not self._at_boundary():
-            return
-        new = list(self.incoming)
-        self.incoming = []
+            return old
+        K, prec = self.shape[3], self.opts.precision
+
+        def need(rs):
+            return admit_bytes([r.inst for r in rs], K, prec)
+
+        n_new = len(self.incoming)
+        while n_new > 0 and old + need(keep + self.incoming[:n_new]) > room:
+            n_new -= 1
+        if n_new == 0 and len(keep) == len(self.members):
+            return old                     # nothing leaves and nothing fits yet
+        if n_new == 0 and keep and old + need(keep) > room:
+            return old                     # shrinking would overrun the budget now: finished
+                                           # members stay (masked) until it fits or all finish
+        new, self.incoming = self.incoming[:n_new], self.incoming[n_new:]
         members = keep + new
+        for r in new:
+            r.t_admit = now
         with torch.cuda.stream(self.stream):
             if not members:
                 self.P = self.ws = self.state = None
                 self.members = []
-                return
-            K = self.shape[3]
+                return old
             P = colloc.Problem([r.inst for r in members], K)
             if self.tiles:
                 for k, ts in self.tiles.items():
                     P.tile_set(k, ts)
-            ws, st = P.workspace(self.opts.precision), P.state()
-            if new:
-                Pn = colloc.Problem([r.inst for r in new], K)
-                wsn, stn = Pn.workspace(self.opts.precision), Pn.state()
-                x0 = torch.tensor(np.concatenate([workloads.initial_point(r.inst, K) for r in new]),
-                                  dtype=torch.float64, device="cuda")
-                Pn.ipm_init(x0, stn, wsn, self.opts)
-                for j in range(len(new)):
-                    copy_instance(Pn, stn, j, P, st, len(keep) + j)
+            ws, st = P.workspace(prec), P.state()
+            # every slot starts from its initial point; continuing members then take their state
+            x0 = torch.tensor(np.concatenate([workloads.initial_point(r.inst, K) for r in members]),
+                              dtype=torch.float64, device="cuda")
+            P.ipm_init(x0, st, ws, self.opts)
             for q, r in enumerate(keep):
                 copy_instance(self.P, self.state, self.members.index(r), P, st, q)
+            peak = old + need(members)
+            if self.P is not None:
+                self.stream.synchronize()      # copies done before the old batch is freed
+                self.P.close()
             self.P, self.ws, self.state, self.members = P, ws, st, members
+        # the old batch's blocks go back to the device: a cached block reused whole for a smaller
+        # buffer would hold more memory than the batch sizes account for
+        torch.cuda.empty_cache()
+        return peak
 
     def step(self, n):
         if self.P is None:
@@ -159,12 +194,14 @@ class ClassBatch:
             for _ in range(n):
                 self.P.ipm_step(self.state, self.ws, self.opts)
 
-    def poll(self, now):
-        """Record finished members (their results are read back here)."""
+    def poll(self, clock):
+        """Record finished members (their results are read back here; the completion time is
+        taken after the stream has synchronized)."""
         if self.P is None:
             return []
         with self.torch.cuda.stream(self.stream):
             info = self.P.info(self.state)
+            now = clock()
             done = []
             x = None
             for q, r in enumerate(self.members):
@@ -184,67 +221,85 @@ class ClassBatch:
 class ServeResult:
     requests: list
     wall: float
-    peak_bytes: int
+    peak_bytes: int               # largest sum of the live batches' device bytes (rebuilds included)
     steps: int = 0
+    peak_allocator_bytes: int = 0  # the torch allocator's peak over the run (state + workspaces)
     log: list = field(default_factory=list)
 
     def latencies(self):
         return np.array([r.latency for r in self.requests])
 
+    def status_counts(self):
+        out = {}
+        for r in self.requests:
+            out[colloc.STATUS_NAMES.get(r.status, str(r.status))] = out.get(
+                colloc.STATUS_NAMES.get(r.status, str(r.status)), 0) + 1
+        return out
+
     def summary(self):
         lat = self.latencies()
-        return {"requests": len(self.requests), "solves_per_s": len(self.requests) / self.wall,
+        return {"requests": len(self.requests), "finished_per_s": len(self.requests) / self.wall,
                 "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
                 "wall_s": self.wall, "peak_bytes": int(self.peak_bytes),
-                "solved": int(sum(r.status in (colloc.SOLVED, colloc.ACCEPTABLE) for r in self.requests))}
+                "peak_allocator_bytes": int(self.peak_allocator_bytes),
+                "solved": int(sum(r.status in (colloc.SOLVED, colloc.ACCEPTABLE) for r in self.requests)),
+                "status": self.status_counts()}
 
 
 def serve(requests, opts, budget_bytes, steps_per_round=4, max_steps=3000, tiles_for=None,
           clock=time.perf_counter):
     """Run the requests through the continuous-batching loop in real time (arrival times in
-    seconds from the start).  Returns a ServeResult with per-request latency and results."""
+    seconds from the start).  Every batch, and every rebuild with its old and new batch alive at
+    once, stays within budget_bytes of device memory.  Returns a ServeResult with per-request
+    latency and results."""
     import torch
 
     for r in requests:
         r.shape = shape_class(r.inst, r.K)
-        r.bytes = request_bytes(r.inst, r.K, opts.precision)
+        r.bytes = admit_bytes([r.inst], r.K, opts.precision)
         if r.bytes > budget_bytes:
             raise ValueError(f"request {r.rid} needs {r.bytes} bytes, above the budget")
     pending = deque(sorted(requests, key=lambda r: r.arrival))
     classes: dict[tuple, ClassBatch] = {}
-    reserved = 0          # bytes of admitted, unfinished requests
     peak = 0
+    import gc
+    gc.collect()                  # earlier handles freed before the baseline is taken
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    base_alloc = torch.cuda.memory_allocated()
+    torch.cuda.reset_peak_memory_stats()
     t0 = clock()
     rounds = 0
     while pending or any(c.busy() for c in classes.values()):
         now = clock() - t0
-        while pending and pending[0].arrival <= now and reserved + pending[0].bytes <= budget_bytes:
+        while pending and pending[0].arrival <= now:   # arrivals queue at their class
             r = pending.popleft()
-            r.t_admit = now
-            reserved += r.bytes
             cb = classes.get(r.shape)
             if cb is None:
                 tiles = tiles_for(r) if tiles_for else None
                 cb = classes[r.shape] = ClassBatch(r.shape, opts, torch, tiles)
             cb.incoming.append(r)
-        if not any(c.busy() for c in classes.values()):
+        if not any(c.members for c in classes.values()) and not any(c.incoming for c in classes.values()):
             if pending:
                 time.sleep(max(0.0, min(0.01, pending[0].arrival - now)))
             continue
         for cb in classes.values():
-            cb.rebuild(now)
-        peak = max(peak, sum(c.device_bytes() for c in classes.values()))
+            # room for this class's rebuild: the budget less what the other classes hold, by the
+            # library's sizes and by the allocator's count, whichever is larger
+            others = sum(c.device_bytes() for c in classes.values() if c is not cb)
+            live = torch.cuda.memory_allocated() - base_alloc - cb.device_bytes()
+            held = cb.rebuild(now, budget_bytes - max(others, live))
+            peak = max(peak, others + held)
         for cb in classes.values():
             cb.step(steps_per_round)
         rounds += 1
-        now = clock() - t0
         for cb in classes.values():
-            for r in cb.poll(now):
-                reserved -= r.bytes
+            cb.poll(lambda: clock() - t0)
         if rounds * steps_per_round > max_steps * 4:
             raise RuntimeError("serving loop did not drain")
     torch.cuda.synchronize()
-    return ServeResult(list(requests), clock() - t0, peak, rounds * steps_per_round)
+    alloc_peak = torch.cuda.max_memory_allocated() - base_alloc
+    return ServeResult(list(requests), clock() - t0, peak, rounds * steps_per_round, alloc_peak)
 
 
 def solve_alone(inst, opts, K=3, max_steps=3000, tiles=None):
