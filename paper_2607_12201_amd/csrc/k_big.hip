@@ -75,31 +75,6 @@ size_t big_asm_lds(const Shape& S) {
   return sizeof(double) * nd + sizeof(int) * ni;
 }
 
-// F_k[s][u] summed over the column list of u.
-__device__ inline double a_F(const AsmLds& L, int lcf, int k, int s, int u) {
-  double v = 0.0;
-  const double* vf = L.vF + (k - 1) * lcf;
-  for (int o = L.cfp[u]; o < L.cfp[u + 1]; ++o) v += (L.cfs[o] == s) ? vf[o] : 0.0;
-  return v;
-}
-__device__ inline double a_T(const AsmLds& L, int lct, int k, int s, int c) {
-  double v = 0.0;
-  const double* vt = L.vT + (k - 1) * lct;
-  for (int o = L.ctp[c]; o < L.ctp[c + 1]; ++o) v += (L.cts[o] == s) ? vt[o] : 0.0;
-  return v;
-}
-// sum_s d_k[s] X[s][p] Y[s][q] for two column lists
-__device__ inline double a_dot(const int* p1, const int* s1, const double* v1, int u1, const int* p2,
-                               const int* s2, const double* v2, int u2, const double* d) {
-  double acc = 0.0;
-  for (int o1 = p1[u1]; o1 < p1[u1 + 1]; ++o1) {
-    const int s = s1[o1];
-    const double x = v1[o1] * d[s];
-    for (int o2 = p2[u2]; o2 < p2[u2 + 1]; ++o2) acc += (s2[o2] == s) ? x * v2[o2] : 0.0;
-  }
-  return acc;
-}
-
 // Entry (r, c), r >= c, of element i's matrix over [z (b) | theta (np) | P (ns)]: node-0 rows
 // (initial condition / continuity, eq. 2c-2d), the measurement Hessian and dw on z, and for every
 // collocation point k the product of its rows a_jk e_(j,s) - h F_k on node k - h Fth_k on theta,
@@ -139,18 +114,22 @@ __device__ inline double big_entry(const Shape& S, const AsmLds& L, int i, doubl
   if (r < b + np) {
     const int th = r - b;
     if (c < b) {
+      // one pass over theta's column list: its entries for species s at every point (the
+      // -h a_jk Ds_k Fth_k[s][th] terms) and, for j >= 1, (Fth_j^T Ds_j F_j)[th][s]
       const int j = c / ns, s = c - j * ns;
-      double v = 0.0;
-      for (int k = 1; k <= K; ++k) v -= h * L.a[j * 8 + k] * L.D[k * ns + s] * a_T(L, S.lct, k, s, th);
+      double t1 = 0.0, q2 = 0.0;
+      for (int o = L.ctp[th]; o < L.ctp[th + 1]; ++o) {
+        const int so = L.cts[o];
+        if (so == s)
+          for (int k = 1; k <= K; ++k) t1 += L.a[j * 8 + k] * L.D[k * ns + s] * L.vT[(k - 1) * S.lct + o];
+        if (j >= 1) q2 += L.vT[(j - 1) * S.lct + o] * wv[so];
+      }
+      double v = -h * t1;
       if (j >= 1) {
-        const int k = j;
-        const double* vt = L.vT + (k - 1) * S.lct;
-        double q2 = 0.0;   // (Fth^T Ds F)[th][s]
-        for (int o = L.ctp[th]; o < L.ctp[th + 1]; ++o) q2 += vt[o] * wv[L.cts[o]];
         double wt = 0.0;   // reactions with s in a slot and rate parameter th
         for (int o = L.rqp[s]; o < L.rqp[s + 1]; ++o) {
           const int rr = L.rqr[o], sl = L.rqt[o];
-          wt += (L.par[rr] == th) ? L.hv[((k - 1) * nr + rr) * 4 + 1 + sl] : 0.0;
+          wt += (L.par[rr] == th) ? L.hv[((j - 1) * nr + rr) * 4 + 1 + sl] : 0.0;
         }
         v += h * h * q2 + wt;
       }
