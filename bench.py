@@ -68,6 +68,22 @@ def assembly_bytes(ns, np_, K):
     return 8.0 * R * (R + 1) / 2
 
 
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed counter summary
+    (profiles/<kernel>_<workload>_traffic.md, a 'traffic_bytes_per_launch:' line, FETCH_SIZE and
+    WRITE_SIZE each scaled by the same counter's reading for a copy of known size); None without
+    one."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.md")
+    try:
+        with open(path) as f:
+            for line in f:
+                if line.startswith("traffic_bytes_per_launch:"):
+                    return float(line.split(":", 1)[1])
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(name, K, seconds=20.0):
     """The oracle's Newton iteration (natural-order block Cholesky path) timed on the host on a
     bounded sample: the same network on a mesh short enough for ~seconds of CPU work, the rate
@@ -206,23 +222,40 @@ def bench_single(args):
     value = r64["newton"] / r64["dt"]
     E = P.n_elem
     ph = {k: r64["ph_ms"][k] / max(1, r64["ph_n"][k]) for k in r64["ph_ms"]}
+    kernels = {}
     if tiled:
         f_panel, f_schur = element_flops(P.ns, P.np_, K, True)
-        cand = {"level0": ("k_pchol_panel (element interior-column factorization)", "mfma", f_panel * E),
-                "schur": ("k_pchol_syrk (element Schur complement tiles)", "mfma", f_schur * E),
-                "assembly": ("k_big_asm (element matrix assembly)", "hbm",
-                             assembly_bytes(P.ns, P.np_, K) * E)}
-        key = max(cand, key=lambda k: ph.get(k, 0.0))
-        kname, bound, work = cand[key]
+        # per-step launches of the element level: assembly (one launch), the interior-column
+        # factorization (a diagonal and a strip launch per 32-column panel), the trailing update
+        # (one launch); the dominant single launch carries the roofline line
+        cand = {"assembly": ("k_big_asm", "element matrix assembly, one launch per step", "hbm",
+                             assembly_bytes(P.ns, P.np_, K) * E),
+                "schur": ("k_pchol_trail", "element Schur complement (trailing update), one launch per step",
+                          "mfma", f_schur * E),
+                "level0": ("k_pchol_diag + k_pchol_strip", "element interior-column factorization, "
+                           "two launches per 32-column panel", "mfma", f_panel * E)}
+        for key, (kn, desc, bound_k, work_k) in cand.items():
+            ms_k = ph.get(key, 0.0)
+            if ms_k <= 0:
+                continue
+            if bound_k == "hbm":
+                a_k, p_k, u_k = work_k / (ms_k * 1e-3) / 1e9, PEAK_HBM_GBS, "GB/s"
+            else:
+                a_k, p_k, u_k = work_k / (ms_k * 1e-3) / 1e12, PEAK_FP64_TFLOPS, "TFLOP/s"
+            kernels[kn] = {"what": desc, "bound": bound_k, "ms": ms_k, "achieved": a_k, "unit": u_k,
+                           "frac": a_k / p_k}
+        key = "assembly" if ph.get("assembly", 0.0) >= ph.get("schur", 0.0) else "schur"
+        kname, kdesc, bound, work = cand[key]
     else:
         f_panel, f_schur = element_flops(P.ns, P.np_, K, False)
-        key, kname, bound, work = "level0", "k_level0r (fused assembly + element condensation)", "mfma", \
-            (f_panel + f_schur) * E
+        key, kname, kdesc, bound, work = ("level0", "k_level0r", "fused assembly + element condensation",
+                                          "mfma", (f_panel + f_schur) * E)
     ms = ph[key]
     if bound == "hbm":
         achieved, peak, unit = work / (ms * 1e-3) / 1e9, PEAK_HBM_GBS, "GB/s"
     else:
         achieved, peak, unit = work / (ms * 1e-3) / 1e12, PEAK_FP64_TFLOPS, "TFLOP/s"
+    traffic = measured_traffic(kname, name)
     cfg = {"workload": WORKLOADS[name], "factor_path": "tiled" if tiled else "register",
            "newton_steps": r64["newton"], "ipm_step_calls": args.steps, "graph_replay": True,
            "final_status": int(r64["info"]["status"]), "iter_end": int(r64["info"]["iter"]),
@@ -252,9 +285,10 @@ def bench_single(args):
         "dtype": "f64",
         "data": "synthetic",
         "config": cfg,
-        "roofline": {"bound": bound, "kernel": kname, "achieved": achieved, "peak": peak, "unit": unit,
-                     "frac": achieved / peak, "traffic": None, "avg_launch_ms": ms,
-                     ("algorithmic_flops_per_launch" if bound != "hbm" else "algorithmic_bytes_per_launch"): work},
+        "roofline": {"bound": bound, "kernel": f"{kname} ({kdesc})", "achieved": achieved, "peak": peak,
+                     "unit": unit, "frac": achieved / peak, "traffic": traffic, "avg_launch_ms": ms,
+                     ("algorithmic_flops_per_launch" if bound != "hbm" else "algorithmic_bytes_per_launch"): work,
+                     "other_kernels": kernels},
     }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(name, K, args.cpu_seconds)
