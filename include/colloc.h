@@ -66,7 +66,8 @@ enum {
   COLLOC_TIMEOUT = 4,
   COLLOC_ENOTPD = 5,              /* inertia correction exceeded delta_max */
   COLLOC_ENONFINITE = 6,          /* NaN/Inf in the optimality error */
-  COLLOC_RESTORATION_REQUIRED = 7 /* line search reached alpha_min (no restoration phase) */
+  COLLOC_RESTORATION_REQUIRED = 7, /* line search reached alpha_min (no restoration phase) */
+  COLLOC_EFILTER = 8              /* the filter's COLLOC_FILTER_CAP entries were all taken */
 };
 
 /* Factor precision of kkt_factor / ipm_step. */
@@ -113,6 +114,9 @@ typedef struct colloc_ipm_opts {
   int32_t pad_;
   double ir_tol;               /* normwise backward-error target of the refinement (1e-14), see
                                   kkt_solve */
+  double max_wall_s;           /* wall-clock limit per instance in seconds from ipm_init, read
+                                  from the device clock at each iteration's decision; 0 = none
+                                  (default).  Exceeding it ends the instance with COLLOC_TIMEOUT */
 } colloc_ipm_opts;
 
 #define COLLOC_MAX_LS 48
@@ -129,6 +133,7 @@ typedef struct colloc_ipm_info {
   double Emu, s_d, s_c;
   int32_t ir_fallbacks, pad_;  /* FP32_IR: iterations factored in FP64 (after the first
                                 * fallback an instance stays on FP64 factors) */
+  double t_start;              /* device wall clock at ipm_init, seconds */
 } colloc_ipm_info;
 
 /* Sizes and per-instance offsets of a handle (host arrays owned by the handle). */

@@ -12,10 +12,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcolloc.so")
 
 OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED = 0, -1, -2, -3, -4
-RUNNING, SOLVED, ACCEPTABLE, MAXITER, TIMEOUT, ENOTPD, ENONFINITE, RESTORATION_REQUIRED = range(8)
+RUNNING, SOLVED, ACCEPTABLE, MAXITER, TIMEOUT, ENOTPD, ENONFINITE, RESTORATION_REQUIRED, EFILTER = range(9)
 STATUS_NAMES = {RUNNING: "running", SOLVED: "solved", ACCEPTABLE: "acceptable", MAXITER: "maxiter",
                 TIMEOUT: "timeout", ENOTPD: "enotpd", ENONFINITE: "enonfinite",
-                RESTORATION_REQUIRED: "restoration_required"}
+                RESTORATION_REQUIRED: "restoration_required", EFILTER: "efilter"}
 FP64, FP32_IR = 0, 1
 PHASES = ("eval", "level0", "cr", "border", "solve", "step", "linesearch", "assembly", "schur")
 MAX_LS = 48
@@ -47,7 +47,7 @@ class IpmOpts(C.Structure):
         ("gamma_theta", C.c_double), ("gamma_phi", C.c_double), ("s_theta", C.c_double),
         ("s_phi", C.c_double), ("eta_phi", C.c_double), ("delta_sw", C.c_double),
         ("gamma_alpha", C.c_double), ("max_ls", C.c_int32), ("precision", C.c_int32),
-        ("ir_max", C.c_int32), ("pad_", C.c_int32), ("ir_tol", C.c_double),
+        ("ir_max", C.c_int32), ("pad_", C.c_int32), ("ir_tol", C.c_double), ("max_wall_s", C.c_double),
     ]
 
 
@@ -59,6 +59,7 @@ INFO_DTYPE = np.dtype([
     ("inf_du", "<f8"), ("E0", "<f8"), ("theta_cv", "<f8"), ("phi", "<f8"),
     ("theta_max", "<f8"), ("theta_min", "<f8"), ("dphi", "<f8"), ("alpha_min", "<f8"),
     ("Emu", "<f8"), ("s_d", "<f8"), ("s_c", "<f8"), ("ir_fallbacks", "<i4"), ("pad_", "<i4"),
+    ("t_start", "<f8"),
 ])
 
 

@@ -22,6 +22,7 @@ struct Shape {
 
 // Device tables (all pointers into the caller's table buffer).
 struct Tab {
+  double wclk_hz;             // rate of the device wall clock (wall_clock64), ticks per second
   int n_inst;
   int L;                      // cyclic-reduction levels (max over the batch)
   int64_t n_elem;

@@ -535,6 +535,11 @@ extern "C" int colloc_upload(colloc_problem* p, void* table_dev, hipStream_t str
   }
   char* b = (char*)table_dev;
   Tab& t = p->tab;
+  int dev = 0, khz = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+    return COLLOC_EHIP;
+  t.wclk_hz = 1e3 * (double)khz;
   t.n_inst = p->n_inst;
   t.L = p->hp.L;
   t.n_elem = p->n_elem;
@@ -859,6 +864,7 @@ extern "C" void colloc_ipm_default_opts(colloc_ipm_opts* o) {
   o->precision = COLLOC_FP64;
   o->ir_max = 10;
   o->ir_tol = 1e-14;
+  o->max_wall_s = 0.0;
 }
 
 static int check_opts(const colloc_ipm_opts* o) {
@@ -866,6 +872,7 @@ static int check_opts(const colloc_ipm_opts* o) {
   if (!(o->tol > 0 && o->tau_r > 0 && o->mu_init > 0 && o->max_ls >= 1 && o->max_ls <= CL_MAX_LS)) return 0;
   if (o->precision != COLLOC_FP64 && o->precision != COLLOC_FP32_IR) return 0;
   if (o->ir_max < 0 || o->ir_max > 100 || !(o->ir_tol >= 0.0)) return 0;
+  if (!(o->max_wall_s >= 0.0)) return 0;
   return 1;
 }
 

@@ -71,6 +71,7 @@ __global__ void k_init_inst(Shape S, Tab tb, IpmState st, Ws ws, colloc_ipm_opts
     I.theta_max = 1e4 * fmax(1.0, acc);
     I.theta_min = 1e-4 * fmax(1.0, acc);
     I.filter_len = 1;
+    I.t_start = (double)wall_clock64() / tb.wclk_hz;
     st.info[inst] = I;
     st.fth[inst * CL_FILTER_CAP] = I.theta_max;
     st.fph[inst * CL_FILTER_CAP] = -INFINITY;
@@ -270,6 +271,8 @@ __global__ void __launch_bounds__(1024) k_ipm_decide(Shape S, Tab tb, IpmState s
         I.acc_count = (E0 <= o.acceptable_tol) ? I.acc_count + 1 : 0;
         if (I.acc_count >= o.acceptable_iter) stt = COLLOC_ACCEPTABLE;
         else if (I.iter >= o.max_iter) stt = COLLOC_MAXITER;
+        else if (o.max_wall_s > 0.0 && (double)wall_clock64() / tb.wclk_hz - I.t_start > o.max_wall_s)
+          stt = COLLOC_TIMEOUT;
       }
       I.status = stt;
       if (stt == COLLOC_RUNNING) {
@@ -693,7 +696,7 @@ __global__ void k_ipm_select(Shape S, Tab tb, IpmState st, Ws ws, colloc_ipm_opt
       wp[k] = nph;
       ++k;
     } else {
-      I.status = COLLOC_ENONFINITE;  // filter capacity exhausted
+      I.status = COLLOC_EFILTER;  // filter capacity exhausted
     }
     I.filter_len = k;
   }

@@ -183,3 +183,11 @@ def test_null_handle_calls_are_rejected(lib):
     assert lib.colloc_workspace_bytes(None, 0) == 0
     assert lib.kkt_factor(None, None, 0, None, None) == colloc.EINVAL
     assert lib.ipm_step(None, None, None, None, None) == colloc.EINVAL
+
+
+def test_status_codes_and_option_defaults():
+    """The binding's status codes follow the header's enum (a full filter has its own code), and
+    the wall-clock limit defaults to off."""
+    assert (colloc.RUNNING, colloc.SOLVED, colloc.TIMEOUT, colloc.ENONFINITE, colloc.EFILTER) == (0, 1, 4, 6, 8)
+    o = colloc.default_opts()
+    assert o.max_wall_s == 0.0 and o.ir_max == 10 and o.ir_tol == 1e-14
