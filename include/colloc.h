@@ -246,6 +246,20 @@ int kkt_solve(const colloc_problem* p, void* ws_dev, int32_t precision, const do
 int kkt_matvec(const colloc_problem* p, void* ws_dev, const double* v_dev, double* out_dev,
                hipStream_t stream);
 
+/* Collocation-consistent starting states (forward implicit Runge-Kutta sweep at fixed
+ * parameters; the paper's initial state guesses come from a forward solve at the nominal
+ * parameters, numerical-results section, benchmark setup).  For every instance, element by element
+ * in mesh order, the K stage values solve the collocation equations of eq. 2b / eq. 3 at
+ * theta from the element's first node (z0, eq. 2d; then the previous element's last node,
+ * eq. 2c) by Newton's method with the dense K n_s x K n_s Jacobian, factored on chip.
+ * theta_dev [n_inst][n_p] (device): the parameters; x_dev [n_total] (device, written): every
+ * instance's [z | theta], ready for ipm_init.  status_dev [n_inst] (device, written): 0, or
+ * 1 + the first element whose Newton iteration did not converge (its values are the last
+ * iterate).  Allocates nothing.  COLLOC_EUNSUPPORTED when K n_s > 96 (the Newton system must
+ * fit in LDS). */
+int colloc_forward_init(const colloc_problem* p, const double* theta_dev, double* x_dev,
+                        int32_t* status_dev, hipStream_t stream);
+
 /* a6 -- interior-point iteration.  ipm_init pushes theta into its bounds, sets the slacks,
  * multipliers, mu and filter (state buffer of colloc_state_bytes).  ipm_step performs one
  * iteration for every running instance: evaluate, test convergence, update mu, assemble and

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libcolloc.so")
 SOURCES = ["k_level0_x.hip", "k_level0_m.hip", "k_level0_s.hip", "k_level0_t.hip", "k_level0_l.hip",
-           "k_level0_w.hip", "k_level0_u.hip", "k_kkt.hip", "k_ipm.hip", "host.hip", "k_eval.hip", "k_level0.hip", "noalloc.hip", "k_big.hip"]
+           "k_level0_w.hip", "k_level0_u.hip", "k_kkt.hip", "k_ipm.hip", "host.hip", "k_eval.hip", "k_level0.hip", "noalloc.hip", "k_big.hip", "k_init.hip"]
 ARCH = os.environ.get("COLLOC_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

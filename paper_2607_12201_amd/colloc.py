@@ -85,7 +85,7 @@ EXPORTS = [
     "ipm_init", "ipm_step", "colloc_state_layout_get", "colloc_timing_enable",
     "colloc_timing_read", "colloc_tables", "ipm_graph_create", "ipm_graph_launch",
     "ipm_graph_destroy", "colloc_tile_options", "colloc_tile_set", "colloc_tile_get",
-    "colloc_eval_noalloc",
+    "colloc_eval_noalloc", "colloc_forward_init",
 ]
 NOALLOC_MAX_ELEMS = (1 << 19) // 13
 
@@ -119,6 +119,7 @@ def load(path: str = LIB_PATH):
         "colloc_ipm_default_opts": (None, [C.POINTER(IpmOpts)]),
         "ipm_init": (i32, [vp, vp, vp, vp, C.POINTER(IpmOpts), vp]),
         "ipm_step": (i32, [vp, vp, vp, C.POINTER(IpmOpts), vp]),
+        "colloc_forward_init": (i32, [vp, vp, vp, vp, vp]),
         "colloc_state_layout_get": (i32, [vp, C.POINTER(StateLayout)]),
         "colloc_timing_enable": (i32, [vp, i32]),
         "colloc_timing_read": (i32, [vp, _f64p, C.POINTER(i64), i32]),
@@ -312,6 +313,17 @@ class Problem:
         out = self.vec(self.n_total)
         _check(self.lib.kkt_matvec(self.h, _ptr(ws), _ptr(v), _ptr(out), _stream()), "kkt_matvec")
         return out
+
+    # -- starting states ---------------------------------------------------------------------
+    def forward_init(self, theta):
+        """Collocation-consistent x = [z | theta] of every instance at theta ([n_inst, n_p] or
+        the concatenation), and the per-instance Newton status (0 = converged)."""
+        th = self.torch.as_tensor(theta, dtype=self.torch.float64, device=self.device).contiguous().reshape(-1)
+        x = self.torch.empty(self.n_total, dtype=self.torch.float64, device=self.device)
+        stat = self.torch.zeros(self.n_inst, dtype=self.torch.int32, device=self.device)
+        _check(self.lib.colloc_forward_init(self.h, _ptr(th), _ptr(x), _ptr(stat), _stream()),
+               "colloc_forward_init")
+        return x, stat
 
     # -- a6 ------------------------------------------------------------------------------
     def ipm_init(self, x0, state, ws, opts):

@@ -884,6 +884,13 @@ extern "C" int ipm_init(const colloc_problem* p, const double* x0, void* state, 
   return launch_ipm_init(p->S, p->tab, st, w, x0, *opts, stream) ? COLLOC_EHIP : COLLOC_OK;
 }
 
+extern "C" int colloc_forward_init(const colloc_problem* p, const double* theta_dev, double* x_dev,
+                                   int32_t* status_dev, hipStream_t stream) {
+  CHECK(p && p->uploaded && aligned8(theta_dev) && aligned8(x_dev) && status_dev);
+  const int rc = launch_fwd_init(p->S, p->tab, theta_dev, x_dev, status_dev, stream);
+  return rc == -2 ? COLLOC_EUNSUPPORTED : rc ? COLLOC_EHIP : COLLOC_OK;
+}
+
 extern "C" int ipm_step(const colloc_problem* p, void* state, void* ws_dev, const colloc_ipm_opts* opts,
                         hipStream_t stream) {
   CHECK(p && p->uploaded && state && ws_dev && check_opts(opts));

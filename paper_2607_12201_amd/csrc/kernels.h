@@ -77,4 +77,8 @@ size_t big_solve_lds(const Shape& S);
 int big_prepare_attrs(const Shape& S);
 
 
+// collocation-consistent states at fixed parameters (k_init.hip); -2: K ns above the LDS limit
+int launch_fwd_init(const Shape& S, const Tab& tb, const double* theta, double* x, int* status,
+                    hipStream_t st);
+
 }  // namespace cl
