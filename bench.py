@@ -14,6 +14,7 @@ Newton step is timed on a bounded sample for context.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -68,20 +69,38 @@ def assembly_bytes(ns, np_, K):
     return 8.0 * R * (R + 1) / 2
 
 
+ASM_BEGIN = "// ---------------------------------------------------------------- assembly"
+ASM_END = "// ---------------------------------------------------------------- partial Cholesky"
+
+
+def assembly_fingerprint():
+    """sha256 of the assembly kernel's source section in csrc/k_big.hip."""
+    with open(os.path.join(ROOT, "paper_2607_12201_amd", "csrc", "k_big.hip")) as f:
+        src = f.read()
+    sec = src[src.index(ASM_BEGIN):src.index(ASM_END)]
+    return hashlib.sha256(sec.encode()).hexdigest()
+
+
 def measured_traffic(kernel, workload):
     """HBM bytes per launch of `kernel` on `workload` from the committed counter summary
-    (profiles/<kernel>_<workload>_traffic.md, a 'traffic_bytes_per_launch:' line, FETCH_SIZE and
-    WRITE_SIZE each scaled by the same counter's reading for a copy of known size); None without
-    one."""
+    (profiles/<kernel>_<workload>_traffic.md: a 'traffic_bytes_per_launch:' line, FETCH_SIZE and
+    WRITE_SIZE each scaled by the same counter's reading for a copy of known size).  None without
+    one, or when its 'source_sha256:' line no longer matches the kernel's source (the counters
+    were taken on other code)."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.md")
+    val, sha = None, None
     try:
         with open(path) as f:
             for line in f:
                 if line.startswith("traffic_bytes_per_launch:"):
-                    return float(line.split(":", 1)[1])
+                    val = float(line.split(":", 1)[1])
+                elif line.startswith("source_sha256:"):
+                    sha = line.split(":", 1)[1].strip()
     except OSError:
-        pass
-    return None
+        return None
+    if sha is None or sha != assembly_fingerprint():
+        return None
+    return val
 
 
 def cpu_baseline(name, K, seconds=20.0):

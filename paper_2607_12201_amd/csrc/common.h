@@ -15,7 +15,10 @@ struct Shape {
   int ns, nr, np, K, b, mI, R, Rt;
   int lsp, lrq, lpc, mmax;      // longest per-instance lists (species->reactions, reactant
                                 // slots, parameter->reactions) and most measurements per element
-  int lcf, lct;                 // longest per-instance column lists of F and Fth (tiled path)
+  int lnf, lct;                 // most nonzeros of F and longest column lists of Fth per
+                                // instance (tiled path)
+  int lzs, lzt;                 // most sparse-term groups and terms of the z columns per
+                                // instance (tiled path)
   int big;                      // 1: tiled matrix-core factorization (large element blocks)
   double a[CL_KMAX + 1][CL_KMAX + 1];  // a[j][k] = l_j'(tau_k)
 };
@@ -59,11 +62,18 @@ struct Tab {
   const int* st_ptr;          // [L]  step l (1..L-1): separators that are multiples of 2^l
   const int* st_inst;
   const int* st_s;
-  // column lists of the point Jacobians (tiled assembly): F_k[s][u] = sum over the entries o of
-  // column u of [cf_s[o] == s] cf_nu[o] d rho_(cf_r[o]) / d slot cf_t[o]; Fth_k[s][c] likewise
+  // Nonzero pattern of the point Jacobians F_k (tiled assembly).  A pair q is one nonzero
+  // (row s, column u) of F_k: F_k[s][u] = sum over the terms o in [fq_o[q], fq_o[q + 1]) of
+  // cf_nu[o] d rho_(cf_r[o]) / d slot cf_t[o].  Pairs are stored by column (fq_ptr, rows fq_s,
+  // each column's rows distinct) and indexed by row (fr_ptr; fr_q the pair relative to the
+  // instance's first pair, fr_u its column).  Fth_k[s][c] is given by the column lists ct_*
   // with d rho_(ct_r[o]) / d theta.  Absolute offsets per instance.
-  const int* cf_ptr;          // [n_inst][ns + 1]
-  const int* cf_s;
+  const int* fq_ptr;          // [n_inst][ns + 1]
+  const int* fq_s;
+  const int* fq_o;            // [n_pairs + 1]
+  const int* fr_ptr;          // [n_inst][ns + 1]
+  const int* fr_q;
+  const int* fr_u;
   const int* cf_r;
   const int* cf_t;
   const double* cf_nu;
@@ -71,6 +81,16 @@ struct Tab {
   const int* ct_s;
   const int* ct_r;
   const double* ct_nu;
+  // Sparse terms of the z columns (tiled assembly).  Species s's columns have the groups
+  // [zs_ptr[s], zs_ptr[s + 1]); group g reaches row key zs_key[g] (< ns: that species at the
+  // column's node; ns + th: parameter th) and sums the terms [zs_t[g], zs_t[g + 1]) of zt_code:
+  // code >= 0 the ct entry code relative to the instance (-h sum_k a_jk Ds_(k,s) Fth_k[s][th]);
+  // code < 0, x = -1 - code = 4 rr + 2 sl + kind: reaction rr with s in slot sl, its second
+  // derivative in both slots (kind 0) or in slot sl and its parameter (kind 1).
+  const int* zs_ptr;          // [n_inst][ns + 1]  absolute
+  const int* zs_key;
+  const int* zs_t;            // [n_groups + 1]  absolute
+  const int* zt_code;
   int cr_items_max;           // largest level
 };
 

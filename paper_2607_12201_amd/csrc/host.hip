@@ -129,7 +129,7 @@ struct colloc_problem {
   // offsets of each table in the image
   size_t o_N, o_x, o_g, o_e0, o_ei, o_el, o_eh, o_mptr, o_msp, o_mw, o_mys, o_react, o_param,
       o_logk, o_spp, o_spr, o_spnu, o_rxs, o_rxnu, o_z0, o_lo, o_hi, o_crp, o_cri, o_crj, o_stp,
-      o_sti, o_sts, o_rqp, o_rqr, o_rqt, o_pcp, o_pcr, o_cfp, o_cfs, o_cfr, o_cft, o_cfnu, o_ctp,
+      o_sti, o_sts, o_rqp, o_rqr, o_rqt, o_pcp, o_pcr, o_fqp, o_fqs, o_fqo, o_frp, o_frq, o_fru, o_cfr, o_cft, o_cfnu, o_zsp, o_zsk, o_zst, o_ztc, o_ctp,
       o_cts, o_ctr, o_ctnu;
   int cr_items_max;
   Tab tab;
@@ -369,26 +369,46 @@ extern "C" int colloc_create(const colloc_instance_desc* inst, int32_t n_inst, i
     S.lpc = std::max(S.lpc, pcp[(size_t)q * (np + 1) + np] - pcp[(size_t)q * (np + 1)]);
   }
   for (int64_t e = 0; e < eo; ++e) S.mmax = std::max(S.mmax, mptr[e + 1] - mptr[e]);
-  // column lists of F and Fth (tiled assembly): for reactant species u, every (reaction, slot)
-  // with u in the slot and every species s the reaction changes; for parameter c, every reaction
-  // of c and every species it changes
-  std::vector<int> cfp((size_t)n_inst * (ns + 1)), cfs, cfr, cft, ctp((size_t)n_inst * (np + 1)), cts, ctr;
+  // Pattern of F (tiled assembly): the terms of column u are every (reaction, slot) with u in the
+  // slot and every species s the reaction changes; grouped by s (ascending, terms in reaction
+  // order) they form the column's nonzeros (pairs).  Fth: for parameter c, every reaction of c
+  // and every species it changes.
+  std::vector<int> fqp((size_t)n_inst * (ns + 1)), fqs, fqo, frp((size_t)n_inst * (ns + 1)), frq, fru;
+  std::vector<int> cfr, cft, ctp((size_t)n_inst * (np + 1)), cts, ctr, zsp((size_t)n_inst * (ns + 1)), zsk, zst, ztc;
   std::vector<double> cfnu, ctnu;
   for (int q = 0; q < n_inst; ++q) {
     const int* rs = rxs.data() + (size_t)q * nr * 4;
     const double* rn = rxnu.data() + (size_t)q * nr * 4;
+    const int pair0 = (int)fqs.size();
+    std::vector<std::vector<std::pair<int, int>>> rows(ns);   // per row s: (column u, pair)
     for (int u = 0; u < ns; ++u) {
-      cfp[(size_t)q * (ns + 1) + u] = (int)cfs.size();
+      fqp[(size_t)q * (ns + 1) + u] = (int)fqs.size();
+      struct Term { int s, r, t; double nu; };
+      std::vector<Term> terms;
       for (int o = rqp[(size_t)q * (ns + 1) + u]; o < rqp[(size_t)q * (ns + 1) + u + 1]; ++o)
         for (int k = 0; k < 4; ++k)
-          if (rs[rqr[o] * 4 + k] >= 0) {
-            cfs.push_back(rs[rqr[o] * 4 + k]);
-            cfr.push_back(rqr[o]);
-            cft.push_back(rqt[o]);
-            cfnu.push_back(rn[rqr[o] * 4 + k]);
-          }
+          if (rs[rqr[o] * 4 + k] >= 0) terms.push_back({rs[rqr[o] * 4 + k], rqr[o], rqt[o], rn[rqr[o] * 4 + k]});
+      std::stable_sort(terms.begin(), terms.end(), [](const Term& x, const Term& y) { return x.s < y.s; });
+      for (size_t o = 0; o < terms.size(); ++o) {
+        if (o == 0 || terms[o].s != terms[o - 1].s) {
+          rows[terms[o].s].push_back({u, (int)fqs.size() - pair0});
+          fqs.push_back(terms[o].s);
+          fqo.push_back((int)cfr.size());
+        }
+        cfr.push_back(terms[o].r);
+        cft.push_back(terms[o].t);
+        cfnu.push_back(terms[o].nu);
+      }
     }
-    cfp[(size_t)q * (ns + 1) + ns] = (int)cfs.size();
+    fqp[(size_t)q * (ns + 1) + ns] = (int)fqs.size();
+    for (int s = 0; s < ns; ++s) {
+      frp[(size_t)q * (ns + 1) + s] = (int)frq.size();
+      for (const auto& uq : rows[s]) {
+        fru.push_back(uq.first);
+        frq.push_back(uq.second);
+      }
+    }
+    frp[(size_t)q * (ns + 1) + ns] = (int)frq.size();
     for (int c = 0; c < np; ++c) {
       ctp[(size_t)q * (np + 1) + c] = (int)cts.size();
       for (int o = pcp[(size_t)q * (np + 1) + c]; o < pcp[(size_t)q * (np + 1) + c + 1]; ++o)
@@ -400,7 +420,36 @@ extern "C" int colloc_create(const colloc_instance_desc* inst, int32_t n_inst, i
           }
     }
     ctp[(size_t)q * (np + 1) + np] = (int)cts.size();
-    S.lcf = std::max(S.lcf, cfp[(size_t)q * (ns + 1) + ns] - cfp[(size_t)q * (ns + 1)]);
+    // Sparse terms of the z columns of species sp, grouped by the row they reach (key): the theta
+    // rows of row sp of Fth (key ns + th, code = the ct entry), and for every reactant slot of sp
+    // the other reactant's row at the column's node (key = that species, code -1 - (4 rr + 2 sl))
+    // and the row of the reaction's parameter (key ns + th, code -2 - (4 rr + 2 sl)).
+    const int c0 = ctp[(size_t)q * (np + 1)], zs0 = (int)zsk.size(), zt0 = (int)ztc.size();
+    for (int sp = 0; sp < ns; ++sp) {
+      struct Zt { int key, code; };
+      std::vector<Zt> zt;
+      for (int c = 0; c < np; ++c)
+        for (int o = ctp[(size_t)q * (np + 1) + c]; o < ctp[(size_t)q * (np + 1) + c + 1]; ++o)
+          if (cts[o] == sp) zt.push_back({ns + c, o - c0});
+      for (int o = rqp[(size_t)q * (ns + 1) + sp]; o < rqp[(size_t)q * (ns + 1) + sp + 1]; ++o) {
+        const int rr = rqr[o], sl = rqt[o], other = react[((size_t)q * nr + rr) * 2 + 1 - sl];
+        if (other >= 0) zt.push_back({other, -1 - (4 * rr + 2 * sl)});
+        if (param[(size_t)q * nr + rr] >= 0) zt.push_back({ns + param[(size_t)q * nr + rr], -2 - (4 * rr + 2 * sl)});
+      }
+      std::stable_sort(zt.begin(), zt.end(), [](const Zt& x, const Zt& y) { return x.key < y.key; });
+      zsp[(size_t)q * (ns + 1) + sp] = (int)zsk.size();
+      for (size_t i = 0; i < zt.size(); ++i) {
+        if (i == 0 || zt[i].key != zt[i - 1].key) {
+          zsk.push_back(zt[i].key);
+          zst.push_back((int)ztc.size());
+        }
+        ztc.push_back(zt[i].code);
+      }
+    }
+    zsp[(size_t)q * (ns + 1) + ns] = (int)zsk.size();
+    S.lzs = std::max(S.lzs, (int)zsk.size() - zs0);
+    S.lzt = std::max(S.lzt, (int)ztc.size() - zt0);
+    S.lnf = std::max(S.lnf, fqp[(size_t)q * (ns + 1) + ns] - fqp[(size_t)q * (ns + 1)]);
     S.lct = std::max(S.lct, ctp[(size_t)q * (np + 1) + np] - ctp[(size_t)q * (np + 1)]);
   }
   if ((!S.big && level0r_lds_bytes(S) > lds_limit()) || (S.big && big_asm_lds(S) > lds_limit())) {
@@ -475,11 +524,21 @@ extern "C" int colloc_create(const colloc_instance_desc* inst, int32_t n_inst, i
   p->o_stp = im.add(stp.data(), sizeof(int) * stp.size());
   p->o_sti = im.add(sti.data(), sizeof(int) * sti.size());
   p->o_sts = im.add(sts.data(), sizeof(int) * sts.size());
-  p->o_cfp = im.add(cfp.data(), sizeof(int) * cfp.size());
-  p->o_cfs = im.add(cfs.data(), sizeof(int) * cfs.size());
+  fqo.push_back((int)cfr.size());
+  p->o_fqp = im.add(fqp.data(), sizeof(int) * fqp.size());
+  p->o_fqs = im.add(fqs.data(), sizeof(int) * fqs.size());
+  p->o_fqo = im.add(fqo.data(), sizeof(int) * fqo.size());
+  p->o_frp = im.add(frp.data(), sizeof(int) * frp.size());
+  p->o_frq = im.add(frq.data(), sizeof(int) * frq.size());
+  p->o_fru = im.add(fru.data(), sizeof(int) * fru.size());
   p->o_cfr = im.add(cfr.data(), sizeof(int) * cfr.size());
   p->o_cft = im.add(cft.data(), sizeof(int) * cft.size());
   p->o_cfnu = im.add(cfnu.data(), sizeof(double) * cfnu.size());
+  zst.push_back((int)ztc.size());
+  p->o_zsp = im.add(zsp.data(), sizeof(int) * zsp.size());
+  p->o_zsk = im.add(zsk.data(), sizeof(int) * zsk.size());
+  p->o_zst = im.add(zst.data(), sizeof(int) * zst.size());
+  p->o_ztc = im.add(ztc.data(), sizeof(int) * ztc.size());
   p->o_ctp = im.add(ctp.data(), sizeof(int) * ctp.size());
   p->o_cts = im.add(cts.data(), sizeof(int) * cts.size());
   p->o_ctr = im.add(ctr.data(), sizeof(int) * ctr.size());
@@ -576,11 +635,19 @@ extern "C" int colloc_upload(colloc_problem* p, void* table_dev, hipStream_t str
   t.st_ptr = (const int*)(b + p->o_stp);
   t.st_inst = (const int*)(b + p->o_sti);
   t.st_s = (const int*)(b + p->o_sts);
-  t.cf_ptr = (const int*)(b + p->o_cfp);
-  t.cf_s = (const int*)(b + p->o_cfs);
+  t.fq_ptr = (const int*)(b + p->o_fqp);
+  t.fq_s = (const int*)(b + p->o_fqs);
+  t.fq_o = (const int*)(b + p->o_fqo);
+  t.fr_ptr = (const int*)(b + p->o_frp);
+  t.fr_q = (const int*)(b + p->o_frq);
+  t.fr_u = (const int*)(b + p->o_fru);
   t.cf_r = (const int*)(b + p->o_cfr);
   t.cf_t = (const int*)(b + p->o_cft);
   t.cf_nu = (const double*)(b + p->o_cfnu);
+  t.zs_ptr = (const int*)(b + p->o_zsp);
+  t.zs_key = (const int*)(b + p->o_zsk);
+  t.zs_t = (const int*)(b + p->o_zst);
+  t.zt_code = (const int*)(b + p->o_ztc);
   t.ct_ptr = (const int*)(b + p->o_ctp);
   t.ct_s = (const int*)(b + p->o_cts);
   t.ct_r = (const int*)(b + p->o_ctr);

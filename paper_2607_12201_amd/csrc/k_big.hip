@@ -59,100 +59,41 @@ __device__ inline void pitem(const Tab& tb, const PArgs& a, int k, int64_t& mat,
 // LDS layout of k_big_asm (doubles, then ints).
 struct AsmLds {
   double *D;            // (K + 1) x ns row weights Ds of the element (node-major)
-  double *vF, *vT;      // K x lcf, K x lct list values of the F and Fth columns per point
-  double *hv;           // K nr 4 weighted second-derivative values
+  double *vF, *vT;      // K x lnf nonzeros of F (pair order), K x lct list values of Fth
   double *mw;           // element measurements' weights (mmax x (K + 1))
   double *a;            // collocation weights a[j * 8 + k] = l_j'(tau_k)
-  int *cfp, *cfs, *ctp, *cts, *rqp, *rqr, *rqt, *pcp, *pcr, *rea, *par, *msp;
+  const double* hes;    // the element's weighted second-derivative values (global, K nr 4)
+  int *fcp, *fqs, *frp, *frq, *fru, *ctp, *cts, *zsp, *zsk, *zst, *ztc, *pcp, *pcr, *msp;
   int nmeas;
 };
 
+// Per-wave scratch of one column (doubles): wv the dense weights, ext the column's sparse terms
+// by target row (ns entries for the rows of its own node, np for the theta rows), dg the diagonal
+// terms of rows of its own species at every node.
+__host__ __device__ inline int asm_wave_doubles(const Shape& S) { return (S.K + 1) * S.ns + S.ns + S.np + 8; }
+
 size_t big_asm_lds(const Shape& S) {
-  const size_t nd = (size_t)(S.K + 1) * S.ns + (size_t)S.K * (S.lcf + S.lct) + 4 * (size_t)S.K * S.nr +
-                    (size_t)S.mmax * (S.K + 1) + 64 + 16 * (size_t)(S.K + 1) * S.ns;
-  const size_t ni = (S.ns + 1) + (size_t)S.lcf + (S.np + 1) + S.lct + (S.ns + 1) + 2 * (size_t)S.lrq +
-                    (S.np + 1) + S.lpc + 3 * (size_t)S.nr + S.mmax + 8;
+  const size_t nd = (size_t)(S.K + 1) * S.ns + (size_t)S.K * (S.lnf + S.lct) + (size_t)S.mmax * (S.K + 1) + 64 +
+                    16 * (size_t)asm_wave_doubles(S);
+  const size_t ni = 2 * (S.ns + 1) + 3 * (size_t)S.lnf + (S.np + 1) + S.lct + (S.ns + 1) + 2 * (size_t)S.lzs + 1 +
+                    S.lzt + (S.np + 1) + S.lpc + S.mmax + 8;
   return sizeof(double) * nd + sizeof(int) * ni;
 }
 
-// Entry (r, c), r >= c, of element i's matrix over [z (b) | theta (np) | P (ns)]: node-0 rows
-// (initial condition / continuity, eq. 2c-2d), the measurement Hessian and dw on z, and for every
-// collocation point k the product of its rows a_jk e_(j,s) - h F_k on node k - h Fth_k on theta,
-// weighted by Ds, plus the reaction second derivatives (W).  theta-theta entries exclude Sx + dw
-// (added once per instance at the border).  wv holds the column's dense weights (see
-// column_weights), which turn the products F^T Ds F, F^T Ds Fth and Fth^T Ds Fth into one pass
-// over the row's column list.
-__device__ inline double big_entry(const Shape& S, const AsmLds& L, int i, double h, double dw, int r, int c,
-                                   const double* wv) {
-  const int ns = S.ns, np = S.np, b = S.b, K = S.K, nr = S.nr;
-  const double* d0 = L.D;
-  if (r < b) {
-    const int j1 = r / ns, s1 = r - j1 * ns, j2 = c / ns, s2 = c - j2 * ns;
-    double v = (r == c) ? dw : 0.0;
-    if (s1 == s2) {
-      if (j1 == 0 && j2 == 0) v += d0[s1];
-      for (int q = 0; q < L.nmeas; ++q)
-        if (L.msp[q] == s1) v += L.mw[q * (K + 1) + j1] * L.mw[q * (K + 1) + j2];
-      for (int k = 1; k <= K; ++k) v += L.D[k * ns + s1] * L.a[j1 * 8 + k] * L.a[j2 * 8 + k];
-    }
-    if (j2 >= 1) v -= h * L.a[j1 * 8 + j2] * wv[s1];   // wv[s] = Ds_(j2,s) F_j2[s][s2]
-    if (j1 >= 1) v -= h * L.a[j2 * 8 + j1] * L.D[j1 * ns + s2] * wv[ns + (j1 - 1) * ns + s1];   // F_j1[s2][s1]
-    if (j1 == j2 && j1 >= 1) {
-      const int k = j1;
-      const double* vf = L.vF + (k - 1) * S.lcf;
-      double q1 = 0.0;   // (F^T Ds F)[s1][s2] = sum over column s1's entries of F[s][s1] wv[s]
-      for (int o = L.cfp[s1]; o < L.cfp[s1 + 1]; ++o) q1 += vf[o] * wv[L.cfs[o]];
-      double wz = 0.0;   // reactions with s1 in a slot and s2 in the other
-      for (int o = L.rqp[s1]; o < L.rqp[s1 + 1]; ++o) {
-        const int rr = L.rqr[o], sl = L.rqt[o];
-        wz += (L.rea[2 * rr + 1 - sl] == s2) ? L.hv[((k - 1) * nr + rr) * 4] : 0.0;
-      }
-      v += h * h * q1 + wz;
-    }
-    return v;
+// sum of term(o) over o in [b, e) with four independent partial sums, so that the LDS loads of
+// four terms are in flight together
+template <typename F>
+__device__ inline double sum4(int b, int e, F term) {
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int o = b;
+  for (; o + 4 <= e; o += 4) {
+    a0 += term(o);
+    a1 += term(o + 1);
+    a2 += term(o + 2);
+    a3 += term(o + 3);
   }
-  if (r < b + np) {
-    const int th = r - b;
-    if (c < b) {
-      // one pass over theta's column list: its entries for species s at every point (the
-      // -h a_jk Ds_k Fth_k[s][th] terms) and, for j >= 1, (Fth_j^T Ds_j F_j)[th][s]
-      const int j = c / ns, s = c - j * ns;
-      double t1 = 0.0, q2 = 0.0;
-      for (int o = L.ctp[th]; o < L.ctp[th + 1]; ++o) {
-        const int so = L.cts[o];
-        if (so == s)
-          for (int k = 1; k <= K; ++k) t1 += L.a[j * 8 + k] * L.D[k * ns + s] * L.vT[(k - 1) * S.lct + o];
-        if (j >= 1) q2 += L.vT[(j - 1) * S.lct + o] * wv[so];
-      }
-      double v = -h * t1;
-      if (j >= 1) {
-        double wt = 0.0;   // reactions with s in a slot and rate parameter th
-        for (int o = L.rqp[s]; o < L.rqp[s + 1]; ++o) {
-          const int rr = L.rqr[o], sl = L.rqt[o];
-          wt += (L.par[rr] == th) ? L.hv[((j - 1) * nr + rr) * 4 + 1 + sl] : 0.0;
-        }
-        v += h * h * q2 + wt;
-      }
-      return v;
-    }
-    const int th2 = c - b;
-    double v = 0.0;
-    for (int k = 1; k <= K; ++k) {
-      const double* vt = L.vT + (k - 1) * S.lct;
-      const double* w = wv + (k - 1) * ns;   // w[s] = Ds_(k,s) Fth_k[s][th2]
-      double q3 = 0.0;
-      for (int o = L.ctp[th]; o < L.ctp[th + 1]; ++o) q3 += vt[o] * w[L.cts[o]];
-      v += h * h * q3;
-      if (th == th2)
-        for (int o = L.pcp[th]; o < L.pcp[th + 1]; ++o) v += L.hv[((k - 1) * nr + L.pcr[o]) * 4 + 3];
-    }
-    return v;
-  }
-  const int p = r - b - np;   // P row: the previous separator, coupled through eq. 2c
-  if (i == 0) return 0.0;
-  if (c < b) return (c == p) ? -d0[p] : 0.0;
-  if (c < b + np) return 0.0;
-  return (c == r) ? d0[p] : 0.0;
+  for (; o < e; ++o) a0 += term(o);
+  return (a0 + a1) + (a2 + a3);
 }
 
 __device__ inline void wave_sync() {
@@ -161,35 +102,62 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Dense weights of column c, built by one wave in its private LDS slice.  For a z column (j, s2):
-// wv[s] = Ds_(j,s) F_j[s][s2] (j >= 1) and wv[ns + (k-1) ns + u] = F_k[s2][u], row s2 of every
-// point's F; for a theta column th, wv[(k-1) ns + s] = Ds_(k,s) Fth_k[s][th] for every point k.
-// A list may name a species more than once, so one lane per vector adds its list in order.
-__device__ inline void column_weights(const Shape& S, const Tab& tb, const AsmLds& L, int inst, const double* jac,
-                                      int c, int lane, double* wv) {
-  const int ns = S.ns, np = S.np, b = S.b, K = S.K, nr = S.nr;
+// Element i's matrix over [z (b) | theta (np) | P (ns)] (eq. 2b-2d through J^T Ds J + W): for
+// every collocation point k the rows a_jk e_(j,s) - h F_k on node k - h Fth_k on theta, weighted
+// by Ds, the node-0 rows (initial condition / continuity), the measurement Hessian and dw on z,
+// and the reaction second derivatives.  A column is assembled by one wave: its dense weights
+// first (column_prep), then one lane per row, so the products F^T Ds F, Fth^T Ds F and
+// Fth^T Ds Fth take one pass over the row's column list.
+//
+// Dense weights of z column (j, s2): wv[s] = Ds_(j,s) F_j[s][s2] (j >= 1) and
+// wv[ns + (k-1) ns + u] = F_k[s2][u], scattered from the nonzeros of F (distinct targets, one
+// lane each); ext the sums of its term groups by target row (one lane per group, terms in
+// order); dg[j1] the diagonal part of row (j1, s2): sum_k Ds_(k,s2) a_(j1,k) a_(j,k), the
+// measurements of s2 in the element, and Ds of node 0 on the (0, 0) block.  Theta column th:
+// wv[(k-1) ns + s] = Ds_(k,s) Fth_k[s][th] (a parameter's list may name a species more than once,
+// so one lane per point adds its list in order).
+__device__ inline void column_prep(const Shape& S, const AsmLds& L, double h, int c, int lane, double* wv) {
+  const int ns = S.ns, np = S.np, nr = S.nr, b = S.b, K = S.K;
+  double* ext = wv + (K + 1) * ns;
+  double* dg = ext + ns + np;
   if (c < b) {
     const int j = c / ns, s2 = c - j * ns;
-    for (int s = lane; s < (K + 1) * ns; s += 64) wv[s] = 0.0;
+    for (int s = lane; s < (K + 1) * ns + ns + np; s += 64) wv[s] = 0.0;
     wave_sync();
-    if (lane == 0 && j >= 1) {
-      const double* vf = L.vF + (j - 1) * S.lcf;
-      for (int o = L.cfp[s2]; o < L.cfp[s2 + 1]; ++o) {
-        const int s = L.cfs[o];
-        wv[s] += L.D[j * ns + s] * vf[o];
+    if (j >= 1) {
+      const double* vf = L.vF + (j - 1) * S.lnf;
+      for (int q = L.fcp[s2] + lane; q < L.fcp[s2 + 1]; q += 64) {
+        const int s = L.fqs[q];
+        wv[s] = L.D[j * ns + s] * vf[q];
       }
-    } else if (lane >= 1 && lane <= K) {   // row s2 of F_k: reactions that change s2, by slot
-      const int k = lane;
-      double* fr = wv + ns + (k - 1) * ns;
-      const int p0 = tb.sp_ptr[inst * (ns + 1) + s2], p1 = tb.sp_ptr[inst * (ns + 1) + s2 + 1];
-      for (int q = p0; q < p1; ++q) {
-        const int r = tb.sp_r[q];
-        const double nu = tb.sp_nu[q];
-        const double* jr = jac + ((k - 1) * nr + r) * 3;
-        const int u0 = L.rea[2 * r], u1 = L.rea[2 * r + 1];
-        if (u0 >= 0) fr[u0] += nu * jr[0];
-        if (u1 >= 0) fr[u1] += nu * jr[1];
+    }
+    const int r0 = L.frp[s2], nrow = L.frp[s2 + 1] - r0;
+    for (int t = lane; t < K * nrow; t += 64) {   // row s2 of F_k
+      const int k = t / nrow, o = r0 + t - k * nrow;
+      wv[ns + k * ns + L.fru[o]] = L.vF[k * S.lnf + L.frq[o]];
+    }
+    for (int g = L.zsp[s2] + lane; g < L.zsp[s2 + 1]; g += 64) {
+      double v = 0.0;
+      for (int t = L.zst[g]; t < L.zst[g + 1]; ++t) {
+        const int code = L.ztc[t];
+        if (code >= 0) {
+          double q = 0.0;
+          for (int k = 1; k <= K; ++k) q += L.a[j * 8 + k] * L.D[k * ns + s2] * L.vT[(k - 1) * S.lct + code];
+          v += -h * q;
+        } else if (j >= 1) {
+          const int x = -1 - code, rr = x >> 2, sl = (x >> 1) & 1;
+          v += L.hes[((j - 1) * nr + rr) * 4 + ((x & 1) ? 1 + sl : 0)];
+        }
       }
+      ext[L.zsk[g]] = v;
+    }
+    if (lane <= K) {
+      const int j1 = lane;
+      double v = (j1 == 0 && j == 0) ? L.D[s2] : 0.0;
+      for (int q = 0; q < L.nmeas; ++q)
+        if (L.msp[q] == s2) v += L.mw[q * (K + 1) + j1] * L.mw[q * (K + 1) + j];
+      for (int k = 1; k <= K; ++k) v += L.D[k * ns + s2] * L.a[j1 * 8 + k] * L.a[j * 8 + k];
+      dg[j1] = v;
     }
   } else if (c < b + np) {
     const int th = c - b;
@@ -207,9 +175,26 @@ __device__ inline void column_weights(const Shape& S, const Tab& tb, const AsmLd
   wave_sync();
 }
 
+// Theta-theta entry (th, th2), th2 <= th: h^2 sum_k (Fth_k^T Ds_k Fth_k)[th][th2] plus, on the
+// diagonal, the reactions' second derivatives in their parameter; wv holds the weights of column
+// th, so the entry is one pass over th2's column list (the block is symmetric).  Sx + dw are added
+// once per instance at the border.
+__device__ inline double theta_entry(const Shape& S, const AsmLds& L, double h, int th, int th2, const double* wv) {
+  const int ns = S.ns, K = S.K, nr = S.nr;
+  double v = 0.0;
+  for (int k = 1; k <= K; ++k) {
+    const double* vt = L.vT + (k - 1) * S.lct;
+    const double* w = wv + (k - 1) * ns;
+    v += h * h * sum4(L.ctp[th2], L.ctp[th2 + 1], [&](int o) { return vt[o] * w[L.cts[o]]; });
+    if (th == th2)
+      for (int o = L.pcp[th]; o < L.pcp[th + 1]; ++o) v += L.hes[((k - 1) * nr + L.pcr[o]) * 4 + 3];
+  }
+  return v;
+}
+
 // One workgroup of 16 waves per element; each wave assembles whole columns (column c by wave
 // c mod 16), its lanes on consecutive rows (coalesced stores), after building the column's dense
-// weights.
+// weights.  The theta-theta block goes to an FP64 side array, row-major, written by rows.
 template <typename T>
 __global__ void __launch_bounds__(1024) k_big_asm(Shape S, Tab tb, Ws ws) {
   extern __shared__ double lds[];
@@ -219,62 +204,71 @@ __global__ void __launch_bounds__(1024) k_big_asm(Shape S, Tab tb, Ws ws) {
   const int ns = S.ns, np = S.np, nr = S.nr, K = S.K, b = S.b, R = S.R;
   const BigGeom G = big_geom(S);
   const double h = tb.elem_h[e], dw = ws.dw[inst];
+  const int WD = asm_wave_doubles(S);
   AsmLds L;
   L.D = lds;
   L.vF = L.D + (K + 1) * ns;
-  L.vT = L.vF + K * S.lcf;
-  L.hv = L.vT + K * S.lct;
-  L.mw = L.hv + 4 * K * nr;
+  L.vT = L.vF + K * S.lnf;
+  L.mw = L.vT + K * S.lct;
   L.a = L.mw + S.mmax * (K + 1);
-  double* wscr = L.a + 64;   // 16 wave slices of (K + 1) ns doubles
-  int* ip = (int*)(wscr + 16 * (K + 1) * ns);
-  L.cfp = ip; ip += ns + 1;
-  L.cfs = ip; ip += S.lcf;
+  double* wscr = L.a + 64;   // 16 wave slices of WD doubles
+  int* ip = (int*)(wscr + 16 * WD);
+  L.fcp = ip; ip += ns + 1;
+  L.fqs = ip; ip += S.lnf;
+  L.frp = ip; ip += ns + 1;
+  L.frq = ip; ip += S.lnf;
+  L.fru = ip; ip += S.lnf;
   L.ctp = ip; ip += np + 1;
   L.cts = ip; ip += S.lct;
-  L.rqp = ip; ip += ns + 1;
-  L.rqr = ip; ip += S.lrq;
-  L.rqt = ip; ip += S.lrq;
+  L.zsp = ip; ip += ns + 1;
+  L.zsk = ip; ip += S.lzs;
+  L.zst = ip; ip += S.lzs + 1;
+  L.ztc = ip; ip += S.lzt;
   L.pcp = ip; ip += np + 1;
   L.pcr = ip; ip += S.lpc;
-  L.rea = ip; ip += 2 * nr;
-  L.par = ip; ip += nr;
   L.msp = ip;
   // instance tables (relative list offsets), element values
-  const int cf0 = tb.cf_ptr[inst * (ns + 1)], ct0 = tb.ct_ptr[inst * (np + 1)];
-  const int rq0 = tb.rq_ptr[inst * (ns + 1)], pc0 = tb.pc_ptr[inst * (np + 1)];
-  const int ncf = tb.cf_ptr[inst * (ns + 1) + ns] - cf0, nct = tb.ct_ptr[inst * (np + 1) + np] - ct0;
-  const int nrq = tb.rq_ptr[inst * (ns + 1) + ns] - rq0, npc = tb.pc_ptr[inst * (np + 1) + np] - pc0;
+  const int fq0 = tb.fq_ptr[inst * (ns + 1)], fr0 = tb.fr_ptr[inst * (ns + 1)], ct0 = tb.ct_ptr[inst * (np + 1)];
+  const int zs0 = tb.zs_ptr[inst * (ns + 1)], pc0 = tb.pc_ptr[inst * (np + 1)];
+  const int nfq = tb.fq_ptr[inst * (ns + 1) + ns] - fq0, nct = tb.ct_ptr[inst * (np + 1) + np] - ct0;
+  const int nzs = tb.zs_ptr[inst * (ns + 1) + ns] - zs0, zt0 = tb.zs_t[zs0];
+  const int nzt = tb.zs_t[zs0 + nzs] - zt0, npc = tb.pc_ptr[inst * (np + 1) + np] - pc0;
   const int m0 = tb.elem_mptr[e], nm = tb.elem_mptr[e + 1] - m0;
   const int64_t gi = tb.inst_g[inst] + (int64_t)i * b;
   const int64_t jl = (int64_t)K * nr;
   const double* jac = ws.jac + e * jl * 3;
-  const double* hes = ws.hess + e * jl * 4;
+  L.hes = ws.hess + e * jl * 4;
   for (int t = tid(); t <= ns; t += nthr()) {
-    L.cfp[t] = tb.cf_ptr[inst * (ns + 1) + t] - cf0;
-    L.rqp[t] = tb.rq_ptr[inst * (ns + 1) + t] - rq0;
+    L.fcp[t] = tb.fq_ptr[inst * (ns + 1) + t] - fq0;
+    L.frp[t] = tb.fr_ptr[inst * (ns + 1) + t] - fr0;
+    L.zsp[t] = tb.zs_ptr[inst * (ns + 1) + t] - zs0;
   }
   for (int t = tid(); t <= np; t += nthr()) {
     L.ctp[t] = tb.ct_ptr[inst * (np + 1) + t] - ct0;
     L.pcp[t] = tb.pc_ptr[inst * (np + 1) + t] - pc0;
   }
-  for (int t = tid(); t < ncf; t += nthr()) L.cfs[t] = tb.cf_s[cf0 + t];
-  for (int t = tid(); t < nct; t += nthr()) L.cts[t] = tb.ct_s[ct0 + t];
-  for (int t = tid(); t < nrq; t += nthr()) {
-    L.rqr[t] = tb.rq_r[rq0 + t];
-    L.rqt[t] = tb.rq_t[rq0 + t];
+  for (int t = tid(); t < nfq; t += nthr()) {
+    L.fqs[t] = tb.fq_s[fq0 + t];
+    L.frq[t] = tb.fr_q[fr0 + t];
+    L.fru[t] = tb.fr_u[fr0 + t];
   }
+  for (int t = tid(); t < nct; t += nthr()) L.cts[t] = tb.ct_s[ct0 + t];
+  for (int t = tid(); t <= nzs; t += nthr()) {
+    if (t < nzs) L.zsk[t] = tb.zs_key[zs0 + t];
+    L.zst[t] = tb.zs_t[zs0 + t] - zt0;
+  }
+  for (int t = tid(); t < nzt; t += nthr()) L.ztc[t] = tb.zt_code[zt0 + t];
   for (int t = tid(); t < npc; t += nthr()) L.pcr[t] = tb.pc_r[pc0 + t];
-  for (int t = tid(); t < 2 * nr; t += nthr()) L.rea[t] = tb.react[inst * nr * 2 + t];
-  for (int t = tid(); t < nr; t += nthr()) L.par[t] = tb.param[inst * nr + t];
   for (int t = tid(); t < nm; t += nthr()) L.msp[t] = tb.meas_sp[m0 + t];
   for (int t = tid(); t < nm * (K + 1); t += nthr()) L.mw[t] = tb.meas_w[(int64_t)m0 * (K + 1) + t];
   for (int t = tid(); t < b; t += nthr()) L.D[t] = ws.Ds[gi + t];
   for (int t = tid(); t < 64; t += nthr()) L.a[t] = ((t >> 3) <= K && (t & 7) <= K) ? S.a[t >> 3][t & 7] : 0.0;
-  for (int t = tid(); t < 4 * jl; t += nthr()) L.hv[t] = hes[t];
-  for (int t = tid(); t < K * ncf; t += nthr()) {
-    const int k = t / ncf, o = t - k * ncf;
-    L.vF[k * S.lcf + o] = tb.cf_nu[cf0 + o] * jac[(k * nr + tb.cf_r[cf0 + o]) * 3 + tb.cf_t[cf0 + o]];
+  for (int t = tid(); t < K * nfq; t += nthr()) {   // nonzeros of F_k, each summed in term order
+    const int k = t / nfq, q = t - k * nfq;
+    double v = 0.0;
+    for (int o = tb.fq_o[fq0 + q]; o < tb.fq_o[fq0 + q + 1]; ++o)
+      v += tb.cf_nu[o] * jac[(k * nr + tb.cf_r[o]) * 3 + tb.cf_t[o]];
+    L.vF[k * S.lnf + q] = v;
   }
   for (int t = tid(); t < K * nct; t += nthr()) {
     const int k = t / nct, o = t - k * nct;
@@ -285,14 +279,50 @@ __global__ void __launch_bounds__(1024) k_big_asm(Shape S, Tab tb, Ws ws) {
   T* A = (T*)ws.ebuf + e * (int64_t)G.Rp * G.Rp;
   double* ath = ws.ath + e * (int64_t)np * np;
   const int wid = tid() >> 6, lane = tid() & 63;
-  double* wv = wscr + wid * (K + 1) * ns;
+  double* wv = wscr + wid * WD;
+  const double* ext = wv + (K + 1) * ns;
+  const double* dg = ext + ns + np;
+  const double* d0 = L.D;
   for (int c = wid; c < R; c += 16) {
-    column_weights(S, tb, L, inst, jac, c, lane, wv);
-    for (int r = c + lane; r < R; r += 64) {
-      const bool tt = r >= b && r < b + np && c >= b;   // theta-theta: FP64 side array
-      const double v = big_entry(S, L, i, h, dw, r, c, wv);
-      if (tt) ath[(r - b) * np + (c - b)] = v;
-      else A[r + (int64_t)c * G.Rp] = (T)v;
+    column_prep(S, L, h, c, lane, wv);
+    T* col = A + (int64_t)c * G.Rp;
+    if (c < b) {
+      const int j2 = c / ns, s2 = c - j2 * ns;
+      int r = c + lane, j1 = r / ns, s1 = r - j1 * ns;
+      for (; r < b; r += 64) {   // z rows (j1, s1)
+        double v = (r == c) ? dw : 0.0;
+        if (s1 == s2) v += dg[j1];
+        if (j2 >= 1) v -= h * L.a[j1 * 8 + j2] * wv[s1];   // wv[s] = Ds_(j2,s) F_j2[s][s2]
+        if (j1 >= 1) v -= h * L.a[j2 * 8 + j1] * L.D[j1 * ns + s2] * wv[ns + (j1 - 1) * ns + s1];   // F_j1[s2][s1]
+        if (j1 == j2 && j1 >= 1) {
+          // (F^T Ds F)[s1][s2] = sum over column s1's nonzeros of F[s][s1] wv[s]
+          const double* vf = L.vF + (j1 - 1) * S.lnf;
+          v += h * h * sum4(L.fcp[s1], L.fcp[s1 + 1], [&](int q) { return vf[q] * wv[L.fqs[q]]; }) + ext[s1];
+        }
+        col[r] = (T)v;
+        s1 += 64;
+        while (s1 >= ns) {
+          s1 -= ns;
+          ++j1;
+        }
+      }
+      const double* vt = L.vT + (j2 >= 1 ? j2 - 1 : 0) * S.lct;
+      for (int th = lane; th < np; th += 64) {   // theta rows: for j2 >= 1 (Fth_j^T Ds_j F_j)[th][s2]
+        double v = ext[ns + th];
+        if (j2 >= 1) v += h * h * sum4(L.ctp[th], L.ctp[th + 1], [&](int o) { return vt[o] * wv[L.cts[o]]; });
+        col[b + th] = (T)v;
+      }
+      for (int p = lane; p < ns; p += 64)   // P rows: the previous separator through eq. 2c
+        col[b + np + p] = (T)((i != 0 && c == p) ? -d0[p] : 0.0);
+    } else if (c < b + np) {
+      // theta column th: row th of the theta-theta block (th2 <= th, consecutive lanes on
+      // consecutive entries), zeros in the P rows
+      const int th = c - b;
+      for (int t2 = lane; t2 <= th; t2 += 64) ath[th * np + t2] = theta_entry(S, L, h, th, t2, wv);
+      for (int p = lane; p < ns; p += 64) col[b + np + p] = (T)0;
+    } else {
+      const int pc = c - b - np;
+      for (int r = c + lane; r < R; r += 64) col[r] = (T)((i != 0 && r == c) ? d0[pc] : 0.0);
     }
     wave_sync();
   }
