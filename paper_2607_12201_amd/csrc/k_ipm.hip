@@ -476,7 +476,7 @@ __global__ void k_ipm_steplen(Shape S, Tab tb, IpmState st, Ws ws, colloc_ipm_op
 // Trial evaluations: thread t of the workgroup evaluates candidate alpha_max 2^-t on the
 // element's rows (constraint violation, objective, slack barrier logs).  LDS: z,dz (b each),
 // zp,dzp (ns), th,dth (np), kap? (recomputed per thread from theta trial: np exps per thread)
-__global__ void __launch_bounds__(256) k_ipm_trial(Shape S, Tab tb, IpmState st, Ws ws,
+__global__ void __launch_bounds__(1024) k_ipm_trial(Shape S, Tab tb, IpmState st, Ws ws,
                                                    colloc_ipm_opts o) {
   extern __shared__ double lds[];
   const int64_t e = blockIdx.x;
@@ -761,8 +761,12 @@ size_t ipm_eval_lds(const Shape& S, int nt) {
   return sizeof(double) * (5 * S.b + 2 * S.ns + S.np * 2 + S.nr + 4 * S.K * S.nr + nt);
 }
 
+// Threads of the line-search trial kernel: large elements (whose candidate table fills most of
+// a compute unit's LDS) take 1024, so that one workgroup still keeps 16 waves in flight.
+int ipm_trial_threads(const Shape& S) { return S.b >= 128 ? 1024 : 256; }
+
 size_t ipm_trial_lds(const Shape& S, int max_ls) {
-  return sizeof(double) * (4 * (size_t)S.b + 2 * S.ns + 2 * S.np + (size_t)max_ls * S.nr + 3 * 256);
+  return sizeof(double) * (4 * (size_t)S.b + 2 * S.ns + 2 * S.np + (size_t)max_ls * S.nr + 3 * (size_t)ipm_trial_threads(S));
 }
 
 // Dynamic LDS above 64 KiB (large networks) is declared for the evaluation and trial kernels.
@@ -862,7 +866,7 @@ int launch_ipm_step(const Shape& S, const Tab& tb, const HostPlan& hp, const Ipm
   hipLaunchKernelGGL(k_ipm_steplen, dim3(tb.n_inst), dim3(256), 0, s, S, tb, st, ws, o);
   if (cb) cb(ctx, COLLOC_PH_STEP, 0, s);
   if (cb) cb(ctx, COLLOC_PH_LINESEARCH, 1, s);
-  hipLaunchKernelGGL(k_ipm_trial, dim3(ne), dim3(256), ipm_trial_lds(S, o.max_ls), s, S, tb, st, ws, o);
+  hipLaunchKernelGGL(k_ipm_trial, dim3(ne), dim3(ipm_trial_threads(S)), ipm_trial_lds(S, o.max_ls), s, S, tb, st, ws, o);
   hipLaunchKernelGGL(k_ipm_select, dim3(tb.n_inst), dim3(256), 0, s, S, tb, st, ws, o);
   hipLaunchKernelGGL(k_ipm_update, dim3(ne), dim3(nt), 0, s, S, tb, st, ws, o);
   if (cb) cb(ctx, COLLOC_PH_LINESEARCH, 0, s);
