@@ -69,24 +69,18 @@ def assembly_bytes(ns, np_, K):
     return 8.0 * R * (R + 1) / 2
 
 
-ASM_BEGIN = "// ---------------------------------------------------------------- assembly"
-ASM_END = "// ---------------------------------------------------------------- partial Cholesky"
-
-
-def assembly_fingerprint():
-    """sha256 of the assembly kernel's source section in csrc/k_big.hip."""
-    with open(os.path.join(ROOT, "paper_2607_12201_amd", "csrc", "k_big.hip")) as f:
-        src = f.read()
-    sec = src[src.index(ASM_BEGIN):src.index(ASM_END)]
-    return hashlib.sha256(sec.encode()).hexdigest()
+def kernel_source_fingerprint():
+    """sha256 of csrc/k_big.hip, the source of the tiled path's kernels."""
+    with open(os.path.join(ROOT, "paper_2607_12201_amd", "csrc", "k_big.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
 
 
 def measured_traffic(kernel, workload):
     """HBM bytes per launch of `kernel` on `workload` from the committed counter summary
     (profiles/<kernel>_<workload>_traffic.md: a 'traffic_bytes_per_launch:' line, FETCH_SIZE and
     WRITE_SIZE each scaled by the same counter's reading for a copy of known size).  None without
-    one, or when its 'source_sha256:' line no longer matches the kernel's source (the counters
-    were taken on other code)."""
+    one, or when its 'source_sha256:' line no longer matches the kernels' source file (the
+    counters were taken on other code)."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.md")
     val, sha = None, None
     try:
@@ -98,7 +92,7 @@ def measured_traffic(kernel, workload):
                     sha = line.split(":", 1)[1].strip()
     except OSError:
         return None
-    if sha is None or sha != assembly_fingerprint():
+    if sha is None or sha != kernel_source_fingerprint():
         return None
     return val
 
