@@ -66,15 +66,34 @@ def request_bytes(inst, K, precision):
 def admit_bytes(insts, K, precision):
     """Device bytes a batch of these instances needs while it is built: the batch, plus the
     rebuild's own temporaries (the starting points and 64 KiB for host-visible copies)."""
-    return batch_bytes(insts, K, precision) + 65536 + 8 * sum(
-        int(i["N"]) * (K + 1) * int(i["n_s"]) + int(i["n_p"]) for i in insts)
+    return batch_bytes(insts, K, precision) + 65536 + alloc_bytes(8 * sum(
+        int(i["N"]) * (K + 1) * int(i["n_s"]) + int(i["n_p"]) for i in insts))
+
+
+# The torch caching allocator rounds a request up to 512 bytes, and hands a request above 1 MiB a
+# cached block whole when less than 1 MiB of it would remain (it splits a large block only when
+# more than 1 MiB is left over), so such a buffer can hold up to 1 MiB more than it asked for.
+LARGE_BLOCK = 1 << 20
+
+
+def alloc_bytes(n):
+    """Device bytes one torch allocation of n bytes can hold at most."""
+    n = (int(n) + 511) // 512 * 512
+    return n + (LARGE_BLOCK if n > LARGE_BLOCK else 0)
+
+
+def held_bytes(P, precision):
+    """Device bytes a batch handle holds at most: its tables, state and workspace, each one
+    allocator block."""
+    return (alloc_bytes(P.table_bytes + 256) + alloc_bytes(P.lib.colloc_state_bytes(P.h)) +
+            alloc_bytes(P.lib.colloc_workspace_bytes(P.h, precision)))
 
 
 def batch_bytes(insts, K, precision):
     """Device bytes of a batch of these instances (its padding included), host-only."""
     P = colloc.Problem(list(insts), K, upload=False)
     try:
-        return P.device_bytes(precision)
+        return held_bytes(P, precision)
     finally:
         P.close()
 
@@ -121,7 +140,7 @@ class ClassBatch:
         return bool(self.members or self.incoming)
 
     def device_bytes(self):
-        return self.P.device_bytes(self.opts.precision) if self.P is not None else 0
+        return held_bytes(self.P, self.opts.precision) if self.P is not None else 0
 
     def _at_boundary(self):
         """Every member is between iterations (no inertia retry pending)."""
@@ -178,12 +197,13 @@ class ClassBatch:
             for q, r in enumerate(keep):
                 copy_instance(self.P, self.state, self.members.index(r), P, st, q)
             peak = old + need(members)
+            self.stream.synchronize()          # init and copies done before x0 and the old batch go
+            del x0
             if self.P is not None:
-                self.stream.synchronize()      # copies done before the old batch is freed
                 self.P.close()
             self.P, self.ws, self.state, self.members = P, ws, st, members
-        # the old batch's blocks go back to the device: a cached block reused whole for a smaller
-        # buffer would hold more memory than the batch sizes account for
+        # the old batch's and the starting points' blocks go back to the device: a cached block
+        # reused whole for a smaller buffer would hold more memory than the batch sizes account for
         torch.cuda.empty_cache()
         return peak
 
