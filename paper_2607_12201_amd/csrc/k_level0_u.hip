@@ -1,68 +1,10 @@
-// Instantiations of the register-resident element and chain kernels for thread grids
-// TS x TS with NB register blocks per side: 20x20/5, 20x20/6, 20x20/7, 20x20/8.
-// Every block index of the register array is a compile-time constant for these NB.
-#include "level0_impl.h"
-#include "chain_impl.h"
+// Register-resident element and chain kernels instantiated for the thread grids (TS x TS / NB
+// register blocks per side) 20x20/5, 20x20/6, 20x20/7, 20x20/8.
+#include "level0_inst.h"
 
 namespace cl {
-void launch_level0_20_5(const Shape& S, const Tab& tb, const Ws& ws, int prec, int fused, hipStream_t st) {
-  if (prec) hipLaunchKernelGGL((k_level0r<float, 20, 5>), dim3((unsigned)tb.n_elem), dim3(400), level0r_lds_bytes(S), st, S, tb, ws, fused);
-  else hipLaunchKernelGGL((k_level0r<double, 20, 5>), dim3((unsigned)tb.n_elem), dim3(400), level0r_lds_bytes(S), st, S, tb, ws, fused);
-}
-int attrs_level0_20_5(size_t bytes) {
-  if (hipFuncSetAttribute((const void*)k_level0r<double, 20, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
-  if (hipFuncSetAttribute((const void*)k_level0r<float, 20, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
-  if (hipFuncSetAttribute((const void*)k_chain<double, 20, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
-  if (hipFuncSetAttribute((const void*)k_chain<float, 20, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
-  return 0;
-}
-void launch_chain_20_5(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level, unsigned grid, size_t lds, hipStream_t st) {
-  if (prec) hipLaunchKernelGGL((k_chain<float, 20, 5>), dim3(grid), dim3(400), lds, st, S, tb, ws, mode, level);
-  else hipLaunchKernelGGL((k_chain<double, 20, 5>), dim3(grid), dim3(400), lds, st, S, tb, ws, mode, level);
-}
-void launch_level0_20_6(const Shape& S, const Tab& tb, const Ws& ws, int prec, int fused, hipStream_t st) {
-  if (prec) hipLaunchKernelGGL((k_level0r<float, 20, 6>), dim3((unsigned)tb.n_elem), dim3(400), level0r_lds_bytes(S), st, S, tb, ws, fused);
-  else hipLaunchKernelGGL((k_level0r<double, 20, 6>), dim3((unsigned)tb.n_elem), dim3(400), level0r_lds_bytes(S), st, S, tb, ws, fused);
-}
-int attrs_level0_20_6(size_t bytes) {
-  if (hipFuncSetAttribute((const void*)k_level0r<double, 20, 6>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
-  if (hipFuncSetAttribute((const void*)k_level0r<float, 20, 6>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
-  if (hipFuncSetAttribute((const void*)k_chain<double, 20, 6>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
-  if (hipFuncSetAttribute((const void*)k_chain<float, 20, 6>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
-  return 0;
-}
-void launch_chain_20_6(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level, unsigned grid, size_t lds, hipStream_t st) {
-  if (prec) hipLaunchKernelGGL((k_chain<float, 20, 6>), dim3(grid), dim3(400), lds, st, S, tb, ws, mode, level);
-  else hipLaunchKernelGGL((k_chain<double, 20, 6>), dim3(grid), dim3(400), lds, st, S, tb, ws, mode, level);
-}
-void launch_level0_20_7(const Shape& S, const Tab& tb, const Ws& ws, int prec, int fused, hipStream_t st) {
-  if (prec) hipLaunchKernelGGL((k_level0r<float, 20, 7>), dim3((unsigned)tb.n_elem), dim3(400), level0r_lds_bytes(S), st, S, tb, ws, fused);
-  else hipLaunchKernelGGL((k_level0r<double, 20, 7>), dim3((unsigned)tb.n_elem), dim3(400), level0r_lds_bytes(S), st, S, tb, ws, fused);
-}
-int attrs_level0_20_7(size_t bytes) {
-  if (hipFuncSetAttribute((const void*)k_level0r<double, 20, 7>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
-  if (hipFuncSetAttribute((const void*)k_level0r<float, 20, 7>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
-  if (hipFuncSetAttribute((const void*)k_chain<double, 20, 7>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
-  if (hipFuncSetAttribute((const void*)k_chain<float, 20, 7>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
-  return 0;
-}
-void launch_chain_20_7(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level, unsigned grid, size_t lds, hipStream_t st) {
-  if (prec) hipLaunchKernelGGL((k_chain<float, 20, 7>), dim3(grid), dim3(400), lds, st, S, tb, ws, mode, level);
-  else hipLaunchKernelGGL((k_chain<double, 20, 7>), dim3(grid), dim3(400), lds, st, S, tb, ws, mode, level);
-}
-void launch_level0_20_8(const Shape& S, const Tab& tb, const Ws& ws, int prec, int fused, hipStream_t st) {
-  if (prec) hipLaunchKernelGGL((k_level0r<float, 20, 8>), dim3((unsigned)tb.n_elem), dim3(400), level0r_lds_bytes(S), st, S, tb, ws, fused);
-  else hipLaunchKernelGGL((k_level0r<double, 20, 8>), dim3((unsigned)tb.n_elem), dim3(400), level0r_lds_bytes(S), st, S, tb, ws, fused);
-}
-int attrs_level0_20_8(size_t bytes) {
-  if (hipFuncSetAttribute((const void*)k_level0r<double, 20, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
-  if (hipFuncSetAttribute((const void*)k_level0r<float, 20, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
-  if (hipFuncSetAttribute((const void*)k_chain<double, 20, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
-  if (hipFuncSetAttribute((const void*)k_chain<float, 20, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
-  return 0;
-}
-void launch_chain_20_8(const Shape& S, const Tab& tb, const Ws& ws, int prec, int mode, int level, unsigned grid, size_t lds, hipStream_t st) {
-  if (prec) hipLaunchKernelGGL((k_chain<float, 20, 8>), dim3(grid), dim3(400), lds, st, S, tb, ws, mode, level);
-  else hipLaunchKernelGGL((k_chain<double, 20, 8>), dim3(grid), dim3(400), lds, st, S, tb, ws, mode, level);
-}
+CL_LEVEL0_INSTANCE(20, 5)
+CL_LEVEL0_INSTANCE(20, 6)
+CL_LEVEL0_INSTANCE(20, 7)
+CL_LEVEL0_INSTANCE(20, 8)
 }  // namespace cl
