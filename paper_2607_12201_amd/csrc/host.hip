@@ -452,7 +452,8 @@ extern "C" int colloc_create(const colloc_instance_desc* inst, int32_t n_inst, i
     S.lnf = std::max(S.lnf, fqp[(size_t)q * (ns + 1) + ns] - fqp[(size_t)q * (ns + 1)]);
     S.lct = std::max(S.lct, ctp[(size_t)q * (np + 1) + np] - ctp[(size_t)q * (np + 1)]);
   }
-  if ((!S.big && level0r_lds_bytes(S) > lds_limit()) || (S.big && big_asm_lds(S) > lds_limit())) {
+  if ((!S.big && level0r_lds_bytes(S) > lds_limit()) || (S.big && big_asm_lds(S) > lds_limit()) ||
+      ipm_trial_lds(S, CL_MAX_LS) > lds_limit()) {   // sizes that depend on the list lengths
     delete p;
     return COLLOC_EUNSUPPORTED;
   }

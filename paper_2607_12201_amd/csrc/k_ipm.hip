@@ -497,6 +497,19 @@ __global__ void __launch_bounds__(1024) k_ipm_trial(Shape S, Tab tb, IpmState st
   double* dsv = sv + b;
   double* kap = dsv + b;              // [nls][nr] rate constants at the trial parameters
   double* part = kap + nls * nr;      // [3][nthr] per-thread partial sums
+  double* spnu = part + 3 * nthr();   // the instance's species -> reaction lists (S.lsp)
+  int* spp = (int*)(spnu + S.lsp);    // [ns + 1] relative offsets
+  int* spr = spp + ns + 1;            // [S.lsp]
+  int* rea = spr + S.lsp;             // [nr][2] reactant slots
+  {
+    const int q0 = tb.sp_ptr[inst * (ns + 1)], nq = tb.sp_ptr[inst * (ns + 1) + ns] - q0;
+    for (int t = tid(); t <= ns; t += nthr()) spp[t] = tb.sp_ptr[inst * (ns + 1) + t] - q0;
+    for (int t = tid(); t < nq; t += nthr()) {
+      spr[t] = tb.sp_r[q0 + t];
+      spnu[t] = tb.sp_nu[q0 + t];
+    }
+    for (int t = tid(); t < 2 * nr; t += nthr()) rea[t] = tb.react[inst * nr * 2 + t];
+  }
   for (int t = tid(); t < b; t += nthr()) {
     z[t] = st.x[xo + (int64_t)i * b + t];
     dz[t] = st.dx[xo + (int64_t)i * b + t];
@@ -540,13 +553,12 @@ __global__ void __launch_bounds__(1024) k_ipm_trial(Shape S, Tab tb, IpmState st
         double acc = 0.0;
         for (int jj = 0; jj <= K; ++jj) acc += S.a[jj][j] * (z[jj * ns + s] + alpha * dz[jj * ns + s]);
         double f = 0.0;
-        const int p0 = tb.sp_ptr[inst * (ns + 1) + s], p1 = tb.sp_ptr[inst * (ns + 1) + s + 1];
-        for (int q = p0; q < p1; ++q) {
-          const int r = tb.sp_r[q];
-          const int q0 = tb.react[(inst * nr + r) * 2], q1 = tb.react[(inst * nr + r) * 2 + 1];
+        for (int q = spp[s]; q < spp[s + 1]; ++q) {
+          const int r = spr[q];
+          const int q0 = rea[2 * r], q1 = rea[2 * r + 1];
           const double u0 = q0 >= 0 ? z[j * ns + q0] + alpha * dz[j * ns + q0] : 1.0;
           const double u1 = q1 >= 0 ? z[j * ns + q1] + alpha * dz[j * ns + q1] : 1.0;
-          f += tb.sp_nu[q] * kc[r] * u0 * u1;
+          f += spnu[q] * kc[r] * u0 * u1;
         }
         gv = acc - h * f;
       }
@@ -766,7 +778,9 @@ size_t ipm_eval_lds(const Shape& S, int nt) {
 int ipm_trial_threads(const Shape& S) { return S.b >= 128 ? 1024 : 256; }
 
 size_t ipm_trial_lds(const Shape& S, int max_ls) {
-  return sizeof(double) * (4 * (size_t)S.b + 2 * S.ns + 2 * S.np + (size_t)max_ls * S.nr + 3 * (size_t)ipm_trial_threads(S));
+  return sizeof(double) * (4 * (size_t)S.b + 2 * S.ns + 2 * S.np + (size_t)max_ls * S.nr +
+                           3 * (size_t)ipm_trial_threads(S) + S.lsp) +
+         sizeof(int) * ((size_t)S.ns + 1 + S.lsp + 2 * (size_t)S.nr);
 }
 
 // Dynamic LDS above 64 KiB (large networks) is declared for the evaluation and trial kernels.
