@@ -346,10 +346,11 @@ __global__ void __launch_bounds__(1024) k_big_asm(Shape S, Tab tb, Ws ws) {
 // L[r0 + 16 rt + li][k], i = Mma<T>::row(lane, v): the (panel, strip) blocks of L L^T transposed.
 // Operands are loaded from memory straight into the product's register layout (32-bit byte
 // offsets from the matrix base, rows clamped to the matrix: rows past its end give products that
-// are never used), the next columns in flight while the current ones are multiplied.
+// are never used), the next columns in flight while the current ones are multiplied.  Bit
+// 4 q + 2 jt + rt of `skip` (the same in every lane) leaves the 16 x 16 product c[q][jt][rt] out.
 template <typename T, int NP>
 __device__ inline void panel_products(const T* A, int ld, int n, int kb, int ke, int pr, int r0, int lane,
-                                      typename Mma<T>::acc (&c)[NP][2][2]) {
+                                      typename Mma<T>::acc (&c)[NP][2][2], uint32_t skip = 0) {
   constexpr int KU = NP == 1 ? 4 : 2;
   const int li = lane & 15, lk = lane >> 4;
   const char* base = (const char*)A;
@@ -380,10 +381,10 @@ __device__ inline void panel_products(const T* A, int ld, int n, int kb, int ke,
     for (int u = 0; u < KU; ++u)
 #pragma unroll
       for (int q = 0; q < NP; ++q) {
-        c[q][0][0] = Mma<T>::mma(p[q][0][u], s0[u], c[q][0][0]);
-        c[q][0][1] = Mma<T>::mma(p[q][0][u], s1[u], c[q][0][1]);
-        c[q][1][0] = Mma<T>::mma(p[q][1][u], s0[u], c[q][1][0]);
-        c[q][1][1] = Mma<T>::mma(p[q][1][u], s1[u], c[q][1][1]);
+        if (!(skip >> (4 * q) & 1)) c[q][0][0] = Mma<T>::mma(p[q][0][u], s0[u], c[q][0][0]);
+        if (!(skip >> (4 * q + 1) & 1)) c[q][0][1] = Mma<T>::mma(p[q][0][u], s1[u], c[q][0][1]);
+        if (!(skip >> (4 * q + 2) & 1)) c[q][1][0] = Mma<T>::mma(p[q][1][u], s0[u], c[q][1][0]);
+        if (!(skip >> (4 * q + 3) & 1)) c[q][1][1] = Mma<T>::mma(p[q][1][u], s1[u], c[q][1][1]);
       }
   };
   const int kfull = kb + (ke > kb ? (ke - kb) / (8 * KU) * (8 * KU) : 0);
@@ -410,10 +411,10 @@ __device__ inline void panel_products(const T* A, int ld, int n, int kb, int ke,
     s1[0] = ok ? *(const T*)(base + (os1 + off)) : (T)0;
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
-      c[q][0][0] = Mma<T>::mma(p[q][0][0], s0[0], c[q][0][0]);
-      c[q][0][1] = Mma<T>::mma(p[q][0][0], s1[0], c[q][0][1]);
-      c[q][1][0] = Mma<T>::mma(p[q][1][0], s0[0], c[q][1][0]);
-      c[q][1][1] = Mma<T>::mma(p[q][1][0], s1[0], c[q][1][1]);
+      if (!(skip >> (4 * q) & 1)) c[q][0][0] = Mma<T>::mma(p[q][0][0], s0[0], c[q][0][0]);
+      if (!(skip >> (4 * q + 1) & 1)) c[q][0][1] = Mma<T>::mma(p[q][0][0], s1[0], c[q][0][1]);
+      if (!(skip >> (4 * q + 2) & 1)) c[q][1][0] = Mma<T>::mma(p[q][1][0], s0[0], c[q][1][0]);
+      if (!(skip >> (4 * q + 3) & 1)) c[q][1][1] = Mma<T>::mma(p[q][1][0], s1[0], c[q][1][1]);
     }
   }
 }
@@ -653,7 +654,21 @@ k_pchol_trail(Tab tb, Ws ws, PArgs a, int groups) {
   for (int q = 0; q < 2; ++q)
 #pragma unroll
     for (int h = 0; h < 2; ++h) c[q][h][0] = c[q][h][1] = acc_t{0, 0, 0, 0};
-  panel_products<T, 2>(A, ld, n, 0, a.m, c0, r0, lane, c);
+  // 16 x 16 products not stored: wholly above the diagonal, past the matrix, or inside the
+  // square left out [skip0, skip1)^2
+  uint32_t skip = 0;
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int jt = 0; jt < 2; ++jt)
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt) {
+        const int cs = c0 + 32 * q + 16 * jt, rs = r0 + 16 * rt;
+        const bool above = cs >= rs + 16, past = rs >= n || cs >= n;
+        const bool inner = rs >= a.skip0 && rs + 16 <= a.skip1 && cs >= a.skip0 && cs + 16 <= a.skip1;
+        if (above || past || inner) skip |= 1u << (4 * q + 2 * jt + rt);
+      }
+  panel_products<T, 2>(A, ld, n, 0, a.m, c0, r0, lane, c, skip);
   lane = opaque_lane();
   const int li = lane & 15;
   // element v of c[q][jt][rt]: column c0 + 32 q + 16 jt + row(lane, v), row r0 + 16 rt + li
