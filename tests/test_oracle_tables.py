@@ -71,6 +71,26 @@ def test_radau_stability_function(zlam):
         assert abs(got - R) <= 1e-14 * max(1.0, abs(R))
 
 
+def _pade_radau(K, z):
+    """(K-1, K) Pade approximant of exp(z), the stability function of the K-stage Radau IIA
+    method, from its closed-form coefficients."""
+    from math import factorial as f
+    num = sum(f(2 * K - 1 - j) * f(K - 1) / (f(2 * K - 1) * f(j) * f(K - 1 - j)) * z ** j for j in range(K))
+    den = sum(f(2 * K - 1 - j) * f(K) / (f(2 * K - 1) * f(j) * f(K - j)) * (-z) ** j for j in range(K + 1))
+    return num / den
+
+
+@pytest.mark.parametrize("zlam", [-0.3, -2.0, -17.0, 0.4, -1.0 + 2.0j])
+def test_radau_stability_function_general_order(zlam):
+    """K = 1 .. 5 against the closed-form Pade coefficients (the K <= 3 forms above are the same
+    approximants written out).  K = 4, 5 carry the rounding of the monomial-basis derivative
+    table (measured up to 6e-14 relative at K = 5), hence 1e-12."""
+    for K in range(1, 6):
+        R = _pade_radau(K, zlam)
+        got = _one_element_amplification(K, "radau", zlam)
+        assert abs(got - R) <= (1e-14 if K <= 3 else 1e-12) * max(1.0, abs(R)), (K, abs(got - R))
+
+
 @pytest.mark.parametrize("zlam", [-0.3, -2.0, 0.4])
 def test_gauss_stability_function(zlam):
     # Gauss collocation with K = 2: diagonal Pade (2, 2)
