@@ -1,0 +1,41 @@
+"""The sequential objective Phi_seq used for solution quality, pinned by the closed-form solution
+of the linear A <-> B system: A(t) = A_inf + (A0 - A_inf) exp(-(k1 + k2) t) with
+A_inf = k2 (A0 + B0) / (k1 + k2), measured in [A]; and the measurement times of a mesh."""
+import numpy as np
+
+from paper_2607_12201_amd import quality, workloads
+
+
+def _closed_form_phi(inst, theta):
+    k1, k2 = np.exp(theta)
+    a0, b0 = inst["z0"]
+    ainf = k2 * (a0 + b0) / (k1 + k2)
+    t = quality.measurement_times(inst)
+    pred = ainf + (a0 - ainf) * np.exp(-(k1 + k2) * t)
+    r = (inst["meas_y"] - pred) / inst["meas_sigma"]
+    return 0.5 * float(r @ r)
+
+
+def test_measurement_times_are_element_ends():
+    inst = workloads.ab_reversible(0)
+    t = quality.measurement_times(inst)
+    ends = np.cumsum(inst["h"])
+    assert np.allclose(t, ends[inst["meas_elem"]], rtol=0, atol=1e-13)
+
+
+def test_sequential_objective_matches_closed_form():
+    inst = workloads.ab_reversible(0)
+    for theta in (inst["theta_true"], inst["theta0"], np.array([1.5, -2.0])):
+        ref = _closed_form_phi(inst, theta)
+        got = quality.sequential_objective(inst, theta)
+        assert abs(got - ref) <= 1e-7 * max(1.0, ref), (got, ref)
+
+
+def test_relative_objective_gap():
+    inst = workloads.ab_reversible(0)
+    th = inst["theta_true"]
+    assert quality.relative_objective_gap(inst, th, th) == 0.0
+    other = th + np.array([0.3, -0.2])
+    g = quality.relative_objective_gap(inst, other, th)
+    ref = abs(_closed_form_phi(inst, other) - _closed_form_phi(inst, th)) / _closed_form_phi(inst, th)
+    assert abs(g - ref) <= 1e-6 * max(1.0, ref)
