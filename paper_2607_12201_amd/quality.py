@@ -80,3 +80,42 @@ def relative_objective_gap(inst, theta, theta_ref):
     """|Phi_seq(theta) - Phi_seq(theta_ref)| / |Phi_seq(theta_ref)|."""
     a, b = sequential_objective(inst, theta), sequential_objective(inst, theta_ref)
     return abs(a - b) / abs(b)
+
+
+def lagrange_values(nodes, t):
+    """Values at t of the Lagrange basis polynomials on `nodes` (product formula)."""
+    nodes = np.asarray(nodes, float)
+    out = np.ones(len(nodes))
+    for j in range(len(nodes)):
+        for m in range(len(nodes)):
+            if m != j:
+                out[j] *= (t - nodes[m]) / (nodes[j] - nodes[m])
+    return out
+
+
+def refine_uniform(inst, K, x):
+    """One step of a mesh-refinement outer loop: every element is halved, the measurements are
+    mapped to the new elements, and the warm start on the new mesh interpolates the solution's
+    collocation polynomials at the new nodes (theta kept).  Returns (new instance, x0)."""
+    from paper_2607_12201_amd import colloc
+
+    tau, _ = colloc.library_tables(K)
+    ns, N, np_ = int(inst["n_s"]), int(inst["N"]), int(inst["n_p"])
+    z = np.asarray(x[: N * (K + 1) * ns], float).reshape(N, K + 1, ns)
+    theta = np.asarray(x[N * (K + 1) * ns:], float)
+    new = dict(inst)
+    h = np.asarray(inst["h"], float)
+    new["h"] = np.repeat(h / 2.0, 2)
+    new["N"] = 2 * N
+    e = np.asarray(inst["meas_elem"], np.int64)
+    t = np.asarray(inst["meas_tau"], float)
+    second = t > 0.5
+    new["meas_elem"] = (2 * e + second).astype(np.int32)
+    new["meas_tau"] = np.where(second, 2.0 * t - 1.0, 2.0 * t)
+    zn = np.empty((2 * N, K + 1, ns))
+    for i in range(N):
+        for half in range(2):
+            for j in range(K + 1):
+                w = lagrange_values(tau, 0.5 * half + 0.5 * tau[j])
+                zn[2 * i + half, j] = w @ z[i]
+    return new, np.concatenate([zn.ravel(), theta])

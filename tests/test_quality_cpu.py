@@ -39,3 +39,24 @@ def test_relative_objective_gap():
     g = quality.relative_objective_gap(inst, other, th)
     ref = abs(_closed_form_phi(inst, other) - _closed_form_phi(inst, th)) / _closed_form_phi(inst, th)
     assert abs(g - ref) <= 1e-6 * max(1.0, ref)
+
+
+def test_refine_uniform_maps_measurements_and_interpolates_polynomials():
+    """Halving the mesh keeps every measurement at its absolute time, and the warm start
+    reproduces states that are polynomials of degree <= K in time exactly."""
+    from paper_2607_12201_amd import colloc
+    inst = workloads.ab_reversible(0)
+    K = 3
+    tau, _ = colloc.library_tables(K)
+    N, ns = inst["N"], inst["n_s"]
+    starts = np.concatenate([[0.0], np.cumsum(inst["h"])[:-1]])
+    t_nodes = starts[:, None] + np.asarray(inst["h"])[:, None] * tau[None, :]
+    poly = lambda t: np.stack([1 + 0.3 * t - 0.05 * t ** 2 + 0.002 * t ** 3, 2 - t ** 3 / 100], axis=-1)
+    x = np.concatenate([poly(t_nodes).ravel(), inst["theta0"]])
+    new, x0 = quality.refine_uniform(inst, K, x)
+    assert new["N"] == 2 * N
+    assert np.allclose(quality.measurement_times(new), quality.measurement_times(inst), rtol=0, atol=1e-12)
+    starts2 = np.concatenate([[0.0], np.cumsum(new["h"])[:-1]])
+    t2 = starts2[:, None] + np.asarray(new["h"])[:, None] * tau[None, :]
+    assert np.allclose(x0[: 2 * N * (K + 1) * ns], poly(t2).ravel(), rtol=0, atol=1e-12)
+    assert np.array_equal(x0[2 * N * (K + 1) * ns:], inst["theta0"])
